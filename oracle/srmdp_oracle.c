@@ -1,0 +1,679 @@
+/*
+ * srmdp_oracle.c -- plain FP64 CPU oracle of the SRMDP backward sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY (see srmdp_oracle.h).  Slow on purpose: no blocking,
+ * no fusion, no reordering beyond what the paper's definitions state.  Each
+ * function names the passage of the paper it follows.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled on them):
+ *  - Euler dynamics (Section 2, Algorithm "Euler dynamics") is read with the
+ *    time index of the current step j, X_{j+1} = X_j + b dt + sigma dW_j.
+ *  - The z-response of Algorithm SRMDP, eq. (PsiM), uses the tail
+ *    g(X_N) + sum_{j=i+1}^{N-1} f_j dt of the same path started at X_i,
+ *    multiplied by dW_i / dt, as in the MDP identity eq. (MDP:intro).
+ *  - z is fitted before y (the y response contains f_i(., z_i)).
+ *  - Truncation T_L (eq. TL) is applied when a fitted function is evaluated;
+ *    stored coefficients are untruncated; +inf disables it.
+ *  - Only the K bounded cells of the domain are sampled; a point outside the
+ *    domain is evaluated with the affine fit of the nearest boundary cell.
+ *  - Cells are half-open [x-, x+) as in assumption (A_Strat).
+ *  - Uniforms are open, u = (2*(r >> 9) + 1) * 2^-24, exact in binary32 and
+ *    binary64, so both precisions of the GPU library see the same number.
+ *  - Random inputs: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *    key (seed mod 2^32, seed >> 32) and counter (block, m, k, i | inst << 16);
+ *    words 0..d-1 of blocks 0.. give the start point, the following blocks give
+ *    the Gaussian increments through Box-Muller (1958) pairs.
+ *  - Least squares by the normal equations with a Cholesky factor of the Gram
+ *    matrix on the cube-centred, scaled basis (1, xi_1..xi_d),
+ *    xi_l = 2 (x_l - c_l) / h_l; same solution as the QR route of Section
+ *    "Explicit solutions to OLS".  A pivot <= 1e-12 * trace(G) is treated as
+ *    singular and the stratum falls back to the empirical mean (LP0).
+ */
+#include "srmdp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- Philox -- */
+
+/* Philox4x32-10 as published by Salmon et al. (SC'11): ten rounds of the
+ * two-multiplier S-box; the key is bumped by the Weyl constants between
+ * rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t mult0 = 0xD2511F53u, mult1 = 0xCD9E8D57u;
+    const uint32_t weyl0 = 0x9E3779B9u, weyl1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += weyl0;
+            k1 += weyl1;
+        }
+        uint64_t p0 = (uint64_t)mult0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)mult1 * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The random stream of one simulation: uniform number n is word n%4 of the
+ * Philox block n/4.  A one-block cache avoids recomputing a block for every
+ * word; it changes nothing in the values. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t m, k, tag;
+    int64_t cached_block;
+    uint32_t words[4];
+} path_stream;
+
+static void stream_init(path_stream *s, uint64_t seed, uint32_t inst, int32_t i, uint32_t k,
+                        uint32_t m)
+{
+    s->key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->m = m;
+    s->k = k;
+    s->tag = ((uint32_t)i & 0xFFFFu) | (inst << 16);
+    s->cached_block = -1;
+}
+
+static uint32_t stream_word(path_stream *s, int64_t n)
+{
+    int64_t blk = n / 4;
+    if (blk != s->cached_block) {
+        uint32_t ctr[4] = {(uint32_t)blk, s->m, s->k, s->tag};
+        orc_philox4x32_10(ctr, s->key, s->words);
+        s->cached_block = blk;
+    }
+    return s->words[n % 4];
+}
+
+/* Open uniform on (0,1): the top 23 bits, made odd, times 2^-24. */
+static double word_to_uniform(uint32_t r)
+{
+    return (2.0 * (double)(r >> 9) + 1.0) * ldexp(1.0, -24);
+}
+
+static double stream_uniform(path_stream *s, int64_t n)
+{
+    return word_to_uniform(stream_word(s, n));
+}
+
+void orc_path_uniforms(uint64_t seed, uint32_t inst, int32_t i, uint32_t k, uint32_t m,
+                       int32_t n, double *u)
+{
+    path_stream s;
+    stream_init(&s, seed, inst, i, k, m);
+    for (int32_t a = 0; a < n; ++a) u[a] = stream_uniform(&s, a);
+}
+
+/* Number of Philox blocks used by the start point: ceil(d/4). */
+static int start_blocks(int d) { return (d + 3) / 4; }
+
+/* Standard normal number n of the path: Box-Muller on the uniform pair
+ * p = n/2 that follows the start blocks; even n takes the cosine branch, odd n
+ * the sine branch. */
+static double stream_normal(path_stream *s, int d, int64_t n)
+{
+    const double pi = 3.14159265358979323846;
+    int64_t p = n / 2;
+    int64_t base = 4 * (int64_t)start_blocks(d) + 2 * p;
+    double u1 = stream_uniform(s, base);
+    double u2 = stream_uniform(s, base + 1);
+    double rho = sqrt(-2.0 * log(u1));
+    double theta = 2.0 * pi * u2;
+    return (n % 2 == 0) ? rho * cos(theta) : rho * sin(theta);
+}
+
+/* ------------------------------------------------------------------ grid -- */
+
+typedef struct {
+    int d;
+    int64_t K;
+    double lo[64], hi[64], h[64];
+    int32_t cells[64];
+    int64_t stride[64];
+} grid_t;
+
+static int grid_init(const orc_problem *P, grid_t *G)
+{
+    if (P->d < 1 || P->d > 64) return -1;
+    G->d = P->d;
+    G->K = 1;
+    for (int l = 0; l < P->d; ++l) {
+        if (!(P->lo[l] < P->hi[l]) || P->cells[l] < 1) return -1;
+        G->lo[l] = P->lo[l];
+        G->hi[l] = P->hi[l];
+        G->cells[l] = P->cells[l];
+        G->h[l] = (P->hi[l] - P->lo[l]) / (double)P->cells[l];
+        G->stride[l] = G->K; /* dimension 0 varies fastest */
+        G->K *= P->cells[l];
+    }
+    return 0;
+}
+
+/* Cell of x along dimension l: floor((x - lo) * (C / (hi - lo))), clamped to
+ * the boundary cells (points outside the domain belong to the nearest
+ * boundary cell for evaluation). */
+static int64_t cell_of(const grid_t *G, int l, double x)
+{
+    double scale = (double)G->cells[l] / (G->hi[l] - G->lo[l]);
+    double c = floor((x - G->lo[l]) * scale);
+    if (c < 0.0) c = 0.0;
+    if (c > (double)(G->cells[l] - 1)) c = (double)(G->cells[l] - 1);
+    return (int64_t)c;
+}
+
+static int64_t cube_of(const grid_t *G, const double *x)
+{
+    int64_t k = 0;
+    for (int l = 0; l < G->d; ++l) k += cell_of(G, l, x[l]) * G->stride[l];
+    return k;
+}
+
+static int64_t cube_cell(const grid_t *G, int64_t k, int l)
+{
+    return (k / G->stride[l]) % G->cells[l];
+}
+
+/* Basis of the local spaces of assumption (A_Strat): LP0 = {1}, LP1 =
+ * {1, xi_1..xi_d} with xi the cube-centred and scaled coordinate. */
+static int basis_size(const orc_problem *P) { return P->basis == ORC_LP1 ? P->d + 1 : 1; }
+
+static void basis_eval(const orc_problem *P, const grid_t *G, int64_t k, const double *x,
+                       double *phi)
+{
+    phi[0] = 1.0;
+    if (P->basis != ORC_LP1) return;
+    for (int l = 0; l < G->d; ++l) {
+        double lower = G->lo[l] + (double)cube_cell(G, k, l) * G->h[l];
+        double centre = lower + 0.5 * G->h[l];
+        phi[1 + l] = 2.0 * (x[l] - centre) / G->h[l];
+    }
+}
+
+/* ------------------------------------------------------- problem data -- */
+
+/* Terminal condition g (Section "Model, stratification, and performance
+ * benchmark" for the logistic case; cos of the coordinate sum otherwise). */
+double orc_terminal(const orc_problem *P, const double *x)
+{
+    double s = 0.0;
+    for (int l = 0; l < P->d; ++l) s += x[l];
+    if (P->terminal == ORC_G_LOGISTIC) {
+        double w = exp(P->T + s);
+        return w / (1.0 + w);
+    }
+    return cos(s);
+}
+
+/* Driver f(t, x, y, z): logistic f = (sum z)(y - (2+q)/(2q)) of the paper's
+ * benchmark, or the linear f = -r y + kappa sum z. */
+double orc_driver(const orc_problem *P, double t, const double *x, double y, const double *z)
+{
+    (void)t;
+    (void)x;
+    double sz = 0.0;
+    for (int l = 0; l < P->q; ++l) sz += z[l];
+    if (P->driver == ORC_DRV_LOGISTIC)
+        return sz * (y - (2.0 + P->q) / (2.0 * P->q));
+    return -P->r * y + P->kappa * sz;
+}
+
+static double clampv(double v, double L)
+{
+    if (!(L < INFINITY)) return v;
+    if (v < -L) return -L;
+    if (v > L) return L;
+    return v;
+}
+
+/* ---------------------------------------------------------- the MLP ---- */
+
+int64_t orc_mlp_param_count(int32_t in, int32_t H, int32_t out)
+{
+    return (int64_t)H * in + H + (int64_t)H * H + H + (int64_t)out * H + out;
+}
+
+static double silu(double a) { return a / (1.0 + exp(-a)); }
+static double silu_grad(double a)
+{
+    double s = 1.0 / (1.0 + exp(-a));
+    return s * (1.0 + a * (1.0 - s));
+}
+
+/* One sample through in -> H -> H -> out with SiLU after both hidden layers;
+ * pre-activations are returned in a1, a2 (length H) when non-NULL. */
+static void mlp_one(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
+                    double *y, double *a1, double *a2, double *h1, double *h2)
+{
+    const double *W1 = p, *b1 = W1 + (int64_t)H * in, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H,
+                 *W3 = b2 + H, *b3 = W3 + (int64_t)out * H;
+    for (int a = 0; a < H; ++a) {
+        double s = b1[a];
+        for (int c = 0; c < in; ++c) s += W1[(int64_t)a * in + c] * x[c];
+        a1[a] = s;
+        h1[a] = silu(s);
+    }
+    for (int a = 0; a < H; ++a) {
+        double s = b2[a];
+        for (int c = 0; c < H; ++c) s += W2[(int64_t)a * H + c] * h1[c];
+        a2[a] = s;
+        h2[a] = silu(s);
+    }
+    for (int o = 0; o < out; ++o) {
+        double s = b3[o];
+        for (int c = 0; c < H; ++c) s += W3[(int64_t)o * H + c] * h2[c];
+        y[o] = s;
+    }
+}
+
+void orc_mlp_forward(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
+                     int64_t B, double *y)
+{
+    double *buf = (double *)malloc(sizeof(double) * 4 * (size_t)H);
+    for (int64_t s = 0; s < B; ++s)
+        mlp_one(in, H, out, params, x + s * in, y + s * out, buf, buf + H, buf + 2 * H,
+                buf + 3 * H);
+    free(buf);
+}
+
+/* Gradient of sum_s <dy_s, y_s> with respect to the parameters (dy is the
+ * upstream gradient), by the chain rule written layer by layer. */
+void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
+                      const double *dy, int64_t B, double *grad)
+{
+    const double *W2 = params + (int64_t)H * in + H, *W3 = W2 + (int64_t)H * H + H;
+    double *gW1 = grad, *gb1 = gW1 + (int64_t)H * in, *gW2 = gb1 + H,
+           *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H, *gb3 = gW3 + (int64_t)out * H;
+    memset(grad, 0, sizeof(double) * (size_t)orc_mlp_param_count(in, H, out));
+    double *buf = (double *)malloc(sizeof(double) * (6 * (size_t)H + (size_t)out));
+    double *a1 = buf, *a2 = a1 + H, *h1 = a2 + H, *h2 = h1 + H, *d2 = h2 + H, *d1 = d2 + H,
+           *yy = d1 + H;
+    for (int64_t s = 0; s < B; ++s) {
+        const double *xs = x + s * in, *g = dy + s * out;
+        mlp_one(in, H, out, params, xs, yy, a1, a2, h1, h2);
+        for (int o = 0; o < out; ++o) {
+            gb3[o] += g[o];
+            for (int c = 0; c < H; ++c) gW3[(int64_t)o * H + c] += g[o] * h2[c];
+        }
+        for (int c = 0; c < H; ++c) {
+            double acc = 0.0;
+            for (int o = 0; o < out; ++o) acc += W3[(int64_t)o * H + c] * g[o];
+            d2[c] = acc * silu_grad(a2[c]);
+        }
+        for (int a = 0; a < H; ++a) {
+            gb2[a] += d2[a];
+            for (int c = 0; c < H; ++c) gW2[(int64_t)a * H + c] += d2[a] * h1[c];
+        }
+        for (int c = 0; c < H; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < H; ++a) acc += W2[(int64_t)a * H + c] * d2[a];
+            d1[c] = acc * silu_grad(a1[c]);
+        }
+        for (int a = 0; a < H; ++a) {
+            gb1[a] += d1[a];
+            for (int c = 0; c < in; ++c) gW1[(int64_t)a * in + c] += d1[a] * xs[c];
+        }
+    }
+    free(buf);
+}
+
+/* Control-variate term z_theta(t, x) . dW with the frozen network. */
+static double cv_term(const orc_problem *P, double t, const double *x, const double *dW)
+{
+    double inp[65], out[64], buf[4 * 256];
+    if (P->cv_hidden > 256) return NAN;
+    inp[0] = t;
+    for (int l = 0; l < P->d; ++l) inp[1 + l] = x[l];
+    mlp_one(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, out, buf, buf + P->cv_hidden,
+            buf + 2 * P->cv_hidden, buf + 3 * P->cv_hidden);
+    double s = 0.0;
+    for (int l = 0; l < P->q; ++l) s += out[l] * dW[l];
+    return s;
+}
+
+/* -------------------------------------------------------- validation -- */
+
+static int check_problem(const orc_problem *P, grid_t *G)
+{
+    if (!P || P->d < 1 || P->d > 64 || P->q < 1 || P->q > 64) return -1;
+    if (P->N < 1 || P->N > 65535 || !(P->T > 0.0) || !(P->mu > 0.0)) return -1;
+    if (P->basis != ORC_LP0 && P->basis != ORC_LP1) return -1;
+    if (!P->sigma && P->q != P->d) return -1;
+    if (P->M < basis_size(P)) return -1; /* M >= dim of the local space */
+    if (P->cv_params && (P->cv_hidden < 1 || P->cv_hidden > 256)) return -1;
+    return grid_init(P, G);
+}
+
+int64_t orc_table_elems(const orc_problem *P)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0) return -1;
+    return (int64_t)P->N * G.K * (1 + P->q) * basis_size(P);
+}
+
+static int64_t rec_size(const orc_problem *P) { return (int64_t)(1 + P->q) * basis_size(P); }
+
+/* ---------------------------------------------------- sampling (nu_k) -- */
+
+/* Algorithm "stratify": inverse CDF of the logistic law restricted to
+ * [x-, x+), F(x) = 1 / (1 + exp(-mu x)). */
+static double logistic_cdf(double mu, double x) { return 1.0 / (1.0 + exp(-mu * x)); }
+
+static double stratify_one(double mu, double xm, double xp, double U)
+{
+    double Fm = logistic_cdf(mu, xm), Fp = logistic_cdf(mu, xp);
+    return -(1.0 / mu) * log(1.0 / (Fm + U * (Fp - Fm)) - 1.0);
+}
+
+static void start_point(const orc_problem *P, const grid_t *G, path_stream *s, int64_t k,
+                        double *x)
+{
+    for (int l = 0; l < P->d; ++l) {
+        double xm = G->lo[l] + (double)cube_cell(G, k, l) * G->h[l];
+        double xp = xm + G->h[l];
+        x[l] = stratify_one(P->mu, xm, xp, stream_uniform(s, l));
+    }
+}
+
+int orc_start_point(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, double *x)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0 || (int64_t)k >= G.K) return -1;
+    path_stream s;
+    stream_init(&s, P->seed, P->inst, i, k, m);
+    start_point(P, &G, &s, k, x);
+    return 0;
+}
+
+int orc_path_normals(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, int32_t n,
+                     double *out)
+{
+    if (!P || P->d < 1) return -1;
+    path_stream s;
+    stream_init(&s, P->seed, P->inst, i, k, m);
+    for (int32_t a = 0; a < n; ++a) out[a] = stream_normal(&s, P->d, a);
+    return 0;
+}
+
+/* ----------------------------------------------- fitted-table evaluation -- */
+
+/* y-component (c = 0) or z-component c = 1..q of the fitted function at
+ * row j, evaluated at x (with the cell of x, extended past the domain). */
+static double fitted(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
+                     int c, const double *x)
+{
+    int nb = basis_size(P);
+    double phi[65];
+    int64_t k = cube_of(G, x);
+    basis_eval(P, G, k, x, phi);
+    const double *rec = table + ((int64_t)j * G->K + k) * rec_size(P) + (int64_t)c * nb;
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += rec[b] * phi[b];
+    return clampv(v, c == 0 ? P->clamp_y : P->clamp_z);
+}
+
+/* y_{j}(x) of the sweep: g at j = N, the fitted row otherwise. */
+static double y_at(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
+                   const double *x)
+{
+    if (j == P->N) return orc_terminal(P, x);
+    return fitted(P, G, table, j, 0, x);
+}
+
+static void z_at(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
+                 const double *x, double *z)
+{
+    for (int l = 0; l < P->q; ++l) z[l] = fitted(P, G, table, j, 1 + l, x);
+}
+
+int orc_eval(const orc_problem *P, const double *table, int32_t i, int64_t n, const double *x,
+             double *y, double *z)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0 || i < 0 || i >= P->N) return -1;
+    for (int64_t a = 0; a < n; ++a) {
+        if (y) y[a] = fitted(P, &G, table, i, 0, x + a * P->d);
+        if (z) z_at(P, &G, table, i, x + a * P->d, z + a * P->q);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------- one simulation -- */
+
+/* Simulates one path from X_i (already in x0) to X_N with the Euler scheme and
+ * returns what the regressions of step i need:
+ *   dWi  -- the increment Delta W_i,
+ *   *Sp  -- g(X_N) + sum_{j=i+1}^{N-1} f_j(X_j, y_{j+1}(X_{j+1}), z_j(X_j)) dt
+ *           minus the control-variate terms sum_{j=i+1}^{N-1} z_theta(t_j,X_j).dW_j,
+ *   *y1  -- y_{i+1}(X_{i+1}) (g(X_N) when i+1 = N),
+ *   *cvi -- z_theta(t_i, X_i) . dW_i (zero without control variate).
+ * Eq. (MDP:intro) and eq. (PsiM). */
+static void simulate(const orc_problem *P, const grid_t *G, const double *table, int32_t i,
+                     path_stream *s, const double *x0, double *dWi, double *Sp, double *y1,
+                     double *cvi)
+{
+    const int d = P->d, q = P->q;
+    const double dt = P->T / P->N, sdt = sqrt(dt);
+    double x[64], xn[64], dW[64], z[64];
+    memcpy(x, x0, sizeof(double) * d);
+    double S = 0.0, cv_tail = 0.0;
+    *cvi = 0.0;
+    for (int32_t j = i; j < P->N; ++j) {
+        for (int l = 0; l < q; ++l)
+            dW[l] = sdt * stream_normal(s, d, (int64_t)(j - i) * q + l);
+        for (int l = 0; l < d; ++l) {
+            double drift = P->b ? P->b[l] : 0.0;
+            double diff = 0.0;
+            if (P->sigma)
+                for (int c = 0; c < q; ++c) diff += P->sigma[l * q + c] * dW[c];
+            else
+                diff = dW[l];
+            xn[l] = x[l] + drift * dt + diff;
+        }
+        double ynext = y_at(P, G, table, j + 1, xn);
+        if (j == i) {
+            memcpy(dWi, dW, sizeof(double) * q);
+            *y1 = ynext;
+            if (P->cv_params) *cvi = cv_term(P, j * dt, x, dW);
+        } else {
+            z_at(P, G, table, j, x, z);
+            S += orc_driver(P, j * dt, x, ynext, z) * dt;
+            if (P->cv_params) cv_tail += cv_term(P, j * dt, x, dW);
+        }
+        memcpy(x, xn, sizeof(double) * d);
+    }
+    *Sp = orc_terminal(P, x) + S - cv_tail;
+}
+
+/* ----------------------------------------------------- least squares -- */
+
+/* Cholesky factor of the n x n SPD matrix A (lower, row-major in L).
+ * Returns 0, or 1 if a pivot is <= tol. */
+static int cholesky(int n, const double *A, double *L, double tol)
+{
+    memset(L, 0, sizeof(double) * (size_t)n * n);
+    for (int r = 0; r < n; ++r) {
+        for (int c = 0; c <= r; ++c) {
+            double s = A[r * n + c];
+            for (int t = 0; t < c; ++t) s -= L[r * n + t] * L[c * n + t];
+            if (r == c) {
+                if (!(s > tol)) return 1;
+                L[r * n + r] = sqrt(s);
+            } else {
+                L[r * n + c] = s / L[c * n + c];
+            }
+        }
+    }
+    return 0;
+}
+
+/* Solves L L^T beta = rhs. */
+static void chol_solve(int n, const double *L, const double *rhs, double *beta)
+{
+    double w[65];
+    for (int r = 0; r < n; ++r) {
+        double s = rhs[r];
+        for (int t = 0; t < r; ++t) s -= L[r * n + t] * w[t];
+        w[r] = s / L[r * n + r];
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = w[r];
+        for (int t = r + 1; t < n; ++t) s -= L[t * n + r] * beta[t];
+        beta[r] = s / L[r * n + r];
+    }
+}
+
+/* ----------------------------------------------- one stratum at step i -- */
+
+int orc_cloud(const orc_problem *P, const double *table, int32_t i, uint32_t k, double *Xi,
+              double *dWi, double *Sp, double *y1, double *cvi)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0 || i < 0 || i >= P->N || (int64_t)k >= G.K) return -1;
+    for (int32_t m = 0; m < P->M; ++m) {
+        path_stream s;
+        stream_init(&s, P->seed, P->inst, i, k, (uint32_t)m);
+        start_point(P, &G, &s, k, Xi + (int64_t)m * P->d);
+        simulate(P, &G, table, i, &s, Xi + (int64_t)m * P->d, dWi + (int64_t)m * P->q, Sp + m,
+                 y1 + m, cvi + m);
+    }
+    return 0;
+}
+
+/* Algorithm SRMDP, one stratum k at step i: the cloud C_{i,k}, then the z
+ * regression of S' dW_i / dt, then the y regression of
+ * S_Y = S' + f_i(X_i, y_{i+1}(X_{i+1}), z_i(X_i)) dt, both on the local basis.
+ * Writes row i, stratum k of the table; returns 1 if the Gram was singular. */
+static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int32_t i, int64_t k,
+                       double *work)
+{
+    const int d = P->d, q = P->q, nb = basis_size(P), M = P->M;
+    const double dt = P->T / P->N;
+    double *Xi = work, *dWi = Xi + (int64_t)M * d, *Sp = dWi + (int64_t)M * q, *y1 = Sp + M,
+           *cvi = y1 + M;
+    orc_cloud(P, table, i, (uint32_t)k, Xi, dWi, Sp, y1, cvi);
+
+    double Gm[65 * 65], L[65 * 65], phi[65], rhs[65], beta[65], zfit[64];
+    double *rec = table + ((int64_t)i * G->K + k) * rec_size(P);
+    memset(Gm, 0, sizeof(Gm));
+    double trace = 0.0;
+    for (int m = 0; m < M; ++m) {
+        basis_eval(P, G, k, Xi + (int64_t)m * d, phi);
+        for (int a = 0; a < nb; ++a)
+            for (int c = 0; c < nb; ++c) Gm[a * nb + c] += phi[a] * phi[c];
+    }
+    for (int a = 0; a < nb; ++a) trace += Gm[a * nb + a];
+    int singular = cholesky(nb, Gm, L, 1e-12 * trace);
+
+    /* z first: q scalar regressions sharing the Gram matrix. */
+    for (int l = 0; l < q; ++l) {
+        memset(rhs, 0, sizeof(rhs));
+        for (int m = 0; m < M; ++m) {
+            double resp = Sp[m] * dWi[(int64_t)m * q + l] / dt;
+            basis_eval(P, G, k, Xi + (int64_t)m * d, phi);
+            for (int a = 0; a < nb; ++a) rhs[a] += phi[a] * resp;
+        }
+        if (!singular) {
+            chol_solve(nb, L, rhs, beta);
+        } else {
+            memset(beta, 0, sizeof(beta));
+            beta[0] = rhs[0] / M;
+        }
+        for (int a = 0; a < nb; ++a) rec[(1 + l) * nb + a] = beta[a];
+    }
+    /* y next, with the just-fitted (truncated) z_i at X_i. */
+    memset(rhs, 0, sizeof(rhs));
+    for (int m = 0; m < M; ++m) {
+        const double *x = Xi + (int64_t)m * d;
+        basis_eval(P, G, k, x, phi);
+        for (int l = 0; l < q; ++l) {
+            double v = 0.0;
+            for (int a = 0; a < nb; ++a) v += rec[(1 + l) * nb + a] * phi[a];
+            zfit[l] = clampv(v, P->clamp_z);
+        }
+        double SY = Sp[m] + orc_driver(P, i * dt, x, y1[m], zfit) * dt - cvi[m];
+        for (int a = 0; a < nb; ++a) rhs[a] += phi[a] * SY;
+    }
+    if (!singular) {
+        chol_solve(nb, L, rhs, beta);
+    } else {
+        memset(beta, 0, sizeof(beta));
+        beta[0] = rhs[0] / M;
+    }
+    for (int a = 0; a < nb; ++a) rec[a] = beta[a];
+    return singular;
+}
+
+int orc_solve(const orc_problem *P, double *table, int32_t i_hi, int32_t i_lo, int64_t *singular,
+              int32_t threads)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0) return -1;
+    if (i_hi >= P->N || i_lo < 0 || i_lo > i_hi) return -1;
+    if (P->d > 64 || basis_size(P) > 65) return -1;
+    int64_t nsing = 0;
+    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 3);
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    /* Backward iteration; the strata of one step are independent. */
+    for (int32_t i = i_hi; i >= i_lo; --i) {
+        int64_t step_sing = 0;
+#pragma omp parallel reduction(+ : step_sing)
+        {
+            double *work = (double *)malloc(sizeof(double) * (size_t)wsz);
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t k = 0; k < G.K; ++k) step_sing += fit_stratum(P, &G, table, i, k, work);
+            free(work);
+        }
+        nsing += step_sing;
+    }
+    if (singular) *singular = nsing;
+    return 0;
+}
+
+/* ----------------------------------------------------------- read-out -- */
+
+/* ROOT read-out: the MDP identity with the initial law delta_{x0} (the value
+ * functions do not depend on the initial law, Section 2): LP0 regressions on
+ * the point x0, z first, then y with the fitted z in the i = 0 driver term. */
+int orc_root(const orc_problem *P, const double *table, const double *x0, int32_t M_root,
+             double *y0, double *z0)
+{
+    grid_t G;
+    if (check_problem(P, &G) != 0 || M_root < 1) return -1;
+    const int q = P->q;
+    const double dt = P->T / P->N;
+    double *Sp = (double *)malloc(sizeof(double) * (size_t)M_root * (q + 3));
+    double *y1 = Sp + M_root, *cvi = y1 + M_root, *dW = cvi + M_root;
+    for (int l = 0; l < q; ++l) z0[l] = 0.0;
+    for (int32_t m = 0; m < M_root; ++m) {
+        path_stream s;
+        stream_init(&s, P->seed, P->inst, 0, 0xFFFFFFFFu, (uint32_t)m);
+        simulate(P, &G, table, 0, &s, x0, dW + (int64_t)m * q, Sp + m, y1 + m, cvi + m);
+        for (int l = 0; l < q; ++l) z0[l] += Sp[m] * dW[(int64_t)m * q + l] / dt;
+    }
+    for (int l = 0; l < q; ++l) z0[l] /= M_root;
+    double zc[64];
+    for (int l = 0; l < q; ++l) zc[l] = clampv(z0[l], P->clamp_z);
+    double acc = 0.0;
+    for (int32_t m = 0; m < M_root; ++m)
+        acc += Sp[m] + orc_driver(P, 0.0, x0, y1[m], zc) * dt - cvi[m];
+    *y0 = acc / M_root;
+    for (int l = 0; l < q; ++l) z0[l] = zc[l];
+    free(Sp);
+    return 0;
+}

@@ -1,0 +1,108 @@
+/*
+ * srmdp_oracle.h -- plain FP64 CPU oracle of the stratified regression
+ * multistep-forward dynamic programming (SRMDP) backward sweep of
+ * Gobet, Lopez-Salas, Turkedjiev, Vazquez, "Stratified regression Monte-Carlo
+ * scheme for semilinear PDEs and BSDEs with large scale parallelization on
+ * GPUs" (arXiv 2407.21085).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP library.  It is
+ * called from the test-suite, from the smoke check and from the CPU-baseline
+ * leg of the benchmark, and from nothing else.  It shares no code, header,
+ * constant table or helper with the GPU library; the only thing both sides
+ * agree on is the published definition of the Philox4x32-10 generator and the
+ * way the paper's random inputs are mapped onto its counter (documented below).
+ *
+ * Everything is computed in IEEE binary64, without fast-math, in one plain code
+ * path, following the paper's Algorithm SRMDP step by step.
+ */
+#ifndef SRMDP_ORACLE_H
+#define SRMDP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_LP0 = 0, ORC_LP1 = 1 };
+enum { ORC_DRV_LINEAR = 0, ORC_DRV_LOGISTIC = 1 };
+enum { ORC_G_COS_SUM = 0, ORC_G_LOGISTIC = 1 };
+
+typedef struct {
+    int32_t d, q;            /* space and Brownian dimensions */
+    double T;                /* horizon */
+    int32_t N;               /* number of time steps, dt = T/N */
+    const double *b;         /* [d] constant drift or NULL (zero) */
+    const double *sigma;     /* [d*q] row-major constant diffusion or NULL (identity, q == d) */
+    int32_t driver;          /* ORC_DRV_* */
+    int32_t terminal;        /* ORC_G_* */
+    double r, kappa;         /* linear driver f = -r*y + kappa*sum(z) */
+    double clamp_y, clamp_z; /* truncation levels; +inf disables */
+    const double *lo, *hi;   /* [d] domain of the stratification */
+    const int32_t *cells;    /* [d] cells per dimension, K = prod(cells) */
+    double mu;               /* logistic parameter */
+    int32_t M;               /* simulations per stratum */
+    int32_t basis;           /* ORC_LP0 / ORC_LP1 */
+    uint64_t seed;           /* Philox key */
+    uint32_t inst;           /* instance tag in the counter */
+    /* frozen control-variate network; NULL disables the control variate */
+    const double *cv_params; /* MLP parameters, layout of orc_mlp_forward */
+    int32_t cv_hidden;
+} orc_problem;
+
+/* Philox4x32-10 of one counter block. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* First n uniforms of the random stream of simulation (i, k, m). */
+void orc_path_uniforms(uint64_t seed, uint32_t inst, int32_t i, uint32_t k, uint32_t m,
+                       int32_t n, double *u);
+
+/* Starting point X_i of simulation (i, k, m), drawn from nu_k. */
+int orc_start_point(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, double *x);
+
+/* First n standard normals of simulation (i, k, m) (before the sqrt(dt) scale). */
+int orc_path_normals(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, int32_t n,
+                     double *out);
+
+/* Number of coefficients of a table: N * K * (1+q) * nb. */
+int64_t orc_table_elems(const orc_problem *P);
+
+/* Runs the backward iteration for i = i_hi down to i_lo (inclusive).  Rows
+ * i > i_hi of `table` must already hold the fitted coefficients.  Returns 0 on
+ * success, a negative value on invalid input.  `singular` (may be NULL)
+ * receives the number of strata whose Gram matrix was singular. */
+int orc_solve(const orc_problem *P, double *table, int32_t i_hi, int32_t i_lo,
+              int64_t *singular, int32_t threads);
+
+/* Cloud of one stratum at step i, given the fitted rows > i of `table`:
+ * Xi [M*d], dWi [M*q], Sp [M] (tail response g(X_N)+sum_{j>i} f_j dt, control
+ * variate included), y1 [M] (fitted y_{i+1} at X_{i+1}, g at i+1 = N), and
+ * cvi [M] (network term at t_i, zero without control variate). */
+int orc_cloud(const orc_problem *P, const double *table, int32_t i, uint32_t k,
+              double *Xi, double *dWi, double *Sp, double *y1, double *cvi);
+
+/* Evaluation of the fitted (truncated) y_i and z_i at n points x [n*d]. */
+int orc_eval(const orc_problem *P, const double *table, int32_t i, int64_t n,
+             const double *x, double *y, double *z);
+
+/* ROOT read-out: LP0 regression on the point x0 at i = 0 with M_root
+ * simulations (counter stratum tag 0xFFFFFFFF).  y0 scalar, z0 [q]. */
+int orc_root(const orc_problem *P, const double *table, const double *x0, int32_t M_root,
+             double *y0, double *z0);
+
+/* Evaluation of the sweep's driver and terminal function (test access). */
+double orc_driver(const orc_problem *P, double t, const double *x, double y, const double *z);
+double orc_terminal(const orc_problem *P, const double *x);
+
+/* Dense MLP (in -> H -> H -> out, SiLU) forward and parameter gradient of
+ * 0.5*|y - target|^2 summed over the batch.  Parameter layout:
+ * W1[H][in], b1[H], W2[H][H], b2[H], W3[out][H], b3[out]. */
+int64_t orc_mlp_param_count(int32_t in, int32_t H, int32_t out);
+void orc_mlp_forward(int32_t in, int32_t H, int32_t out, const double *params,
+                     const double *x, int64_t B, double *y);
+void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params,
+                      const double *x, const double *dy, int64_t B, double *grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

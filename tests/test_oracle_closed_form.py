@@ -1,0 +1,207 @@
+"""Pins of the oracle's responses and backward iteration against solutions
+that are known without running the algorithm.
+
+* Discrete closed form of the cos family.  With X = x0 + W (the SDE dynamics
+  and the Euler dynamics coincide), g(x) = cos(sum x) and the driver
+  f = -r y + kappa sum(z), the MDP identity eq. (MDP:intro) telescopes to the
+  one-step recursion y_i = E_i[y_{i+1} + f_i dt], dt z_i = E_i[y_{i+1} dW_i].
+  Gaussian integration by parts then gives, with w_N = 1 and
+  a = exp(-d dt/2) (1 - r dt + i kappa d dt) (i the imaginary unit),
+      w_i = a^{N-i},  y_i(x) = Re(w_i e^{i sum x}),
+      z_{i,l}(x) = exp(-d dt/2) Re(i w_{i+1} e^{i sum x}).
+  As M grows, the fit of stratum k tends to the nu_k-weighted L2 projection of
+  the exact y_i, z_i on the local space, computed here by Gauss-Legendre
+  quadrature.
+* The logistic benchmark of Section "Model, stratification, and performance
+  benchmark": continuous closed form y = omega/(1+omega), z = omega/(1+omega)^2,
+  omega = exp(t + sum x); the discrete scheme carries an O(dt) time bias.
+* The MSE indicators of the paper's Tables LP1d4 and LP0d4 (loose band only:
+  the paper's generator and exterior-cell convention differ).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def _nu_proj(fun, lows, highs, mu=1.0, npts=48):
+    """nu_k-weighted L2 projection of fun on span{1, xi_1..xi_d} over the cube."""
+    d = len(lows)
+    xs, ws = np.polynomial.legendre.leggauss(npts)
+    grids, wts = [], []
+    for a, b in zip(lows, highs):
+        grids.append(0.5 * (b - a) * xs + 0.5 * (a + b))
+        wts.append(0.5 * (b - a) * ws * mu * np.exp(-mu * grids[-1]) /
+                   (1 + np.exp(-mu * grids[-1])) ** 2)
+    mesh = np.meshgrid(*grids, indexing="ij")
+    W = np.ones_like(mesh[0])
+    for l in range(d):
+        shape = [1] * d
+        shape[l] = npts
+        W = W * wts[l].reshape(shape)
+    X = np.stack([m.ravel() for m in mesh], axis=1)
+    W = W.ravel()
+    c = 0.5 * (np.asarray(lows) + np.asarray(highs))
+    h = np.asarray(highs) - np.asarray(lows)
+    A = np.hstack([np.ones((X.shape[0], 1)), 2 * (X - c) / h])
+    G = (A * W[:, None]).T @ A
+    return np.linalg.solve(G, (A * W[:, None]).T @ fun(X))
+
+
+def _cube_bounds(P, k):
+    lo = np.asarray(P.lo, float)
+    h = (np.asarray(P.hi, float) - lo) / np.asarray(P.cells)
+    idx = []
+    for c in P.cells:
+        idx.append(k % c)
+        k //= c
+    a = lo + np.asarray(idx) * h
+    return a, a + h
+
+
+def _sandwich_se(A, S):
+    beta = np.linalg.lstsq(A, S, rcond=None)[0]
+    e = S - A @ beta
+    Gi = np.linalg.inv(A.T @ A)
+    V = Gi @ (A.T * e ** 2) @ A @ Gi
+    return np.sqrt(np.diag(V))
+
+
+def _cos_exact(P):
+    d, dt, N = P.d, P.dt, P.N
+    a = math.exp(-d * dt / 2) * complex(1 - P.r * dt, P.kappa * d * dt)
+
+    def y(i):
+        return lambda X: np.real(a ** (N - i) * np.exp(1j * X.sum(axis=1)))
+
+    def z(i):
+        return lambda X: math.exp(-d * dt / 2) * np.real(1j * a ** (N - i - 1) *
+                                                         np.exp(1j * X.sum(axis=1)))
+    return y, z
+
+
+@pytest.mark.parametrize("d,cells,N,M", [(1, [16], 4, 20000), (2, [4, 4], 3, 12000)])
+def test_pure_expectation_fits_match_projection_of_closed_form(d, cells, N, M):
+    """r = kappa = 0: y_i(x) = e^{-d(N-i)dt/2} cos(sum x), z_i = -e^{..} sin(sum x).
+    Each coefficient must lie within 5 standard errors of the projection (no
+    feedback between steps in this case, so the cloud's own standard error is
+    the whole Monte Carlo error)."""
+    P = O.Problem(d=d, N=N, lo=[-2.0] * d, hi=[2.0] * d, cells=cells, M=M, seed=3)
+    tab, sing = O.solve(P)
+    assert sing == 0
+    yex, zex = _cos_exact(P)
+    worst = 0.0
+    for i in range(N):
+        for k in range(P.K):
+            a, b = _cube_bounds(P, k)
+            Xi, dW, Sp, y1, cvi = O.cloud(P, tab, i, k)
+            c, h = 0.5 * (a + b), b - a
+            A = np.hstack([np.ones((M, 1)), 2 * (Xi - c) / h])
+            se_y = _sandwich_se(A, Sp)
+            py = _nu_proj(yex(i), a, b)
+            worst = max(worst, np.max(np.abs(tab[i, k, 0] - py) / se_y))
+            for l in range(P.q):
+                se_z = _sandwich_se(A, Sp * dW[:, l] / P.dt)
+                pz = _nu_proj(zex(i), a, b)
+                worst = max(worst, np.max(np.abs(tab[i, k, 1 + l] - pz) / se_z))
+    assert worst < 5.0, worst
+
+
+def test_coupled_driver_matches_discrete_closed_form():
+    """r = 2, kappa = 1 (strong coupling through y_{j+1} and z_j): inside the
+    domain, away from the boundary cells whose extrapolation biases the paths
+    that leave it, the fitted functions stay within a Monte Carlo band of the
+    discrete closed form (over seeds 5..7 the worst errors were 0.011 for y and
+    0.03 for z); a dropped, shifted or sign-flipped driver term moves y by more
+    than 0.05."""
+    P = O.Problem(d=1, N=4, lo=[-3.0], hi=[3.0], cells=[24], M=40000, r=2.0, kappa=1.0, seed=5)
+    tab, _ = O.solve(P)
+    yex, zex = _cos_exact(P)
+    xs = np.linspace(-1.5, 1.5, 61)[:, None]
+    for i in range(P.N):
+        y, z = O.evaluate(P, tab, i, xs)
+        assert np.max(np.abs(y - yex(i)(xs))) < 0.025
+        assert np.max(np.abs(z[:, 0] - zex(i)(xs))) < 0.06
+        assert abs(np.mean(y - yex(i)(xs))) < 0.004
+
+
+def test_cos_config_root_readout_matches_discrete_closed_form():
+    """d = 1, N = 10, f = -0.05 y, g = cos: y(0, 0) = [e^{-dt/2}(1 - r dt)]^N =
+    0.5768775 (continuous value e^{-0.55} = 0.5769498)."""
+    P = O.Problem(d=1, N=10, lo=[-4.0], hi=[4.0], cells=[32], M=512, r=0.05, seed=1)
+    tab, _ = O.solve(P)
+    c0 = (math.exp(-0.05) * (1 - 0.005)) ** 10
+    assert c0 == pytest.approx(0.5768775, abs=5e-8)
+    y0, z0 = O.root(P, tab, [0.0], 400000)
+    # ROOT standard error ~ sqrt(Var(cos(W_1))/M_root) ~ 7e-4; plus table error feedback
+    assert abs(y0 - c0) < 6e-3
+    assert abs(z0[0]) < 0.03
+    y07, _ = O.root(P, tab, [0.7], 400000)
+    assert abs(y07 - c0 * math.cos(0.7)) < 6e-3
+
+
+def test_logistic_root_readout_near_continuous_solution():
+    """The paper's logistic BSDE, d = q = 1 and 2: y(0,0) = 1/2, z(0,0) = 1/4;
+    the scheme differs by an O(dt) time bias plus Monte Carlo error."""
+    for d, N, cells, M in [(1, 20, 32, 2000), (2, 10, 16, 1000)]:
+        P = O.Problem(d=d, N=N, lo=[-4.0] * d, hi=[4.0] * d, cells=[cells] * d, M=M,
+                      driver=O.DRV_LOGISTIC, terminal=O.G_LOGISTIC, seed=1)
+        tab, _ = O.solve(P)
+        y0, z0 = O.root(P, tab, [0.0] * d, 200000)
+        assert abs(y0 - 0.5) < 0.015
+        np.testing.assert_allclose(z0, 0.25, atol=0.03)
+        # without the driver the same read-out would give E[g(X_T)] ~ 0.69
+        P0 = O.Problem(d=d, N=N, lo=[-4.0] * d, hi=[4.0] * d, cells=[cells] * d, M=M,
+                       driver=O.DRV_LINEAR, r=0.0, terminal=O.G_LOGISTIC, seed=1)
+        tab0, _ = O.solve(P0)
+        assert O.root(P0, tab0, [0.0] * d, 200000)[0] > 0.6
+
+
+def _mse_indicators(P, tab, rng, npts=1000):
+    """Eq. (mse): 10^3 nu-distributed test points per time step, ln of the mean."""
+    ey, ez = [], []
+    for i in range(P.N):
+        U = rng.random((npts, P.d))
+        R = np.log(U / (1 - U)) / P.mu
+        y, z = O.evaluate(P, tab, i, R)
+        w = np.exp(i * P.dt + R.sum(axis=1))
+        ey.append(np.mean((y - w / (1 + w)) ** 2))
+        ez.append(np.mean(((z - (w / (1 + w) ** 2)[:, None]) ** 2).sum(axis=1)))
+    return np.log(max(ey)), np.log(np.mean(ey)), np.log(np.mean(ez))
+
+
+@pytest.mark.parametrize("basis,N,C,M,paper", [
+    (O.LP1, 5, 3, 125, (-4.021483, -4.131725, -0.900286)),   # Table LP1d4, dt = 0.2
+    (O.LP0, 5, 8, 25, (-3.712973, -3.774071, -0.964842)),    # Table LP0d4, dt = 0.2
+])
+def test_paper_mse_band(basis, N, C, M, paper):
+    """Loose sanity band (+-0.4 in ln units) around the paper's printed
+    indicators, averaged over 4 seeds.  Not a parity pin."""
+    res = []
+    for seed in range(1, 5):
+        P = O.Problem(d=4, N=N, lo=[-6.5] * 4, hi=[6.5] * 4, cells=[C] * 4, M=M, basis=basis,
+                      driver=O.DRV_LOGISTIC, terminal=O.G_LOGISTIC, seed=seed)
+        tab, _ = O.solve(P)
+        res.append(_mse_indicators(P, tab, np.random.default_rng(100 + seed)))
+    np.testing.assert_allclose(np.mean(res, axis=0), paper, atol=0.4)
+
+
+def test_paper_sizes():
+    """K = #C^q for the rows of the paper's tables and the coefficient-array
+    footnote of Table LP0d6_1 (50 x 14^6 x 7 x 4 bytes = 9.81 GB)."""
+    rows = [  # (d, N, #C formula, printed K)
+        (4, 5, math.floor(4 * math.sqrt(5)), 4096), (4, 50, math.floor(4 * math.sqrt(50)), 614656),
+        (6, 20, math.floor(2 * math.sqrt(20)), 262144), (11, 20, math.floor(math.sqrt(20)), 4194304),
+        (4, 50, math.floor(3 * math.sqrt(4 * math.sqrt(50))) - 5, 10000),
+        (6, 50, math.floor(1.5 * math.sqrt(6 * math.sqrt(50))) - 3, 46656),
+    ]
+    for d, N, C, K in rows:
+        P = O.Problem(d=d, N=N, lo=[-6.5] * d, hi=[6.5] * d, cells=[C] * d, M=d + 1,
+                      basis=O.LP0)
+        assert P.K == K
+    P = O.Problem(d=6, N=50, lo=[-6.5] * 6, hi=[6.5] * 6, cells=[14] * 6, M=7, basis=O.LP0)
+    nbytes = O.lib().orc_table_elems(P.c()) * 4
+    assert nbytes == 50 * 14 ** 6 * 7 * 4
+    assert nbytes / 2 ** 30 == pytest.approx(9.81, abs=0.01)   # the printed "9.81 GBytes"

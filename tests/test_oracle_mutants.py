@@ -1,0 +1,88 @@
+"""The oracle's pins must catch plausible mistakes.  Each case plants one
+mistake in a copy of the oracle's C source (on the CPU; nothing here touches
+a GPU), builds it, and checks that the pin meant to catch that kind of
+mistake now fails."""
+import os
+import tempfile
+
+import pytest
+
+import oracle as O
+import test_oracle_closed_form as CF
+import test_oracle_regression as RG
+import test_oracle_rng as RN
+
+
+def _brute_force_lp1():
+    RG.test_lp1_fit_matches_bruteforce_least_squares(RG._lstsq, 2)
+
+
+def _pure_expectation():
+    CF.test_pure_expectation_fits_match_projection_of_closed_form(1, [16], 4, 20000)
+
+
+MUTANTS = [
+    # (name, original text, planted mistake, pin that must fail)
+    ("drop the j=i driver term",
+     "double SY = Sp[m] + orc_driver(P, i * dt, x, y1[m], zfit) * dt - cvi[m];",
+     "double SY = Sp[m] - cvi[m];",
+     CF.test_coupled_driver_matches_discrete_closed_form),
+    ("driver uses y_j(X_j) instead of y_{j+1}(X_{j+1})",
+     "S += orc_driver(P, j * dt, x, ynext, z) * dt;",
+     "S += orc_driver(P, j * dt, x, y_at(P, G, table, j, x), z) * dt;",
+     CF.test_coupled_driver_matches_discrete_closed_form),
+    ("sign of the kappa term",
+     "return -P->r * y + P->kappa * sz;",
+     "return -P->r * y - P->kappa * sz;",
+     CF.test_coupled_driver_matches_discrete_closed_form),
+    ("z response scaled by 1/sqrt(dt)",
+     "double resp = Sp[m] * dWi[(int64_t)m * q + l] / dt;",
+     "double resp = Sp[m] * dWi[(int64_t)m * q + l] / sqrt(dt);",
+     _pure_expectation),
+    ("Brownian increment scaled by dt",
+     "const double dt = P->T / P->N, sdt = sqrt(dt);",
+     "const double dt = P->T / P->N, sdt = dt;",
+     _pure_expectation),
+    ("path stops one step early",
+     "for (int32_t j = i; j < P->N; ++j) {\n        for (int l = 0; l < q; ++l)",
+     "for (int32_t j = i; j < P->N - 1; ++j) {\n        for (int l = 0; l < q; ++l)",
+     _pure_expectation),
+    ("start point uniform in the cube",
+     "x[l] = stratify_one(P->mu, xm, xp, stream_uniform(s, l));",
+     "x[l] = xm + stream_uniform(s, l) * (xp - xm);",
+     lambda: RN.test_start_sampler_in_cube_ks_and_mean(21, 1.0)),
+    ("Box-Muller pair reuses the cosine",
+     "return (n % 2 == 0) ? rho * cos(theta) : rho * sin(theta);",
+     "return (n % 2 == 0) ? rho * cos(theta) : rho * cos(theta);",
+     RN.test_normals_uncorrelated_across_lags),
+    ("Cholesky with a transposed operand",
+     "for (int t = 0; t < c; ++t) s -= L[r * n + t] * L[c * n + t];",
+     "for (int t = 0; t < c; ++t) s -= L[t * n + r] * L[c * n + t];",
+     _brute_force_lp1),
+    ("uncentred basis",
+     "phi[1 + l] = 2.0 * (x[l] - centre) / G->h[l];",
+     "phi[1 + l] = 2.0 * (x[l] - lower) / G->h[l];",
+     _brute_force_lp1),
+    ("logistic driver constant with the wrong sign",
+     "return sz * (y - (2.0 + P->q) / (2.0 * P->q));",
+     "return sz * (y + (2.0 + P->q) / (2.0 * P->q));",
+     CF.test_logistic_root_readout_near_continuous_solution),
+    ("Philox key bump skipped",
+     "k0 += weyl0;",
+     "k0 += 0u;",
+     RN.test_philox_matches_rocrand_engine),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_planted_mistake(name, old, new, pin):
+    src = open(O._SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {name}"
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "mutant.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        lib = O.compile_source(path, os.path.join(tmp, "libmutant.so"))
+        with O.using_library(lib):
+            with pytest.raises(AssertionError):
+                pin()
