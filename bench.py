@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the SRMDP backward sweep on one MI355X.
+
+One benchmark step = one full backward sweep (every backward step i = N-1..0
+of Algorithm SRMDP: stratified sampling, Euler paths, responses with table
+look-ups, z and y regressions, table writes) of the headline workload:
+logistic BSDE, d = q = 8, [-3, 3]^8 in 4^8 = 65536 strata, M = 64, N = 50,
+LP1, binary32 paths with binary64 Gram sums and solves.  Inputs are synthetic
+(the problem is analytic); nothing is read from disk.
+
+Prints one JSON line:
+  value        path-steps per second of the whole sweep (K M N(N+1)/2 per sweep)
+  roofline     ALU roofline of the sweep-step kernel: algorithmic lane operations
+               per launch / average launch time (HIP events around the step
+               kernels, on the stream they run on) against the VALU issue peak
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+_ROOT = os.path.dirname(os.path.abspath(__file__))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+import workloads as W  # noqa: E402
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 39.3e12 VALU lane-ops/s;
+# FP32 vector 157.3 TFLOP/s (packed FMA).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+FP32_PEAK_FLOPS = 157.3e12
+
+PHILOX_OPS = 10 * 8 + 9 * 2      # per block: 2 mul-hi, 2 mul-lo, 4 xor per round; key bumps
+UNIFORM_OPS = 4                  # shift, or, convert, scale
+BOX_MULLER_OPS = 8               # log, sqrt, sincos (2), 4 multiplies per pair
+LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma, xi fma
+
+
+def algorithmic_ops(cfg: dict, lookup_terms: int):
+    """Lane operations the method needs (lower bound, before compiler overhead).
+
+    Per path-step (d = q here): ceil(q/4) Philox blocks and their 4 uniforms,
+    q/2 Box-Muller pairs, q scalings of dW, d Euler adds, d cell locations,
+    lookup_terms * d FMAs of the LP evaluations + 2 for truncation, 3 for the
+    driver.  Per sample: ceil(d/4) Philox blocks, d uniforms and inverse CDFs
+    (2 logs + 6 ops), and the binary64 Gram/right-hand-side products
+    nb(nb+1)/2 + q nb + nb plus the y completion q nb + 5.
+    """
+    d = q = cfg["d"]
+    nb = d + 1 if cfg["basis"] == "LP1" else 1
+    blocks = math.ceil(q / 4)
+    per_step = (blocks * (PHILOX_OPS + 4 * UNIFORM_OPS) + (q // 2 + q % 2) * BOX_MULLER_OPS
+                + q + d + d * LOCATE_OPS + lookup_terms * d + 2 + 3)
+    per_sample = (math.ceil(d / 4) * PHILOX_OPS + d * (UNIFORM_OPS + 8)
+                  + nb * (nb + 1) // 2 + q * nb + nb + q * nb + 5)
+    flops_step = 2 * q + d + d * 6 + lookup_terms * 2 * d + 4 + (q // 2) * 6
+    return per_step, per_sample, flops_step
+
+
+def _omp_threads() -> int:
+    import oracle as O
+    return int(O.max_threads())
+
+
+def cpu_baseline(cfg: dict, seconds: float) -> dict:
+    """The FP64 oracle as it stands, on the first backward steps of the same
+    workload (steps N-1, N-2, ... until about `seconds` of CPU work)."""
+    import numpy as np
+
+    import oracle as O
+    sys.path.insert(0, os.path.join(_ROOT, "tests"))
+    from sides import oracle_problem
+    P = oracle_problem(cfg)
+    table = np.zeros(P.table_shape())
+    done, t_total, i = 0, 0.0, cfg["N"] - 1
+    while i >= 0:
+        t0 = time.perf_counter()
+        O.solve(P, table=table, i_hi=i, i_lo=i)
+        t_total += time.perf_counter() - t0
+        done += W.path_steps(cfg, i_hi=i, i_lo=i)
+        i -= 1
+        if t_total > seconds:
+            break
+    return {"value": done / t_total, "unit": "path-steps/s", "cores": _omp_threads(),
+            "kind": "oracle",
+            "sample": f"{cfg['name']}: backward steps {cfg['N'] - 1}..{i + 1} "
+                      f"({done} FP64 path-steps in {t_total:.1f} s)"}
+
+
+def _product_args(S, cfg: dict):
+    """The workload as arguments of the HIP library."""
+    logistic = cfg["driver"] == "logistic"
+    P = S.Problem(d=cfg["d"], N=cfg["N"], T=cfg["T"],
+                  driver=S.DRV_LOGISTIC if logistic else S.DRV_LINEAR,
+                  terminal=S.G_LOGISTIC if cfg["terminal"] == "logistic" else S.G_COS_SUM,
+                  r=cfg.get("r", 0.0), kappa=cfg.get("kappa", 0.0))
+    G = S.Grid(cfg["lo"], cfg["hi"], cfg["cells"], cfg["mu"])
+    Opt = S.Options(M=cfg["M"], basis=S.LP1 if cfg["basis"] == "LP1" else S.LP0,
+                    prec=S.FP32 if cfg["prec"] == "fp32" else S.FP64, seed=cfg["seed"])
+    return P, G, Opt
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed full sweeps")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed full sweeps")
+    ap.add_argument("--workload", default="cfg5", choices=sorted(W.CONFIGS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--root-paths", type=int, default=1 << 20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sweep's "
+              "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2407_21085_amd as S
+
+    cfg = W.config(args.workload)
+    P, G, Opt = _product_args(S, cfg)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    table = S.srmdp.alloc_table(P, G, Opt)
+    ws = S.srmdp.alloc_workspace(P, G, Opt)
+    steps_per_sweep = W.path_steps(cfg)
+
+    def sweep():
+        return S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=True)[1]
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            sweep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        stats = [sweep() for _ in range(args.steps)]
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms_sweep = ev0.elapsed_time(ev1) / args.steps
+    ms_steps = sum(s["ms_steps"] for s in stats) / args.steps
+    launches = stats[0]["step_launches"]
+    value = steps_per_sweep / (ms_sweep / 1e3)
+
+    lookup_terms = 2 if (cfg["driver"] == "logistic" or cfg.get("kappa", 0.0)) else 1
+    ops_step, ops_sample, flops_step = algorithmic_ops(cfg, lookup_terms)
+    K = int(math.prod(cfg["cells"]))
+    samples = K * cfg["M"] * cfg["N"]
+    ops_sweep = steps_per_sweep * ops_step + samples * ops_sample
+    avg_launch_s = ms_steps / launches / 1e3
+    achieved = ops_sweep / launches / avg_launch_s
+
+    y0_root, z0_root = S.root(P, G, Opt, table, cfg["x0"], args.root_paths, workspace=ws)
+    x0 = torch.tensor([cfg["x0"]], dtype=torch.float64, device=dev)
+    y0_tab, _ = S.evaluate(P, G, Opt.basis, Opt.prec, table, 0, x0)
+
+    out = {
+        "metric": "paths·steps/s + full-sweep time at fixed y(0,x0) error, plain vs control-variate",
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_sweep,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic (analytic logistic BSDE, seeded Philox4x32-10 draws)",
+        "config": {"workload": cfg["name"], "d": cfg["d"], "K": K, "M": cfg["M"],
+                   "N": cfg["N"], "basis": cfg["basis"], "precision": "fp32 paths, fp64 solves",
+                   "form": "plain", "parallelism": "1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "sweep_step_kernel", "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches_per_sweep": launches, "ops_per_path_step": ops_step,
+                     "ops_per_sample": ops_sample,
+                     "fp32_flop_frac": steps_per_sweep * flops_step / (ms_steps / 1e3)
+                     / FP32_PEAK_FLOPS},
+        "sweep_ms_kernels_only": ms_steps,
+        "wall_s_timed": wall,
+        "y0_root": y0_root,
+        "y0_table": float(y0_tab.cpu()[0]),
+        "y0_exact_continuous": 0.5 if cfg["terminal"] == "logistic" else None,
+        "lanes_per_cube": stats[0]["lanes_per_cube"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,200 @@
+/*
+ * srmdp.h -- C ABI of the MI355X (gfx950) library for the backward
+ * dynamic-programming sweep of the stratified regression Monte-Carlo scheme
+ * (SRMDP) of Gobet, Lopez-Salas, Turkedjiev and Vazquez, "Stratified regression
+ * Monte-Carlo scheme for semilinear PDEs and BSDEs with large scale
+ * parallelization on GPUs", arXiv 2407.21085.
+ *
+ * The library solves the decoupled FBSDE of the paper's eq. (fbsde)-(eds)
+ * (equivalently the semilinear PDE eq. (pde)) on the time grid t_i = i T/N with
+ * the multistep-forward dynamic programming identity eq. (MDP:intro), by
+ * Algorithm SRMDP (Section 3.1): for i = N-1 down to 0, every stratum H_k of a
+ * uniform grid gets M fresh starting points drawn from the restricted logistic
+ * law nu_k (assumption (A_nu), Algorithm "stratify"); each is simulated to t_N
+ * (Algorithm "Euler dynamics"), and the responses of eq. (PsiM) are regressed on
+ * the local space LP0 or LP1 of assumption (A_Strat).  Only the coefficient
+ * table is kept.
+ *
+ * Conventions shared by every entry point
+ *  - C99-compatible, no exceptions cross the ABI; every call returns a
+ *    srmdp_status; srmdp_last_error() describes the last failure on the
+ *    calling thread.
+ *  - Device work is enqueued on `stream` (a hipStream_t passed as void*;
+ *    NULL = the null stream) and is asynchronous unless a host output is
+ *    requested (stats, read-outs), in which case the call synchronises the
+ *    stream before returning.
+ *  - The caller owns every buffer.  The library allocates no device memory in
+ *    srmdp_solve/srmdp_eval/srmdp_root/srmdp_draw; scratch comes from the
+ *    caller's workspace.  It keeps only cached hipGraph executables (flag
+ *    SRMDP_F_GRAPH), released by srmdp_release_graphs().
+ *  - Pointer kinds are stated per argument: "host" pointers are read during
+ *    the call only; "device" pointers must stay valid until the enqueued work
+ *    has finished.
+ *  - Argument errors are detected before anything is enqueued and return
+ *    SRMDP_E_INVALID (or SRMDP_E_WORKSPACE for an undersized workspace,
+ *    SRMDP_E_UNSUPPORTED for a valid request outside what is compiled).
+ */
+#ifndef SRMDP_H
+#define SRMDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRMDP_MAX_D 16          /* largest d = q compiled */
+#define SRMDP_ROOT_STRATUM 0xFFFFFFFFu  /* counter stratum tag of ROOT paths */
+
+typedef enum {
+    SRMDP_OK = 0,
+    SRMDP_E_INVALID = -1,      /* bad argument, nothing enqueued */
+    SRMDP_E_UNSUPPORTED = -2,  /* valid request that this build does not cover */
+    SRMDP_E_WORKSPACE = -3,    /* workspace smaller than srmdp_workspace_bytes() */
+    SRMDP_E_HIP = -4,          /* a HIP runtime call failed (message in srmdp_last_error) */
+    SRMDP_E_NUMERIC = -5       /* SRMDP_F_CHECK_FINITE found a non-finite coefficient */
+} srmdp_status;
+
+/* Local approximation spaces of assumption (A_Strat): LP0 = span{1_H}, nb = 1;
+ * LP1 = span{1, x_1..x_d} on H, nb = d + 1. */
+typedef enum { SRMDP_LP0 = 0, SRMDP_LP1 = 1 } srmdp_basis;
+
+/* Arithmetic of the sweep.  FP64: everything in binary64.  FP32: paths,
+ * responses and table look-ups in binary32; Gram and right-hand-side sums,
+ * Cholesky factors and solves in binary64; coefficients stored in binary32. */
+typedef enum { SRMDP_FP64 = 0, SRMDP_FP32 = 1 } srmdp_precision;
+
+/* Driver f(t, x, y, z).  LINEAR: f = -r y + kappa sum_l z_l.  LOGISTIC: the
+ * paper's benchmark (Section 5.1), f = (sum_l z_l)(y - (2 + q)/(2 q)). */
+typedef enum { SRMDP_DRV_LINEAR = 0, SRMDP_DRV_LOGISTIC = 1 } srmdp_driver;
+
+/* Terminal condition g.  COS_SUM: g = cos(sum_l x_l).  LOGISTIC: the paper's
+ * benchmark, g = omega(T,x)/(1 + omega(T,x)), omega(t,x) = exp(t + sum_l x_l). */
+typedef enum { SRMDP_G_COS_SUM = 0, SRMDP_G_LOGISTIC = 1 } srmdp_terminal;
+
+/* Problem data (eq. (fbsde)-(eds) with constant coefficients). */
+typedef struct {
+    int32_t d, q;          /* 1..SRMDP_MAX_D; the built-in f and g need q == d */
+    double T;              /* horizon > 0 */
+    int32_t N;             /* time steps, 1..65535; dt = T / N */
+    const double *b;       /* host [d]: constant drift; NULL = 0 */
+    const double *sigma;   /* host [d*q] row-major constant diffusion; NULL = identity */
+    int32_t driver;        /* srmdp_driver */
+    int32_t terminal;      /* srmdp_terminal */
+    double r, kappa;       /* LINEAR driver parameters */
+    double clamp_y, clamp_z; /* truncation levels C_y, C_z of eq. (TL), applied when a
+                              * fitted function is evaluated; INFINITY = off */
+} srmdp_problem;
+
+/* Stratification (assumption (A_Strat) with equal-size cells, assumption
+ * (A_nu) for the sampling law).  Cells are half-open; points outside
+ * [lo, hi) are evaluated with the affine fit of the nearest boundary cell;
+ * only the K = prod(cells) bounded cells are sampled. */
+typedef struct {
+    const double *lo, *hi;   /* host [d], lo < hi */
+    const int32_t *cells;    /* host [d], >= 1; K = prod(cells) <= 2^31 - 1 */
+    double mu;               /* logistic parameter > 0 */
+} srmdp_grid;
+
+/* Option flags. */
+#define SRMDP_F_GRAPH        0x1u  /* capture the N step launches in a cached hipGraph */
+#define SRMDP_F_CHECK_FINITE 0x2u  /* fail with SRMDP_E_NUMERIC on a non-finite coefficient */
+
+typedef struct {
+    int32_t M;              /* simulations per stratum, >= nb (Definition of the clouds) */
+    int32_t basis;          /* srmdp_basis */
+    int32_t prec;           /* srmdp_precision */
+    uint64_t seed;          /* Philox4x32-10 key = (seed mod 2^32, seed >> 32) */
+    uint32_t instance;      /* counter tag, < 65536 */
+    int32_t step_hi;        /* first backward step to run (-1 = N-1); rows > step_hi of the
+                             * table must hold a previous run's coefficients (resume) */
+    int32_t step_lo;        /* last backward step to run (-1 = 0) */
+    int32_t lanes_per_cube; /* 0 = automatic; else 8, 16, 32, 64, 128 or 256 */
+    uint32_t flags;         /* SRMDP_F_* */
+    uint8_t *face_flags;    /* device [N*K] or NULL.  When set, entry i*K + k of every step
+                             * run becomes 1 if a simulation of stratum k at step i looked
+                             * up a table row at a point within face_eps cell widths of an
+                             * interior cell face (where binary32 and binary64 positions may
+                             * pick different cells), else 0 */
+    double face_eps;        /* distance in cell widths; <= 0 means 1e-5 */
+} srmdp_options;
+
+typedef struct {
+    uint64_t singular_cubes;   /* strata whose Gram matrix fell back to LP0 */
+    uint64_t path_steps;       /* Euler steps simulated */
+    float ms_total;            /* device time of everything the call enqueued (hipEvents) */
+    float ms_steps;            /* device time of the backward-step kernels alone (hipEvents
+                                * around them); -1 when the steps ran from a hipGraph */
+    int32_t step_launches;     /* backward-step kernels launched */
+    int32_t lanes_per_cube;    /* lanes per stratum actually used */
+    uint64_t near_face_paths;  /* simulations with a near-face look-up (face_flags set) */
+} srmdp_stats;
+
+/* Number of coefficients of the table: N * K * (1 + q) * nb.  Layout
+ * table[i][k][c][b], i < N, k lexicographic with dimension 0 fastest,
+ * c in {y, z_1..z_q}, b in {1, xi_1..xi_d} with the cube-centred, scaled
+ * coordinate xi_l = 2 (x_l - centre_l) / h_l.  Returns 0 on invalid input. */
+size_t srmdp_table_elems(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis);
+
+/* Device workspace bytes srmdp_solve needs; 0 on invalid input. */
+size_t srmdp_workspace_bytes(const srmdp_problem *problem, const srmdp_grid *grid,
+                             const srmdp_options *opts);
+
+/* Algorithm SRMDP (Section 3.1, eq. (PsiM)) for i = step_hi .. step_lo.
+ *  table      device, (1+q)*nb*K*N values of the option's precision (double for
+ *             FP64, float for FP32), layout as in srmdp_table_elems; rows
+ *             step_lo..step_hi are written, rows > step_hi are read.
+ *  workspace  device, ws_bytes >= srmdp_workspace_bytes(...).
+ *  stats      host or NULL; when non-NULL the call synchronises `stream`.
+ * Draws: stratum k, simulation m, step i uses Philox4x32-10 counter
+ * (block, m, k, i | instance << 16); block 0..ceil(d/4)-1 words give the start
+ * point (Algorithm "stratify"), later blocks give Box-Muller normals in pairs. */
+srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
+                         const srmdp_options *opts, void *table, void *workspace,
+                         size_t ws_bytes, srmdp_stats *stats, void *stream);
+
+/* Evaluation of the fitted, truncated y_i and z_i (eq. (PsiM)'s y^M_i, z^M_i)
+ * at n points.  table device (precision prec); x device [n*d] doubles;
+ * y device [n] or NULL; z device [n*q] or NULL. */
+srmdp_status srmdp_eval(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis,
+                        int32_t prec, const void *table, int32_t i, const double *x, int64_t n,
+                        double *y, double *z, void *stream);
+
+/* ROOT read-out of y(0, x0), z(0, x0): the MDP identity with the initial law
+ * delta_{x0} (the value functions do not depend on the initial law, Section 2),
+ * i.e. an LP0 regression on the point x0 with M_root simulations (counter
+ * stratum SRMDP_ROOT_STRATUM, step 0): z first, then y with the fitted z in the
+ * i = 0 driver term.  table device (full, precision opts->prec); x0 host [d];
+ * y0 host scalar; z0 host [q]; workspace as for srmdp_solve.  Synchronises. */
+srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid,
+                        const srmdp_options *opts, const void *table, const double *x0,
+                        int32_t M_root, double *y0, double *z0, void *workspace,
+                        size_t ws_bytes, void *stream);
+
+/* Random inputs of the sweep, for checking the generator (test access).
+ * kind 0: the first `count` uniforms of each simulation's stream;
+ * kind 1: the first `count` standard normals (before the sqrt(dt) scale);
+ * kind 2: the starting point (count must equal d).
+ * Simulations are (i, k0 + a, m0 + c) for a < nk, c < nm; out device doubles
+ * [nk][nm][count], computed in precision prec and widened to double.
+ * problem/grid/opts as for srmdp_solve (grid and problem only matter for
+ * kinds 1 and 2). */
+srmdp_status srmdp_draw(const srmdp_problem *problem, const srmdp_grid *grid,
+                        const srmdp_options *opts, int32_t kind, int32_t i, uint32_t k0,
+                        uint32_t nk, uint32_t m0, uint32_t nm, int32_t count, double *out,
+                        void *stream);
+
+/* Releases cached hipGraph executables. */
+void srmdp_release_graphs(void);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *srmdp_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int32_t srmdp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRMDP_H */

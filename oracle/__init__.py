@@ -73,6 +73,7 @@ class _Problem(ctypes.Structure):
         ("M", ctypes.c_int32), ("basis", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("inst", ctypes.c_uint32),
         ("cv_params", ctypes.POINTER(ctypes.c_double)), ("cv_hidden", ctypes.c_int32),
+        ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
     ]
 
 
@@ -108,6 +109,8 @@ def _bind(L):
     L.orc_driver.restype = ctypes.c_double
     L.orc_terminal.argtypes = [pp, dp]
     L.orc_terminal.restype = ctypes.c_double
+    L.orc_max_threads.argtypes = []
+    L.orc_max_threads.restype = ctypes.c_int
     L.orc_mlp_param_count.argtypes = [ctypes.c_int32] * 3
     L.orc_mlp_param_count.restype = ctypes.c_int64
     L.orc_mlp_forward.argtypes = [ctypes.c_int32] * 3 + [dp, dp, ctypes.c_int64, dp]
@@ -144,6 +147,8 @@ class Problem:
     inst: int = 0
     cv_params: Optional[np.ndarray] = None
     cv_hidden: int = 0
+    face_flags: Optional[np.ndarray] = None   # uint8 [N, K] diagnostic output
+    face_eps: float = 1e-5
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -191,8 +196,17 @@ class Problem:
         s.seed, s.inst = self.seed, self.inst
         s.cv_params = _dp(cvp) if cvp is not None else None
         s.cv_hidden = self.cv_hidden if cvp is not None else 0
+        if self.face_flags is not None:
+            assert self.face_flags.dtype == np.uint8 and self.face_flags.flags["C_CONTIGUOUS"]
+            assert self.face_flags.shape == (self.N, self.K)
+            s.face_flags = self.face_flags.ctypes.data
+        s.face_eps = self.face_eps
         self._keep = keep
         return s
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:

@@ -38,6 +38,15 @@
 #include <omp.h>
 #endif
 
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------- Philox -- */
 
 /* Philox4x32-10 as published by Salmon et al. (SC'11): ten rounds of the
@@ -178,6 +187,20 @@ static int64_t cube_of(const grid_t *G, const double *x)
     int64_t k = 0;
     for (int l = 0; l < G->d; ++l) k += cell_of(G, l, x[l]) * G->stride[l];
     return k;
+}
+
+/* Diagnostic: is x within eps cell widths of a face between two cells? */
+static int near_interior_face(const grid_t *G, const double *x, double eps)
+{
+    for (int l = 0; l < G->d; ++l) {
+        double scale = (double)G->cells[l] / (G->hi[l] - G->lo[l]);
+        double t = (x[l] - G->lo[l]) * scale;
+        double c = (double)cell_of(G, l, x[l]);
+        double frac = t - c;
+        if (frac < eps && c > 0.0 && t >= 0.0) return 1;
+        if (frac > 1.0 - eps && c < (double)(G->cells[l] - 1)) return 1;
+    }
+    return 0;
 }
 
 static int64_t cube_cell(const grid_t *G, int64_t k, int l)
@@ -461,7 +484,7 @@ int orc_eval(const orc_problem *P, const double *table, int32_t i, int64_t n, co
  * Eq. (MDP:intro) and eq. (PsiM). */
 static void simulate(const orc_problem *P, const grid_t *G, const double *table, int32_t i,
                      path_stream *s, const double *x0, double *dWi, double *Sp, double *y1,
-                     double *cvi)
+                     double *cvi, int *near)
 {
     const int d = P->d, q = P->q;
     const double dt = P->T / P->N, sdt = sqrt(dt);
@@ -482,6 +505,7 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
             xn[l] = x[l] + drift * dt + diff;
         }
         double ynext = y_at(P, G, table, j + 1, xn);
+        if (near && j + 1 < P->N && near_interior_face(G, xn, P->face_eps)) *near = 1;
         if (j == i) {
             memcpy(dWi, dW, sizeof(double) * q);
             *y1 = ynext;
@@ -541,13 +565,15 @@ int orc_cloud(const orc_problem *P, const double *table, int32_t i, uint32_t k, 
 {
     grid_t G;
     if (check_problem(P, &G) != 0 || i < 0 || i >= P->N || (int64_t)k >= G.K) return -1;
+    int near = 0;
     for (int32_t m = 0; m < P->M; ++m) {
         path_stream s;
         stream_init(&s, P->seed, P->inst, i, k, (uint32_t)m);
         start_point(P, &G, &s, k, Xi + (int64_t)m * P->d);
         simulate(P, &G, table, i, &s, Xi + (int64_t)m * P->d, dWi + (int64_t)m * P->q, Sp + m,
-                 y1 + m, cvi + m);
+                 y1 + m, cvi + m, &near);
     }
+    if (P->face_flags) P->face_flags[(int64_t)i * G.K + k] = (uint8_t)near;
     return 0;
 }
 
@@ -663,7 +689,7 @@ int orc_root(const orc_problem *P, const double *table, const double *x0, int32_
     for (int32_t m = 0; m < M_root; ++m) {
         path_stream s;
         stream_init(&s, P->seed, P->inst, 0, 0xFFFFFFFFu, (uint32_t)m);
-        simulate(P, &G, table, 0, &s, x0, dW + (int64_t)m * q, Sp + m, y1 + m, cvi + m);
+        simulate(P, &G, table, 0, &s, x0, dW + (int64_t)m * q, Sp + m, y1 + m, cvi + m, NULL);
         for (int l = 0; l < q; ++l) z0[l] += Sp[m] * dW[(int64_t)m * q + l] / dt;
     }
     for (int l = 0; l < q; ++l) z0[l] /= M_root;

@@ -47,7 +47,15 @@ typedef struct {
     /* frozen control-variate network; NULL disables the control variate */
     const double *cv_params; /* MLP parameters, layout of orc_mlp_forward */
     int32_t cv_hidden;
+    /* diagnostic output: face_flags[i*K + k] = 1 when a simulation of stratum k
+     * at step i looked up a fitted row at a point within face_eps cell widths of
+     * an interior cell face; NULL disables */
+    uint8_t *face_flags;
+    double face_eps;
 } orc_problem;
+
+/* Threads the OpenMP loops over strata use. */
+int orc_max_threads(void);
 
 /* Philox4x32-10 of one counter block. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

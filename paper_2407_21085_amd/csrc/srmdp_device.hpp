@@ -1,0 +1,203 @@
+// Device building blocks of the SRMDP sweep for gfx950: counter-based random
+// inputs, the stratified start sampler, cell location and the problem data.
+// Everything here is inlined into the kernels of srmdp_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srmdp {
+
+constexpr int kMaxD = 16;
+
+// ------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): ten rounds of the two-multiplier S-box on a 128-bit counter, key
+// bumped by the Weyl constants between rounds.  Stateless: a simulation's
+// stream is addressed by its counter (block, m, k, i | instance << 16).
+struct Key {
+    uint32_t k0, k1;
+};
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, Key key)
+{
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    }
+    return c;
+}
+
+// Open uniform on (0,1): odd multiple of 2^-24 built from the top 23 bits.
+// Exact in binary32, so both precisions see the same real number.
+template <typename R>
+__device__ __forceinline__ R open_uniform(uint32_t w)
+{
+    return (R)(((w >> 9) << 1) | 1u) * (R)5.9604644775390625e-8;  // 2^-24
+}
+
+// Box-Muller (1958): (rho cos(2 pi u2), rho sin(2 pi u2)), rho = sqrt(-2 ln u1).
+__device__ __forceinline__ void box_muller(float u1, float u2, float &n0, float &n1)
+{
+    const float rho = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    n0 = rho * c;
+    n1 = rho * s;
+}
+
+__device__ __forceinline__ void box_muller(double u1, double u2, double &n0, double &n1)
+{
+    const double rho = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    n0 = rho * c;
+    n1 = rho * s;
+}
+
+// The Gaussian increments of one simulation.  Normal n of the simulation
+// (n = step_offset * D + l) is the cosine (n even) or sine (n odd) branch of the
+// Box-Muller pair n/2, which takes uniforms 2*(n/2) and 2*(n/2)+1 of the blocks
+// that follow the ceil(D/4) start blocks.  One Philox block feeds four normals.
+template <typename R, int D>
+struct NormalStream {
+    uint4 ctr;  // x = block, y = m, z = k, w = tag
+    Key key;
+    R buf[4];
+    uint32_t buf_block;  // block held in buf (0 = none: block 0 is a start block)
+
+    __device__ __forceinline__ void init(Key k, uint32_t m, uint32_t cube, uint32_t tag)
+    {
+        key = k;
+        ctr = make_uint4(0u, m, cube, tag);
+        buf_block = 0u;
+    }
+
+    __device__ __forceinline__ void fill(uint32_t blk)
+    {
+        ctr.x = blk;
+        const uint4 w = philox4x32_10(ctr, key);
+        box_muller(open_uniform<R>(w.x), open_uniform<R>(w.y), buf[0], buf[1]);
+        box_muller(open_uniform<R>(w.z), open_uniform<R>(w.w), buf[2], buf[3]);
+        buf_block = blk;
+    }
+
+    // D standard normals of step offset s = j - i (s is uniform over the wave).
+    __device__ __forceinline__ void step(uint32_t s, R *out)
+    {
+        constexpr uint32_t B0 = (D + 3) / 4;
+        if constexpr (D % 4 == 0) {
+#pragma unroll
+            for (int b = 0; b < D / 4; ++b) {
+                fill(B0 + s * (D / 4) + b);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) out[4 * b + w] = buf[w];
+            }
+        } else if constexpr (4 % D == 0) {
+            constexpr uint32_t per = 4 / D;  // steps served by one block
+            const uint32_t off = (s % per) * D;
+            if (off == 0) fill(B0 + s / per);
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                const uint32_t w = off + l;
+                out[l] = w == 0 ? buf[0] : w == 1 ? buf[1] : w == 2 ? buf[2] : buf[3];
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                const uint32_t n = s * D + l;
+                const uint32_t blk = B0 + n / 4;
+                if (blk != buf_block) fill(blk);
+                const uint32_t w = n % 4;
+                out[l] = w == 0 ? buf[0] : w == 1 ? buf[1] : w == 2 ? buf[2] : buf[3];
+            }
+        }
+    }
+};
+
+// Uniform number `idx` of a simulation's stream (start point words).
+__device__ __forceinline__ uint32_t stream_word(Key key, uint32_t m, uint32_t cube, uint32_t tag,
+                                                uint32_t idx)
+{
+    const uint4 w = philox4x32_10(make_uint4(idx / 4, m, cube, tag), key);
+    const uint32_t r = idx % 4;
+    return r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w;
+}
+
+// ------------------------------------------------------------ problem data
+
+// Per-dimension constants of one cell [x-, x+) for the restricted logistic
+// sampler, F(x) = 1/(1+exp(-mu x)), c the cell centre:
+//   delta = F(x+) - F(x-), uc = (F(c) - F(x-)) / delta (the uniform that maps
+//   to c), rp = delta / F(c), rs = delta / (1 - F(c)).
+template <typename R>
+struct CellF {
+    R delta, uc, rp, rs, centre, two_over_h, pad0, pad1;
+};
+
+// Algorithm "stratify": x = F^{-1}(p), p = F(x-) + u (F(x+) - F(x-)).  With
+// v = u - uc, p - F(c) = delta v, so
+//   mu (x - c) = log(p / F(c)) - log((1 - p) / (1 - F(c)))
+//              = log1p(rp v) - log1p(-rs v),
+// which gives the offset from the centre (hence the centred, scaled basis
+// coordinate) to full working precision.
+template <typename R>
+__device__ __forceinline__ R stratified_offset(const CellF<R> &c, R u, R inv_mu)
+{
+    const R v = u - c.uc;
+    return (log1p(c.rp * v) - log1p(-c.rs * v)) * inv_mu;
+}
+
+template <>
+__device__ __forceinline__ float stratified_offset<float>(const CellF<float> &c, float u,
+                                                         float inv_mu)
+{
+    const float v = u - c.uc;
+    return (log1pf(c.rp * v) - log1pf(-c.rs * v)) * inv_mu;
+}
+
+// Terminal condition g.
+template <typename R>
+__device__ __forceinline__ R terminal_g(int kind, R T, R sum_x)
+{
+    if (kind == 1) return (R)1 / ((R)1 + exp(-(T + sum_x)));  // omega/(1+omega)
+    return cos(sum_x);
+}
+
+template <>
+__device__ __forceinline__ float terminal_g<float>(int kind, float T, float sum_x)
+{
+    if (kind == 1) return 1.0f / (1.0f + expf(-(T + sum_x)));
+    return cosf(sum_x);
+}
+
+// Driver f(t, x, y, z) of the built-in problems; both depend on z only through
+// sum_l z_l.  kind 0: -r y + kappa sum z.  kind 1: sum z (y - (2+q)/(2q)).
+template <typename R>
+__device__ __forceinline__ R driver_f(int kind, R r, R kappa, R c_logistic, R y, R zsum)
+{
+    if (kind == 1) return zsum * (y - c_logistic);
+    return kappa * zsum - r * y;
+}
+
+template <typename R>
+__device__ __forceinline__ R clamp_level(R v, R L)
+{
+    return fmin(fmax(v, -L), L);
+}
+
+template <>
+__device__ __forceinline__ float clamp_level<float>(float v, float L)
+{
+    return fminf(fmaxf(v, -L), L);
+}
+
+}  // namespace srmdp

@@ -1,0 +1,587 @@
+// Host runtime of the SRMDP library: argument checks, workspace layout,
+// launch shapes, the backward driver (one kernel per step, optionally replayed
+// from a cached hipGraph) and the read-outs.  Implements include/srmdp.h.
+#include "../../include/srmdp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "srmdp_internal.hpp"
+
+using namespace srmdp;
+
+namespace {
+
+thread_local std::string g_error;
+
+srmdp_status fail(srmdp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+srmdp_status fail(srmdp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+srmdp_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SRMDP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------- validation
+struct Shape {
+    int d, q, N, nb, cmax;
+    uint64_t K;
+};
+
+srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s)
+{
+    if (!p || !g) return fail(SRMDP_E_INVALID, "problem and grid must be non-NULL");
+    if (p->d < 1 || p->d > SRMDP_MAX_D)
+        return fail(SRMDP_E_INVALID, "d = %d outside 1..%d", p->d, SRMDP_MAX_D);
+    if (p->q != p->d)
+        return fail(SRMDP_E_INVALID, "the built-in driver and terminal need q == d (q = %d, d = %d)",
+                    p->q, p->d);
+    if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(SRMDP_E_INVALID, "T must be finite and > 0");
+    if (p->N < 1 || p->N > 65535) return fail(SRMDP_E_INVALID, "N = %d outside 1..65535", p->N);
+    if (p->driver != SRMDP_DRV_LINEAR && p->driver != SRMDP_DRV_LOGISTIC)
+        return fail(SRMDP_E_INVALID, "unknown driver %d", p->driver);
+    if (p->terminal != SRMDP_G_COS_SUM && p->terminal != SRMDP_G_LOGISTIC)
+        return fail(SRMDP_E_INVALID, "unknown terminal %d", p->terminal);
+    if (!(p->clamp_y > 0.0) || !(p->clamp_z > 0.0))
+        return fail(SRMDP_E_INVALID, "truncation levels must be > 0 (INFINITY = off)");
+    if (!std::isfinite(p->r) || !std::isfinite(p->kappa))
+        return fail(SRMDP_E_INVALID, "driver parameters must be finite");
+    if (!g->lo || !g->hi || !g->cells) return fail(SRMDP_E_INVALID, "grid arrays must be non-NULL");
+    if (!(g->mu > 0.0) || !std::isfinite(g->mu)) return fail(SRMDP_E_INVALID, "mu must be > 0");
+    s.d = p->d;
+    s.q = p->q;
+    s.N = p->N;
+    s.K = 1;
+    s.cmax = 1;
+    for (int l = 0; l < p->d; ++l) {
+        if (!(g->lo[l] < g->hi[l]) || !std::isfinite(g->lo[l]) || !std::isfinite(g->hi[l]))
+            return fail(SRMDP_E_INVALID, "grid dimension %d: need finite lo < hi", l);
+        if (g->cells[l] < 1) return fail(SRMDP_E_INVALID, "grid dimension %d: cells < 1", l);
+        s.K *= (uint64_t)g->cells[l];
+        if (s.K > 0x7FFFFFFFull) return fail(SRMDP_E_INVALID, "K exceeds 2^31 - 1 strata");
+        s.cmax = std::max(s.cmax, (int)g->cells[l]);
+    }
+    if (p->b)
+        for (int l = 0; l < p->d; ++l)
+            if (!std::isfinite(p->b[l])) return fail(SRMDP_E_INVALID, "drift must be finite");
+    if (p->sigma)
+        for (int l = 0; l < p->d * p->q; ++l)
+            if (!std::isfinite(p->sigma[l])) return fail(SRMDP_E_INVALID, "sigma must be finite");
+    return SRMDP_OK;
+}
+
+srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
+{
+    if (!o) return fail(SRMDP_E_INVALID, "options must be non-NULL");
+    if (o->basis != SRMDP_LP0 && o->basis != SRMDP_LP1)
+        return fail(SRMDP_E_INVALID, "unknown basis %d", o->basis);
+    if (o->prec != SRMDP_FP64 && o->prec != SRMDP_FP32)
+        return fail(SRMDP_E_INVALID, "unknown precision %d", o->prec);
+    nb = o->basis == SRMDP_LP1 ? s.d + 1 : 1;
+    if (o->M < nb)
+        return fail(SRMDP_E_INVALID, "M = %d is below the dimension %d of the local space", o->M, nb);
+    if (o->instance >= 65536u) return fail(SRMDP_E_INVALID, "instance must be < 65536");
+    const int hi = o->step_hi < 0 ? s.N - 1 : o->step_hi;
+    const int lo = o->step_lo < 0 ? 0 : o->step_lo;
+    if (hi >= s.N || lo > hi) return fail(SRMDP_E_INVALID, "steps %d..%d outside 0..%d", hi, lo, s.N - 1);
+    const int L = o->lanes_per_cube;
+    if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64 && L != 128 && L != 256)
+        return fail(SRMDP_E_INVALID, "lanes_per_cube must be 0, 8, 16, 32, 64, 128 or 256");
+    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE))
+        return fail(SRMDP_E_INVALID, "unknown flag bits");
+    if (!(o->face_eps < 0.5) || std::isnan(o->face_eps))
+        return fail(SRMDP_E_INVALID, "face_eps must be < 0.5 cell widths");
+    return SRMDP_OK;
+}
+
+int lookup_mode(const srmdp_problem *p)
+{
+    if (std::isfinite(p->clamp_z)) return kLookupFull;
+    if (p->driver == SRMDP_DRV_LINEAR && p->kappa == 0.0) return kLookupY;
+    return kLookupYZ;
+}
+
+// ------------------------------------------------------------- workspace
+constexpr int kRootBlocks = 512;
+
+struct Layout {
+    size_t counters, cellF, bsig, lookup, root_partial, root_out, total;
+};
+
+Layout layout(const Shape &s, int nb, int is_float, int lk)
+{
+    const size_t rsz = is_float ? 4 : 8;
+    Layout L{};
+    size_t off = 0;
+    L.counters = off;
+    off = align_up(off + kCounterCount * sizeof(unsigned long long), 256);
+    L.cellF = off;
+    off = align_up(off + (size_t)s.d * s.cmax * 8 * rsz, 256);
+    L.bsig = off;
+    off = align_up(off + (size_t)(s.d + s.d * s.q) * rsz, 256);
+    L.root_partial = off;
+    off = align_up(off + (size_t)kRootBlocks * (s.d + 2) * sizeof(double), 256);
+    L.root_out = off;
+    off = align_up(off + (size_t)(s.d + 1) * sizeof(double), 256);
+    L.lookup = off;
+    off = align_up(off + (size_t)s.N * s.K * lookup_width(is_float, s.d, nb, lk) * rsz, 256);
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------- arguments
+template <typename R>
+void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g, const Shape &s,
+                    const srmdp_options *o)
+{
+    std::memset(&a, 0, sizeof a);
+    uint32_t stride = 1;
+    for (int l = 0; l < s.d; ++l) {
+        a.lo[l] = (R)g->lo[l];
+        a.scale[l] = (R)((double)g->cells[l] / (g->hi[l] - g->lo[l]));
+        a.cmax_f[l] = (R)(g->cells[l] - 1);
+        a.stride[l] = stride;
+        a.cells[l] = (uint32_t)g->cells[l];
+        stride *= (uint32_t)g->cells[l];
+    }
+    a.cmax = s.cmax;
+    a.K = (uint32_t)s.K;
+    a.N = s.N;
+    a.dt_d = p->T / p->N;
+    a.inv_dt = 1.0 / a.dt_d;
+    a.dt = (R)a.dt_d;
+    a.sqrt_dt = (R)std::sqrt(a.dt_d);
+    a.T = (R)p->T;
+    a.inv_mu = (R)(1.0 / g->mu);
+    a.driver = p->driver;
+    a.terminal = p->terminal;
+    a.r = (R)p->r;
+    a.kappa = (R)p->kappa;
+    a.c_logistic = (R)((2.0 + p->q) / (2.0 * p->q));
+    a.clamp_y = (R)p->clamp_y;
+    a.clamp_z = (R)p->clamp_z;
+    bool ident = true;
+    if (p->sigma)
+        for (int l = 0; l < s.d; ++l)
+            for (int c = 0; c < s.q; ++c)
+                if (p->sigma[l * s.q + c] != (l == c ? 1.0 : 0.0)) ident = false;
+    a.identity_sigma = ident ? 1 : 0;
+    bool drift = false;
+    if (p->b)
+        for (int l = 0; l < s.d; ++l)
+            if (p->b[l] != 0.0) drift = true;
+    a.has_drift = drift ? 1 : 0;
+    if (o) {
+        a.M = o->M;
+        a.key0 = (uint32_t)(o->seed & 0xFFFFFFFFull);
+        a.key1 = (uint32_t)(o->seed >> 32);
+        a.check_finite = (o->flags & SRMDP_F_CHECK_FINITE) ? 1 : 0;
+        a.face_flags = o->face_flags;
+        a.face_eps = (R)(o->face_eps > 0.0 ? o->face_eps : 1e-5);
+    }
+}
+
+void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g, const Shape &s)
+{
+    std::memset(&sa, 0, sizeof sa);
+    for (int l = 0; l < s.d; ++l) {
+        sa.lo[l] = g->lo[l];
+        sa.hi[l] = g->hi[l];
+        sa.cells[l] = g->cells[l];
+        sa.b[l] = p->b ? p->b[l] : 0.0;
+    }
+    for (int t = 0; t < s.d * s.q; ++t)
+        sa.sigma[t] = p->sigma ? p->sigma[t] : ((t / s.q) == (t % s.q) ? 1.0 : 0.0);
+    sa.d = s.d;
+    sa.q = s.q;
+    sa.cmax = s.cmax;
+    sa.mu = g->mu;
+}
+
+// Lanes per stratum: enough to give every lane one path up to a wavefront;
+// several strata share a 256-lane workgroup when M is small.
+int auto_lanes(int M)
+{
+    int L = 8;
+    while (L < M && L < 64) L *= 2;
+    return L;
+}
+
+bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube)
+{
+    per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M), 16);
+    int cpw = std::max(1, 256 / L);
+    const size_t lds_cap = 64 * 1024;
+    while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;
+    if ((size_t)cpw * per_cube > lds_cap) return false;
+    ls.threads = (unsigned)(cpw * L);
+    ls.blocks = (unsigned)((s.K + cpw - 1) / cpw);
+    ls.lds_bytes = (size_t)cpw * per_cube;
+    return true;
+}
+
+// ------------------------------------------------------------- graph cache
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::unordered_map<std::string, GraphEntry> g_graphs;
+
+std::string graph_key(const void *args, size_t n, hipStream_t st)
+{
+    std::string k((const char *)args, n);
+    k.append((const char *)&st, sizeof st);
+    return k;
+}
+
+template <typename R>
+srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o,
+                           const Shape &s, int nb, int lk, void *table, unsigned char *ws,
+                           const Layout &lay, hipStream_t st, hipEvent_t steps0 = nullptr,
+                           hipEvent_t steps1 = nullptr)
+{
+    const int is_float = sizeof(R) == 4;
+    const int L = o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
+    LaunchShape ls;
+    size_t per_cube;
+    if (!make_shape(s, nb, is_float, o->M, L, ls, per_cube))
+        return fail(SRMDP_E_UNSUPPORTED, "M = %d does not fit the per-workgroup LDS budget", o->M);
+    StepArgs<R> a;
+    fill_step_args<R>(a, p, g, s, o);
+    a.lanes = L;
+    a.lds_per_cube = per_cube;
+    SetupArgs sa;
+    fill_setup_args(sa, p, g, s);
+    const int hi = o->step_hi < 0 ? s.N - 1 : o->step_hi;
+    const int lo = o->step_lo < 0 ? 0 : o->step_lo;
+
+    HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
+    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    if (hi < s.N - 1)
+        HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, hi + 1,
+                                      s.N - 1, st),
+                "look-up rows");
+    if (steps0) HIP_TRY(hipEventRecord(steps0, st), "hipEventRecord");
+    for (int i = hi; i >= lo; --i) {
+        a.i = i;
+        a.tag = ((uint32_t)i & 0xFFFFu) | (o->instance << 16);
+        HIP_TRY(launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
+                               table, ws + lay.counters, st),
+                "sweep step");
+    }
+    if (steps1) HIP_TRY(hipEventRecord(steps1, st), "hipEventRecord");
+    return SRMDP_OK;
+}
+
+template <typename R>
+srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o,
+                        const Shape &s, int nb, void *table, void *workspace, srmdp_stats *stats,
+                        hipStream_t st)
+{
+    const int lk = lookup_mode(p);
+    const Layout lay = layout(s, nb, sizeof(R) == 4, lk);
+    unsigned char *ws = (unsigned char *)workspace;
+    hipEvent_t e0 = nullptr, e1 = nullptr, s0 = nullptr, s1 = nullptr;
+    bool graph_used = false;
+    if (stats) {
+        HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&s0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&s1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
+    }
+    srmdp_status rc = SRMDP_OK;
+    if ((o->flags & SRMDP_F_GRAPH) && st != nullptr) {
+        // key: every scalar argument and pointer that the captured launches bake in
+        std::vector<unsigned char> key;
+        auto put = [&](const void *v, size_t n) {
+            key.insert(key.end(), (const unsigned char *)v, (const unsigned char *)v + n);
+        };
+        put(p, sizeof *p);
+        if (p->b) put(p->b, sizeof(double) * s.d);
+        if (p->sigma) put(p->sigma, sizeof(double) * s.d * s.q);
+        put(g->lo, sizeof(double) * s.d);
+        put(g->hi, sizeof(double) * s.d);
+        put(g->cells, sizeof(int32_t) * s.d);
+        put(&g->mu, sizeof g->mu);
+        put(o, sizeof *o);
+        put(&table, sizeof table);
+        put(&workspace, sizeof workspace);
+        const std::string k = graph_key(key.data(), key.size(), st);
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        auto it = g_graphs.find(k);
+        if (it == g_graphs.end()) {
+            GraphEntry ent;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &graph);
+            if (rc != SRMDP_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+            ent.graph = graph;
+            HIP_TRY(hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            it = g_graphs.emplace(k, ent).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second.exec, st), "hipGraphLaunch");
+        graph_used = true;
+    } else {
+        rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st, s0, s1);
+        if (rc != SRMDP_OK) return rc;
+    }
+    const bool need_sync = stats || (o->flags & SRMDP_F_CHECK_FINITE);
+    if (need_sync) {
+        unsigned long long ctr[kCounterCount] = {0, 0, 0, 0};
+        if (stats) HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
+        HIP_TRY(hipMemcpyAsync(ctr, ws + lay.counters, sizeof ctr, hipMemcpyDeviceToHost, st), "counters");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (stats) {
+            std::memset(stats, 0, sizeof *stats);
+            stats->singular_cubes = ctr[kCounterSingular];
+            const int hi = o->step_hi < 0 ? s.N - 1 : o->step_hi;
+            const int lo = o->step_lo < 0 ? 0 : o->step_lo;
+            uint64_t steps = 0;
+            for (int i = lo; i <= hi; ++i) steps += (uint64_t)(s.N - i);
+            stats->path_steps = steps * s.K * (uint64_t)o->M;
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            stats->ms_total = ms;
+            stats->ms_steps = -1.f;
+            if (!graph_used) {
+                HIP_TRY(hipEventElapsedTime(&ms, s0, s1), "hipEventElapsedTime");
+                stats->ms_steps = ms;
+            }
+            stats->step_launches = hi - lo + 1;
+            stats->near_face_paths = ctr[kCounterNearFace];
+            stats->lanes_per_cube = o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            (void)hipEventDestroy(s0);
+            (void)hipEventDestroy(s1);
+        }
+        if ((o->flags & SRMDP_F_CHECK_FINITE) && ctr[kCounterNonFinite] != 0)
+            return fail(SRMDP_E_NUMERIC, "%llu non-finite coefficients", ctr[kCounterNonFinite]);
+    }
+    return SRMDP_OK;
+}
+
+}  // namespace
+
+namespace {
+template <typename R>
+srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o,
+                       const Shape &s, int nb, const void *table, const double *x0, int M_root,
+                       double *y0, double *z0, unsigned char *ws, hipStream_t st)
+{
+    const int lk = lookup_mode(p);
+    const Layout lay = layout(s, nb, sizeof(R) == 4, lk);
+    StepArgs<R> a;
+    fill_step_args<R>(a, p, g, s, o);
+    a.i = 0;
+    a.tag = (o->instance << 16);
+    SetupArgs sa;
+    fill_setup_args(sa, p, g, s);
+    RootPoint rp{};
+    for (int l = 0; l < s.d; ++l) rp.x[l] = x0[l];
+    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    if (s.N > 1)
+        HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, 1, s.N - 1, st),
+                "look-up rows");
+    const int blocks = std::min(kRootBlocks, std::max(1, (M_root + 255) / 256));
+    HIP_TRY(launch_root<R>(s.d, o->basis, lk, a, ws + lay.bsig, ws + lay.lookup, rp, M_root, blocks,
+                           (double *)(ws + lay.root_partial), (double *)(ws + lay.root_out), st),
+            "root kernels");
+    double out[SRMDP_MAX_D + 1];
+    HIP_TRY(hipMemcpyAsync(out, ws + lay.root_out, sizeof(double) * (s.d + 1), hipMemcpyDeviceToHost, st),
+            "root copy");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    *y0 = out[0];
+    for (int l = 0; l < s.q; ++l) z0[l] = out[1 + l];
+    return SRMDP_OK;
+}
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+int32_t srmdp_abi_version(void) { return 100; }
+
+const char *srmdp_last_error(void) { return g_error.c_str(); }
+
+size_t srmdp_table_elems(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis)
+{
+    Shape s;
+    if (check_problem(problem, grid, s) != SRMDP_OK) return 0;
+    if (basis != SRMDP_LP0 && basis != SRMDP_LP1) return 0;
+    const int nb = basis == SRMDP_LP1 ? s.d + 1 : 1;
+    return (size_t)s.N * s.K * (1 + s.q) * nb;
+}
+
+size_t srmdp_workspace_bytes(const srmdp_problem *problem, const srmdp_grid *grid,
+                             const srmdp_options *opts)
+{
+    Shape s;
+    int nb;
+    if (check_problem(problem, grid, s) != SRMDP_OK) return 0;
+    if (check_options(opts, s, nb) != SRMDP_OK) return 0;
+    return layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+}
+
+srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
+                         const srmdp_options *opts, void *table, void *workspace, size_t ws_bytes,
+                         srmdp_stats *stats, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    int nb;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    rc = check_options(opts, s, nb);
+    if (rc != SRMDP_OK) return rc;
+    if (!table || !workspace) return fail(SRMDP_E_INVALID, "table and workspace must be non-NULL");
+    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+    if (ws_bytes < need)
+        return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    hipStream_t st = (hipStream_t)stream;
+    if (opts->prec == SRMDP_FP32)
+        return solve_impl<float>(problem, grid, opts, s, nb, table, workspace, stats, st);
+    return solve_impl<double>(problem, grid, opts, s, nb, table, workspace, stats, st);
+}
+
+srmdp_status srmdp_eval(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis,
+                        int32_t prec, const void *table, int32_t i, const double *x, int64_t n,
+                        double *y, double *z, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    if (basis != SRMDP_LP0 && basis != SRMDP_LP1) return fail(SRMDP_E_INVALID, "unknown basis");
+    if (prec != SRMDP_FP64 && prec != SRMDP_FP32) return fail(SRMDP_E_INVALID, "unknown precision");
+    if (i < 0 || i >= s.N) return fail(SRMDP_E_INVALID, "row %d outside 0..%d", i, s.N - 1);
+    if (n < 0) return fail(SRMDP_E_INVALID, "n < 0");
+    if (n == 0) return SRMDP_OK;
+    if (!table || !x || (!y && !z)) return fail(SRMDP_E_INVALID, "table, x and one output are required");
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == SRMDP_FP32) {
+        StepArgs<float> a;
+        fill_step_args<float>(a, problem, grid, s, nullptr);
+        a.i = i;
+        HIP_TRY(launch_eval<float>(s.d, basis, a, table, x, n, y, z, st), "eval kernel");
+    } else {
+        StepArgs<double> a;
+        fill_step_args<double>(a, problem, grid, s, nullptr);
+        a.i = i;
+        HIP_TRY(launch_eval<double>(s.d, basis, a, table, x, n, y, z, st), "eval kernel");
+    }
+    return SRMDP_OK;
+}
+
+
+srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
+                        const void *table, const double *x0, int32_t M_root, double *y0, double *z0,
+                        void *workspace, size_t ws_bytes, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    int nb;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    rc = check_options(opts, s, nb);
+    if (rc != SRMDP_OK) return rc;
+    if (!table || !x0 || !y0 || !z0 || !workspace)
+        return fail(SRMDP_E_INVALID, "table, x0, y0, z0 and workspace are required");
+    if (M_root < 1) return fail(SRMDP_E_INVALID, "M_root must be >= 1");
+    for (int l = 0; l < s.d; ++l)
+        if (!std::isfinite(x0[l])) return fail(SRMDP_E_INVALID, "x0 must be finite");
+    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+    if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    hipStream_t st = (hipStream_t)stream;
+    if (opts->prec == SRMDP_FP32)
+        return root_impl<float>(problem, grid, opts, s, nb, table, x0, M_root, y0, z0,
+                                (unsigned char *)workspace, st);
+    return root_impl<double>(problem, grid, opts, s, nb, table, x0, M_root, y0, z0,
+                             (unsigned char *)workspace, st);
+}
+
+srmdp_status srmdp_draw(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
+                        int32_t kind, int32_t i, uint32_t k0, uint32_t nk, uint32_t m0, uint32_t nm,
+                        int32_t count, double *out, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    int nb;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    rc = check_options(opts, s, nb);
+    if (rc != SRMDP_OK) return rc;
+    if (kind < 0 || kind > 2) return fail(SRMDP_E_INVALID, "kind must be 0, 1 or 2");
+    if (i < 0 || i >= s.N) return fail(SRMDP_E_INVALID, "step %d outside 0..%d", i, s.N - 1);
+    if (count < 1 || (kind == 2 && count != s.d)) return fail(SRMDP_E_INVALID, "bad count");
+    if (kind == 2 && ((uint64_t)k0 + nk > s.K)) return fail(SRMDP_E_INVALID, "strata outside the grid");
+    if (!out) return fail(SRMDP_E_INVALID, "out must be non-NULL");
+    if ((uint64_t)nk * nm == 0) return SRMDP_OK;
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    hipStream_t st = (hipStream_t)stream;
+    SetupArgs sa;
+    fill_setup_args(sa, problem, grid, s);
+    if (opts->prec == SRMDP_FP32) {
+        StepArgs<float> a;
+        fill_step_args<float>(a, problem, grid, s, opts);
+        a.i = i;
+        a.tag = ((uint32_t)i & 0xFFFFu) | (opts->instance << 16);
+        HIP_TRY(launch_draw<float>(s.d, a, sa, kind, k0, nk, m0, nm, count, out, st), "draw kernel");
+    } else {
+        StepArgs<double> a;
+        fill_step_args<double>(a, problem, grid, s, opts);
+        a.i = i;
+        a.tag = ((uint32_t)i & 0xFFFFu) | (opts->instance << 16);
+        HIP_TRY(launch_draw<double>(s.d, a, sa, kind, k0, nk, m0, nm, count, out, st), "draw kernel");
+    }
+    return SRMDP_OK;
+}
+
+void srmdp_release_graphs(void)
+{
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (auto &kv : g_graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal interface between the host runtime (srmdp_host.cpp) and the HIP
+// kernels (srmdp_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace srmdp {
+
+constexpr int kMaxDim = 16;
+
+// What a look-up row holds for each stratum: the y coefficients only (the
+// driver does not use z), y and the sum of the z_l coefficients (both built-in
+// drivers depend on z only through sum_l z_l, and without truncation
+// sum_l z_l(x) = (sum_l beta_{z_l}) . phi(x)), or the whole record (z
+// truncation needs each component).
+enum LookupMode { kLookupY = 0, kLookupYZ = 1, kLookupFull = 2 };
+
+enum CounterIndex { kCounterSingular = 0, kCounterNonFinite = 1, kCounterNearFace = 2, kCounterCount = 4 };
+
+template <typename R, int D, int NB, int LK>
+struct LookupWidth {
+    static constexpr int raw = LK == kLookupY ? NB : LK == kLookupYZ ? 2 * NB : (1 + D) * NB;
+    static constexpr int align = sizeof(R) == 4 ? 4 : 2;  // 16-byte records
+    static constexpr int value = (raw + align - 1) / align * align;
+};
+
+inline int lookup_width(int prec_is_float, int d, int nb, int lk)
+{
+    const int raw = lk == kLookupY ? nb : lk == kLookupYZ ? 2 * nb : (1 + d) * nb;
+    const int align = prec_is_float ? 4 : 2;
+    return (raw + align - 1) / align * align;
+}
+
+// Kernel arguments of one backward step (passed by value).
+template <typename R>
+struct StepArgs {
+    R lo[kMaxDim];        // domain lower corner
+    R scale[kMaxDim];     // cells / (hi - lo)
+    R cmax_f[kMaxDim];    // cells - 1
+    uint32_t stride[kMaxDim];
+    uint32_t cells[kMaxDim];
+    int cmax;             // max cells over the dimensions (row length of the cell table)
+    uint32_t K;
+    int M, i, N;
+    uint32_t key0, key1, tag;
+    R dt, sqrt_dt, T, inv_mu;
+    double dt_d, inv_dt;
+    int driver, terminal;
+    R r, kappa, c_logistic, clamp_y, clamp_z;
+    int identity_sigma, has_drift;
+    int lanes;
+    int check_finite;
+    size_t lds_per_cube;
+    uint8_t *face_flags;  // [N*K] near-face marks or nullptr
+    R face_eps;           // in cell widths
+};
+
+struct SetupArgs {
+    double lo[kMaxDim], hi[kMaxDim];
+    int cells[kMaxDim];
+    double b[kMaxDim];
+    double sigma[kMaxDim * kMaxDim];
+    int d, q, cmax;
+    double mu;
+};
+
+struct RootPoint {
+    double x[kMaxDim];
+};
+
+struct LaunchShape {
+    unsigned blocks, threads;
+    size_t lds_bytes;
+};
+
+template <typename R>
+hipError_t launch_setup(const SetupArgs &s, void *cellF, void *bsig, hipStream_t st);
+template <typename R>
+hipError_t launch_step(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                       const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                       hipStream_t st);
+template <typename R>
+hipError_t launch_lookup_rows(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K,
+                              int i_lo, int i_hi, hipStream_t st);
+template <typename R>
+hipError_t launch_root(int d, int basis, int lkmode, const StepArgs<R> &a, const void *bsig,
+                       const void *lk, const RootPoint &x0, int M_root, int nblocks, double *partial,
+                       double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_eval(int d, int basis, const StepArgs<R> &a, const void *table, const double *x,
+                       int64_t n, double *y, double *z, hipStream_t st);
+template <typename R>
+hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
+                       uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
+
+bool dimension_compiled(int d);
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M);
+
+}  // namespace srmdp

@@ -1,0 +1,303 @@
+"""Python binding of libsrmdp.so (include/srmdp.h): argument marshalling only.
+
+Every step of the sweep runs in the library's HIP kernels.  PyTorch provides
+device memory (tensors) and streams; nothing here computes any part of the
+method.  Importing this module fails loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrmdp.so")
+
+OK, E_INVALID, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_NUMERIC = 0, -1, -2, -3, -4, -5
+LP0, LP1 = 0, 1
+FP64, FP32 = 0, 1
+DRV_LINEAR, DRV_LOGISTIC = 0, 1
+G_COS_SUM, G_LOGISTIC = 0, 1
+F_GRAPH, F_CHECK_FINITE = 0x1, 0x2
+MAX_D = 16
+
+
+class SrmdpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"srmdp status {status}: {message}")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("T", ctypes.c_double), ("N", ctypes.c_int32),
+        ("b", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.POINTER(ctypes.c_double)),
+        ("driver", ctypes.c_int32), ("terminal", ctypes.c_int32),
+        ("r", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("clamp_y", ctypes.c_double), ("clamp_z", ctypes.c_double),
+    ]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [
+        ("lo", ctypes.POINTER(ctypes.c_double)), ("hi", ctypes.POINTER(ctypes.c_double)),
+        ("cells", ctypes.POINTER(ctypes.c_int32)), ("mu", ctypes.c_double),
+    ]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int32), ("basis", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+        ("step_hi", ctypes.c_int32), ("step_lo", ctypes.c_int32),
+        ("lanes_per_cube", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("singular_cubes", ctypes.c_uint64), ("path_steps", ctypes.c_uint64),
+        ("ms_total", ctypes.c_float), ("ms_steps", ctypes.c_float),
+        ("step_launches", ctypes.c_int32), ("lanes_per_cube", ctypes.c_int32),
+        ("near_face_paths", ctypes.c_uint64),
+    ]
+
+
+EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_eval",
+           "srmdp_root", "srmdp_draw", "srmdp_release_graphs", "srmdp_last_error",
+           "srmdp_abi_version")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2407_21085_amd.build`")
+    # PyTorch ships its own HIP runtime.  Loading torch first makes the library
+    # bind to that same runtime (same soname), so one process holds one HIP
+    # runtime and the library can work on torch's tensors and streams.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P, G, O, S = (ctypes.POINTER(_Problem), ctypes.POINTER(_Grid), ctypes.POINTER(_Options),
+                  ctypes.POINTER(_Stats))
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    L.srmdp_table_elems.argtypes = [P, G, ctypes.c_int32]
+    L.srmdp_table_elems.restype = ctypes.c_size_t
+    L.srmdp_workspace_bytes.argtypes = [P, G, O]
+    L.srmdp_workspace_bytes.restype = ctypes.c_size_t
+    L.srmdp_solve.argtypes = [P, G, O, vp, vp, ctypes.c_size_t, S, vp]
+    L.srmdp_solve.restype = ctypes.c_int
+    L.srmdp_eval.argtypes = [P, G, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp,
+                             ctypes.c_int64, vp, vp, vp]
+    L.srmdp_eval.restype = ctypes.c_int
+    L.srmdp_root.argtypes = [P, G, O, vp, dp, ctypes.c_int32, dp, dp, vp, ctypes.c_size_t, vp]
+    L.srmdp_root.restype = ctypes.c_int
+    L.srmdp_draw.argtypes = [P, G, O, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                             ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32,
+                             vp, vp]
+    L.srmdp_draw.restype = ctypes.c_int
+    L.srmdp_release_graphs.argtypes = []
+    L.srmdp_release_graphs.restype = None
+    L.srmdp_last_error.argtypes = []
+    L.srmdp_last_error.restype = ctypes.c_char_p
+    L.srmdp_abi_version.argtypes = []
+    L.srmdp_abi_version.restype = ctypes.c_int32
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise SrmdpError(status, lib.srmdp_last_error().decode())
+
+
+def _darr(v: Sequence[float]):
+    return (ctypes.c_double * len(v))(*[float(a) for a in v])
+
+
+@dataclass
+class Problem:
+    """Problem data of eq. (fbsde)-(eds) with constant coefficients."""
+    d: int
+    N: int
+    T: float = 1.0
+    q: Optional[int] = None
+    driver: int = DRV_LINEAR
+    terminal: int = G_COS_SUM
+    r: float = 0.0
+    kappa: float = 0.0
+    clamp_y: float = math.inf
+    clamp_z: float = math.inf
+    b: Optional[Sequence[float]] = None
+    sigma: Optional[Sequence[float]] = None
+    _keep: list = field(default_factory=list, repr=False)
+
+    def c(self) -> _Problem:
+        q = self.d if self.q is None else self.q
+        s = _Problem(self.d, q, self.T, self.N, None, None, self.driver, self.terminal, self.r,
+                     self.kappa, self.clamp_y, self.clamp_z)
+        self._keep = []
+        if self.b is not None:
+            a = _darr(self.b)
+            self._keep.append(a)
+            s.b = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        if self.sigma is not None:
+            a = _darr(self.sigma)
+            self._keep.append(a)
+            s.sigma = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        return s
+
+
+@dataclass
+class Grid:
+    """Equal-size stratification of [lo, hi) with the logistic sampling law."""
+    lo: Sequence[float]
+    hi: Sequence[float]
+    cells: Sequence[int]
+    mu: float = 1.0
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def K(self) -> int:
+        k = 1
+        for c in self.cells:
+            k *= int(c)
+        return k
+
+    def c(self) -> _Grid:
+        lo, hi = _darr(self.lo), _darr(self.hi)
+        cells = (ctypes.c_int32 * len(self.cells))(*[int(c) for c in self.cells])
+        self._keep = [lo, hi, cells]
+        return _Grid(ctypes.cast(lo, ctypes.POINTER(ctypes.c_double)),
+                     ctypes.cast(hi, ctypes.POINTER(ctypes.c_double)),
+                     ctypes.cast(cells, ctypes.POINTER(ctypes.c_int32)), self.mu)
+
+
+@dataclass
+class Options:
+    M: int
+    basis: int = LP1
+    prec: int = FP64
+    seed: int = 1
+    instance: int = 0
+    step_hi: int = -1
+    step_lo: int = -1
+    lanes_per_cube: int = 0
+    flags: int = 0
+    face_flags: object = None   # device uint8 tensor [N, K] or None
+    face_eps: float = 0.0
+
+    def c(self) -> _Options:
+        ptr = self.face_flags.data_ptr() if self.face_flags is not None else None
+        return _Options(self.M, self.basis, self.prec, self.seed, self.instance, self.step_hi,
+                        self.step_lo, self.lanes_per_cube, self.flags, ptr, self.face_eps)
+
+
+def table_elems(problem: Problem, grid: Grid, basis: int) -> int:
+    return int(lib.srmdp_table_elems(problem.c(), grid.c(), basis))
+
+
+def workspace_bytes(problem: Problem, grid: Grid, opts: Options) -> int:
+    n = int(lib.srmdp_workspace_bytes(problem.c(), grid.c(), opts.c()))
+    if n == 0:
+        raise SrmdpError(E_INVALID, lib.srmdp_last_error().decode())
+    return n
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+def table_shape(problem: Problem, grid: Grid, basis: int):
+    nb = problem.d + 1 if basis == LP1 else 1
+    q = problem.d if problem.q is None else problem.q
+    return (problem.N, grid.K, 1 + q, nb)
+
+
+def alloc_table(problem: Problem, grid: Grid, opts: Options, device="cuda"):
+    torch = _torch()
+    dtype = torch.float32 if opts.prec == FP32 else torch.float64
+    return torch.zeros(table_shape(problem, grid, opts.basis), dtype=dtype, device=device)
+
+
+def alloc_workspace(problem: Problem, grid: Grid, opts: Options, device="cuda"):
+    torch = _torch()
+    return torch.empty(workspace_bytes(problem, grid, opts), dtype=torch.uint8, device=device)
+
+
+def solve(problem: Problem, grid: Grid, opts: Options, table=None, workspace=None, stream=None,
+          stats: bool = True):
+    """Algorithm SRMDP (steps opts.step_hi .. opts.step_lo).  Returns
+    (table, stats dict or None)."""
+    if table is None:
+        table = alloc_table(problem, grid, opts)
+    if workspace is None:
+        workspace = alloc_workspace(problem, grid, opts)
+    st = _Stats()
+    rc = lib.srmdp_solve(problem.c(), grid.c(), opts.c(), table.data_ptr(), workspace.data_ptr(),
+                         workspace.numel(), ctypes.byref(st) if stats else None,
+                         _stream_ptr(stream))
+    _check(rc)
+    out = None
+    if stats:
+        out = {"singular_cubes": int(st.singular_cubes), "path_steps": int(st.path_steps),
+               "ms_total": float(st.ms_total), "ms_steps": float(st.ms_steps),
+               "step_launches": int(st.step_launches), "lanes_per_cube": int(st.lanes_per_cube),
+               "near_face_paths": int(st.near_face_paths)}
+    return table, out
+
+
+def evaluate(problem: Problem, grid: Grid, basis: int, prec: int, table, i: int, x, stream=None):
+    """Fitted, truncated y_i and z_i at the rows of x (device float64 [n, d])."""
+    torch = _torch()
+    x = x.to(dtype=torch.float64).contiguous()
+    n = x.shape[0]
+    q = problem.d if problem.q is None else problem.q
+    y = torch.empty(n, dtype=torch.float64, device=x.device)
+    z = torch.empty((n, q), dtype=torch.float64, device=x.device)
+    _check(lib.srmdp_eval(problem.c(), grid.c(), basis, prec, table.data_ptr(), i, x.data_ptr(),
+                          n, y.data_ptr(), z.data_ptr(), _stream_ptr(stream)))
+    return y, z
+
+
+def root(problem: Problem, grid: Grid, opts: Options, table, x0: Sequence[float], M_root: int,
+         workspace=None, stream=None):
+    """ROOT read-out of y(0, x0), z(0, x0) (synchronises the stream)."""
+    if workspace is None:
+        workspace = alloc_workspace(problem, grid, opts, device=table.device)
+    q = problem.d if problem.q is None else problem.q
+    x0a = _darr(x0)
+    y0 = ctypes.c_double(0.0)
+    z0 = (ctypes.c_double * q)()
+    _check(lib.srmdp_root(problem.c(), grid.c(), opts.c(), table.data_ptr(),
+                          ctypes.cast(x0a, ctypes.POINTER(ctypes.c_double)), M_root,
+                          ctypes.byref(y0), ctypes.cast(z0, ctypes.POINTER(ctypes.c_double)),
+                          workspace.data_ptr(), workspace.numel(), _stream_ptr(stream)))
+    return float(y0.value), [float(v) for v in z0]
+
+
+def draw(problem: Problem, grid: Grid, opts: Options, kind: int, i: int, k0: int, nk: int,
+         m0: int, nm: int, count: int, stream=None):
+    """The sweep's random inputs (kind 0 uniforms, 1 normals, 2 start points)."""
+    torch = _torch()
+    out = torch.empty((nk, nm, count), dtype=torch.float64, device="cuda")
+    _check(lib.srmdp_draw(problem.c(), grid.c(), opts.c(), kind, i, k0, nk, m0, nm, count,
+                          out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def release_graphs() -> None:
+    lib.srmdp_release_graphs()

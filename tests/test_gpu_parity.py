@@ -1,0 +1,337 @@
+"""Parity of the HIP library with the FP64 oracle, element by element on the
+same seeded inputs (GPU tests; they call the library through its C ABI).
+
+Metric (per backward step i and component c in {y, z_1..z_q}):
+    max_{k,b} |beta_gpu - beta_oracle| / max_{k,b} |beta_oracle|
+must be <= 1e-9 in FP64 mode and <= 2e-4 in FP32 mode.  A per-coefficient
+relative error is meaningless for slope coefficients near zero.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from sides import oracle_problem, product_args
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 2e-4}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch
+
+
+def gpu_table(cfg, **kw):
+    import paper_2407_21085_amd as S
+    P, G, Opt = product_args(cfg, **kw)
+    _say(f"[gpu] solve {cfg['name']} {kw}")
+    table, stats = S.solve(P, G, Opt)
+    _torch().cuda.synchronize()
+    return table.double().cpu().numpy(), stats
+
+
+def oracle_table(cfg, i_hi=None, i_lo=0, **kw):
+    P = oracle_problem(cfg, **kw)
+    tab, sing = O.solve(P, i_hi=i_hi, i_lo=i_lo)
+    return tab, sing
+
+
+def parity(gpu, orc, rows):
+    worst = 0.0
+    for i in rows:
+        for c in range(orc.shape[2]):
+            ref = np.max(np.abs(orc[i, :, c, :]))
+            err = np.max(np.abs(gpu[i, :, c, :] - orc[i, :, c, :]))
+            worst = max(worst, err / ref if ref > 0 else err)
+    return worst
+
+
+# ------------------------------------------------------------------ inputs
+
+def test_uniform_stream_bit_exact():
+    import paper_2407_21085_amd as S
+    cfg = W.config("cfg2")
+    for prec in ("fp64", "fp32"):
+        P, G, Opt = product_args(cfg, prec=prec, instance=7)
+        _say(f"[gpu] draw uniforms {prec}")
+        out = S.draw(P, G, Opt, 0, 13, 4000, 3, 5, 4, 40).cpu().numpy()
+        for a in range(3):
+            for c in range(4):
+                ref = O.path_uniforms(cfg["seed"], 7, 13, 4000 + a, 5 + c, 40)
+                np.testing.assert_array_equal(out[a, c], ref)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 8])
+def test_normals_and_starts_match_oracle(d):
+    import paper_2407_21085_amd as S
+    cfg = dict(W.config("cfg2"), d=d, lo=[-3.0] * d, hi=[3.0] * d, cells=[3] * d)
+    Po = oracle_problem(cfg)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        P, G, Opt = product_args(cfg, prec=prec)
+        _say(f"[gpu] draw normals/starts d={d} {prec}")
+        nrm = S.draw(P, G, Opt, 1, 4, 1, 2, 0, 3, 3 * d + 1).cpu().numpy()
+        st = S.draw(P, G, Opt, 2, 4, 1, 2, 0, 3, d).cpu().numpy()
+        for a in range(2):
+            for m in range(3):
+                ref = O.path_normals(Po, 4, 1 + a, m, 3 * d + 1)
+                np.testing.assert_allclose(nrm[a, m], ref, rtol=tol, atol=tol)
+                x = O.start_point(Po, 4, 1 + a, m)
+                np.testing.assert_allclose(st[a, m], x, rtol=tol, atol=tol)
+
+
+# ------------------------------------------------------------------ sweeps
+
+def test_cfg1_fp64_full_sweep_parity():
+    cfg = W.config("cfg1")
+    orc, _ = oracle_table(cfg)
+    gpu, stats = gpu_table(cfg)
+    assert stats["singular_cubes"] == 0
+    assert parity(gpu, orc, range(cfg["N"])) <= TOL["fp64"]
+
+
+def parity_unflagged(gpu, orc, rows, flags):
+    """Parity over the strata whose simulations made no near-face look-up on
+    either side (flags[i, k] == 0), and the worst error on the flagged ones."""
+    worst, worst_flagged, where = 0.0, 0.0, None
+    for i in rows:
+        keep = flags[i] == 0
+        for c in range(orc.shape[2]):
+            ref = np.max(np.abs(orc[i, :, c, :]))
+            diff = np.max(np.abs(gpu[i, :, c, :] - orc[i, :, c, :]), axis=1) / ref
+            if float(np.max(diff[keep])) > worst:
+                worst = float(np.max(diff[keep]))
+                where = (i, c, int(np.flatnonzero(keep)[np.argmax(diff[keep])]))
+            if (~keep).any():
+                worst_flagged = max(worst_flagged, float(np.max(diff[~keep])))
+    _say(f"[gpu] worst unflagged (step, component, stratum) = {where}")
+    return worst, worst_flagged
+
+
+def _oracle_with_flags(cfg, i_hi, i_lo, eps):
+    K = int(np.prod(cfg["cells"]))
+    f_orc = np.zeros((cfg["N"], K), dtype=np.uint8)
+    P = oracle_problem(cfg, face_flags=f_orc, face_eps=eps)
+    orc, _ = O.solve(P, i_hi=i_hi, i_lo=i_lo)
+    return orc, f_orc
+
+
+def fp32_step_parity(cfg, steps, eps=2e-6):
+    """Backward step i of the FP32 library against the oracle's step i, with
+    both starting from the oracle's (binary64) fits of rows > i -- the library
+    resumes from them -- so that each step is compared on its own.
+
+    A binary32 path position can sit on the other side of a cell face than the
+    binary64 one when both lie within a few ulps of it; the cell index is an
+    integer decided by floating point, so the strata whose simulations looked
+    up a row at such a point (on either side) are compared separately, and
+    their share must stay small."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    K = int(np.prod(cfg["cells"]))
+    orc, f_orc = _oracle_with_flags(cfg, cfg["N"] - 1, min(steps), eps)
+    worst, worst_flagged, shares = 0.0, 0.0, []
+    for i in steps:
+        table = torch.from_numpy(orc).to(torch.float32).cuda()
+        f_gpu = torch.zeros((cfg["N"], K), dtype=torch.uint8, device="cuda")
+        Pp, G, Opt = product_args(cfg, step_hi=i, step_lo=i)
+        Opt.face_flags, Opt.face_eps = f_gpu, eps
+        _say(f"[gpu] {cfg['name']}: step {i} from the oracle's rows > {i}")
+        S.solve(Pp, G, Opt, table=table)
+        torch.cuda.synchronize()
+        flags = f_orc | f_gpu.cpu().numpy()
+        e, ef = parity_unflagged(table.double().cpu().numpy(), orc, [i], flags)
+        worst, worst_flagged = max(worst, e), max(worst_flagged, ef)
+        shares.append(float(flags[i].mean()))
+    _say(f"[gpu] {cfg['name']}: per-step parity {worst:.3e} on unflagged strata, flagged share "
+         f"<= {max(shares):.4f} (worst there {worst_flagged:.3e})")
+    return worst, worst_flagged, max(shares)
+
+
+def rms_parity(gpu, orc, rows):
+    """max over (step, component) of RMS_k,b |beta_gpu - beta_orc| / RMS_k,b |beta_orc|."""
+    worst = 0.0
+    for i in rows:
+        for c in range(orc.shape[2]):
+            num = np.sqrt(np.mean((gpu[i, :, c, :] - orc[i, :, c, :]) ** 2))
+            den = np.sqrt(np.mean(orc[i, :, c, :] ** 2))
+            worst = max(worst, num / den)
+    return worst
+
+
+def test_cfg2_fp32_per_step_parity():
+    cfg = W.config("cfg2")
+    err, err_flagged, share = fp32_step_parity(cfg, [19, 18, 10, 3, 0])
+    assert err <= TOL["fp32"]
+    assert share < 0.03
+    assert err_flagged < 0.05
+
+
+def test_cfg2_fp32_full_sweep_rms_parity():
+    """The whole FP32 sweep against the whole FP64 oracle sweep: face flips at
+    one step feed the next steps' responses, so the full-sweep comparison is
+    norm-wise (RMS over strata and basis functions, per step and component)."""
+    cfg = W.config("cfg2")
+    orc, _ = oracle_table(cfg)
+    gpu, _ = gpu_table(cfg)
+    err = rms_parity(gpu, orc, range(cfg["N"]))
+    _say(f"[gpu] cfg2 fp32 full sweep RMS parity {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+def test_cfg2_fp64_parity_last_steps():
+    cfg = W.config("cfg2", prec="fp64")
+    orc, _ = oracle_table(cfg, i_hi=19, i_lo=15)
+    gpu, _ = gpu_table(cfg, step_hi=19, step_lo=15)
+    assert parity(gpu, orc, range(15, 20)) <= TOL["fp64"]
+
+
+CASES = [
+    # (name, overrides) -- small sweeps spanning several workgroups and ragged tails
+    ("lp0 d=2 fp64", dict(d=2, N=6, lo=[-2.0, -2.0], hi=[2.0, 2.0], cells=[5, 3], M=37, basis="LP0",
+                          prec="fp64", driver="linear", r=0.3, kappa=0.2, terminal="cos")),
+    ("lp0 d=2 fp32", dict(d=2, N=6, lo=[-2.0, -2.0], hi=[2.0, 2.0], cells=[5, 3], M=37, basis="LP0",
+                          prec="fp32", driver="linear", r=0.3, kappa=0.2, terminal="cos")),
+    ("lp1 d=3 clamps fp64", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 4, 2], M=70,
+                                 basis="LP1", prec="fp64", driver="logistic", terminal="logistic",
+                                 clamp_y=0.7, clamp_z=0.2)),
+    ("lp1 d=3 clamps fp32", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 4, 2], M=70,
+                                 basis="LP1", prec="fp32", driver="logistic", terminal="logistic",
+                                 clamp_y=0.7, clamp_z=0.2)),
+    ("lp1 d=5 drift sigma fp64", dict(d=5, N=4, lo=[-2.0] * 5, hi=[2.0] * 5, cells=[2] * 5, M=24,
+                                      basis="LP1", prec="fp64", driver="linear", r=0.1, kappa=0.5,
+                                      terminal="cos", b=[0.1, -0.2, 0.0, 0.3, 0.05],
+                                      sigma=list((0.8 * np.eye(5) + 0.05).ravel()))),
+    ("lp1 d=6 M=d+1 fp64", dict(d=6, N=3, lo=[-1.5] * 6, hi=[1.5] * 6, cells=[2] * 6, M=7,
+                                basis="LP1", prec="fp64", driver="logistic", terminal="logistic")),
+    ("lp1 d=1 N=1 fp64", dict(d=1, N=1, lo=[-3.0], hi=[3.0], cells=[7], M=300, basis="LP1",
+                              prec="fp64", driver="linear", r=1.0, kappa=1.0, terminal="cos")),
+    ("lp1 d=2 K=1 fp32", dict(d=2, N=8, lo=[-1.0, -1.0], hi=[1.0, 1.0], cells=[1, 1], M=1000,
+                              basis="LP1", prec="fp32", driver="linear", r=0.2, terminal="cos")),
+    ("lp1 d=8 fp32", dict(d=8, N=4, lo=[-3.0] * 8, hi=[3.0] * 8, cells=[2] * 8, M=64, basis="LP1",
+                          prec="fp32", driver="logistic", terminal="logistic")),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_small_sweeps_parity(name, kw):
+    cfg = dict(W.config("cfg1"), name=name, seed=11, x0=[0.0] * kw["d"], **kw)
+    orc, sing = oracle_table(cfg)
+    gpu, stats = gpu_table(cfg)
+    assert stats["singular_cubes"] == sing
+    err = parity(gpu, orc, range(cfg["N"]))
+    _say(f"[gpu] {name}: parity {err:.3e}")
+    assert err <= TOL[cfg["prec"]]
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64, 128, 256])
+def test_results_independent_of_lanes_per_cube(lanes):
+    cfg = dict(W.config("cfg1"), M=100, N=5)
+    ref, _ = gpu_table(cfg, lanes=64)
+    got, _ = gpu_table(cfg, lanes=lanes)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_resume_is_bit_identical():
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = W.config("cfg1")
+    full, _ = gpu_table(cfg)
+    P, G, Opt = product_args(cfg, step_hi=9, step_lo=6)
+    _say("[gpu] resume: steps 9..6 then 5..0 with a fresh workspace")
+    table, _ = S.solve(P, G, Opt)
+    P, G, Opt = product_args(cfg, step_hi=5, step_lo=0)
+    table, _ = S.solve(P, G, Opt, table=table)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(table.cpu().numpy(), full)
+
+
+def test_graph_replay_matches_direct_launches():
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = W.config("cfg2", N=6)
+    ref, _ = gpu_table(cfg)
+    P, G, Opt = product_args(cfg, flags=S.F_GRAPH)
+    stream = torch.cuda.Stream()
+    table = S.srmdp.alloc_table(P, G, Opt)
+    ws = S.srmdp.alloc_workspace(P, G, Opt)
+    for rep in range(3):
+        _say(f"[gpu] graph replay {rep}")
+        table.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            S.solve(P, G, Opt, table=table, workspace=ws, stream=stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(table.double().cpu().numpy(), ref)
+    S.release_graphs()
+
+
+# ------------------------------------------------------------------ read-outs
+
+def test_eval_matches_oracle():
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = dict(W.config("cfg1"), clamp_y=0.8, clamp_z=0.5)
+    orc, _ = oracle_table(cfg)
+    P, G, Opt = product_args(cfg)
+    _say("[gpu] eval")
+    table = torch.from_numpy(orc).cuda()
+    x = np.linspace(-6, 6, 777)[:, None]
+    for i in (0, 4, 9):
+        y, z = S.evaluate(P, G, S.LP1, S.FP64, table, i, torch.from_numpy(x).cuda())
+        yo, zo = O.evaluate(oracle_problem(cfg), orc, i, x)
+        np.testing.assert_allclose(y.cpu().numpy(), yo, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_root_readout_matches_oracle(name):
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = W.config(name, prec="fp64", N=6) if name == "cfg2" else W.config(name)
+    orc, _ = oracle_table(cfg)
+    P, G, Opt = product_args(cfg)
+    table = torch.from_numpy(orc).cuda()
+    _say(f"[gpu] root {name}")
+    y0, z0 = S.root(P, G, Opt, table, cfg["x0"], 20000)
+    yo, zo = O.root(oracle_problem(cfg), orc, cfg["x0"], 20000)
+    assert y0 == pytest.approx(yo, rel=1e-9)
+    np.testing.assert_allclose(z0, zo, rtol=1e-8, atol=1e-10)
+
+
+# ------------------------------------------------------------ full size
+
+def test_cfg5_full_size_last_steps_parity():
+    """The headline size (K = 65536, M = 64, d = 8) in the benchmark's launch
+    configuration: the first three backward steps, each against the oracle."""
+    cfg = W.config("cfg5")
+    err, err_flagged, share = fp32_step_parity(cfg, [49, 48, 47])
+    assert err <= TOL["fp32"]
+    assert share < 0.03
+    assert err_flagged < 0.05
+
+
+def test_cfg5_full_sweep_properties():
+    """Whole sweep at the headline size: finite coefficients, no singular
+    strata, and the ROOT read-out within the scheme's error of the continuous
+    solution y(0, 0) = 1/2 (O(dt) time bias and basis feedback included)."""
+    import paper_2407_21085_amd as S
+    cfg = W.config("cfg5")
+    P, G, Opt = product_args(cfg, flags=S.F_CHECK_FINITE)
+    _say("[gpu] cfg5 full sweep")
+    table, stats = S.solve(P, G, Opt)
+    assert stats["singular_cubes"] == 0
+    y0, z0 = S.root(P, G, Opt, table, cfg["x0"], 1 << 20)
+    _say(f"[gpu] cfg5 root y0={y0:.5f} z0={np.round(z0, 4)}")
+    assert abs(y0 - 0.5) < 0.05
+    assert np.all(np.abs(np.asarray(z0) - 0.25) < 0.1)
