@@ -93,7 +93,7 @@ typedef struct {
  * only the K = prod(cells) bounded cells are sampled. */
 typedef struct {
     const double *lo, *hi;   /* host [d], lo < hi */
-    const int32_t *cells;    /* host [d], >= 1; K = prod(cells) <= 2^31 - 1 */
+    const int32_t *cells;    /* host [d], >= 1; K = prod(cells) <= 2^24 */
     double mu;               /* logistic parameter > 0 */
 } srmdp_grid;
 

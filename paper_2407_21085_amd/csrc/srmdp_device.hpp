@@ -36,32 +36,55 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, Key key)
     return c;
 }
 
-// Open uniform on (0,1): odd multiple of 2^-24 built from the top 23 bits.
-// Exact in binary32, so both precisions see the same real number.
+// Open uniform on (0,1): (2 (w >> 9) + 1) 2^-24, an odd multiple of 2^-24 built
+// from the top 23 bits.  Exact in binary32, so both precisions see the same
+// real number.  binary32: the bits (w >> 9) | 0x3F800000 are 1 + (w >> 9) 2^-23,
+// and subtracting 1 - 2^-24 is exact.
 template <typename R>
-__device__ __forceinline__ R open_uniform(uint32_t w)
+__device__ __forceinline__ R open_uniform(uint32_t w);
+
+template <>
+__device__ __forceinline__ float open_uniform<float>(uint32_t w)
 {
-    return (R)(((w >> 9) << 1) | 1u) * (R)5.9604644775390625e-8;  // 2^-24
+    return __uint_as_float((w >> 9) | 0x3F800000u) - 0.99999994039535522461f;  // 1 - 2^-24
 }
 
-// Box-Muller (1958): (rho cos(2 pi u2), rho sin(2 pi u2)), rho = sqrt(-2 ln u1).
-__device__ __forceinline__ void box_muller(float u1, float u2, float &n0, float &n1)
+template <>
+__device__ __forceinline__ double open_uniform<double>(uint32_t w)
 {
-    const float rho = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    n0 = rho * c;
-    n1 = rho * s;
+    return (double)(((w >> 9) << 1) | 1u) * 5.9604644775390625e-8;  // 2^-24
 }
 
-__device__ __forceinline__ void box_muller(double u1, double u2, double &n0, double &n1)
+// Box-Muller (1958): scale * (rho cos(2 pi u2), rho sin(2 pi u2)),
+// rho = sqrt(-2 ln u1).  binary32 uses the hardware transcendentals: v_log_f32
+// (log2; -2 ln u1 = -2 ln(2) log2 u1, with scale^2 folded into the constant),
+// v_sqrt_f32 and v_sin_f32 / v_cos_f32, which take their argument in
+// revolutions, so sin(2 pi u2) is v_sin_f32(u2).  binary64 uses the libm
+// functions.
+__device__ __forceinline__ void box_muller(float u1, float u2, float neg2ln2_s2, float &n0,
+                                           float &n1)
 {
-    const double rho = sqrt(-2.0 * log(u1));
+    const float rho = __builtin_amdgcn_sqrtf(neg2ln2_s2 * __builtin_amdgcn_logf(u1));
+    n0 = rho * __builtin_amdgcn_cosf(u2);
+    n1 = rho * __builtin_amdgcn_sinf(u2);
+}
+
+__device__ __forceinline__ void box_muller(double u1, double u2, double scale, double &n0,
+                                           double &n1)
+{
+    const double rho = scale * sqrt(-2.0 * log(u1));
     double s, c;
     sincospi(2.0 * u2, &s, &c);
     n0 = rho * c;
     n1 = rho * s;
 }
+
+// Constant handed to box_muller for increments of standard deviation `scale`.
+__device__ __forceinline__ float box_muller_constant(float scale)
+{
+    return -2.0f * 0.69314718055994530942f * scale * scale;
+}
+__device__ __forceinline__ double box_muller_constant(double scale) { return scale; }
 
 // The Gaussian increments of one simulation.  Normal n of the simulation
 // (n = step_offset * D + l) is the cosine (n even) or sine (n odd) branch of the
@@ -71,13 +94,16 @@ template <typename R, int D>
 struct NormalStream {
     uint4 ctr;  // x = block, y = m, z = k, w = tag
     Key key;
+    R bm;       // box_muller_constant(scale)
     R buf[4];
     uint32_t buf_block;  // block held in buf (0 = none: block 0 is a start block)
 
-    __device__ __forceinline__ void init(Key k, uint32_t m, uint32_t cube, uint32_t tag)
+    // Normals of standard deviation `scale` (sqrt(dt) gives the increments dW).
+    __device__ __forceinline__ void init(Key k, uint32_t m, uint32_t cube, uint32_t tag, R scale)
     {
         key = k;
         ctr = make_uint4(0u, m, cube, tag);
+        bm = box_muller_constant(scale);
         buf_block = 0u;
     }
 
@@ -85,12 +111,12 @@ struct NormalStream {
     {
         ctr.x = blk;
         const uint4 w = philox4x32_10(ctr, key);
-        box_muller(open_uniform<R>(w.x), open_uniform<R>(w.y), buf[0], buf[1]);
-        box_muller(open_uniform<R>(w.z), open_uniform<R>(w.w), buf[2], buf[3]);
+        box_muller(open_uniform<R>(w.x), open_uniform<R>(w.y), bm, buf[0], buf[1]);
+        box_muller(open_uniform<R>(w.z), open_uniform<R>(w.w), bm, buf[2], buf[3]);
         buf_block = blk;
     }
 
-    // D standard normals of step offset s = j - i (s is uniform over the wave).
+    // D normals of step offset s = j - i (s is uniform over the wave).
     __device__ __forceinline__ void step(uint32_t s, R *out)
     {
         constexpr uint32_t B0 = (D + 3) / 4;
@@ -135,12 +161,12 @@ __device__ __forceinline__ uint32_t stream_word(Key key, uint32_t m, uint32_t cu
 // ------------------------------------------------------------ problem data
 
 // Per-dimension constants of one cell [x-, x+) for the restricted logistic
-// sampler, F(x) = 1/(1+exp(-mu x)), c the cell centre:
-//   delta = F(x+) - F(x-), uc = (F(c) - F(x-)) / delta (the uniform that maps
-//   to c), rp = delta / F(c), rs = delta / (1 - F(c)).
+// sampler, F(x) = 1/(1+exp(-mu x)), c the cell centre, delta = F(x+) - F(x-):
+//   uc = (F(c) - F(x-)) / delta (the uniform that maps to c),
+//   rp = delta / F(c), rs = delta / (1 - F(c)).
 template <typename R>
-struct CellF {
-    R delta, uc, rp, rs, centre, two_over_h, pad0, pad1;
+struct alignas(4 * sizeof(R)) CellF {
+    R uc, rp, rs, centre;
 };
 
 // Algorithm "stratify": x = F^{-1}(p), p = F(x-) + u (F(x+) - F(x-)).  With

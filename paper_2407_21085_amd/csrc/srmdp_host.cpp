@@ -84,7 +84,7 @@ srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s
             return fail(SRMDP_E_INVALID, "grid dimension %d: need finite lo < hi", l);
         if (g->cells[l] < 1) return fail(SRMDP_E_INVALID, "grid dimension %d: cells < 1", l);
         s.K *= (uint64_t)g->cells[l];
-        if (s.K > 0x7FFFFFFFull) return fail(SRMDP_E_INVALID, "K exceeds 2^31 - 1 strata");
+        if (s.K > (1ull << 24)) return fail(SRMDP_E_INVALID, "K exceeds 2^24 strata");
         s.cmax = std::max(s.cmax, (int)g->cells[l]);
     }
     if (p->b)
@@ -142,7 +142,7 @@ Layout layout(const Shape &s, int nb, int is_float, int lk)
     L.counters = off;
     off = align_up(off + kCounterCount * sizeof(unsigned long long), 256);
     L.cellF = off;
-    off = align_up(off + (size_t)s.d * s.cmax * 8 * rsz, 256);
+    off = align_up(off + (size_t)s.d * s.cmax * 4 * rsz, 256);
     L.bsig = off;
     off = align_up(off + (size_t)(s.d + s.d * s.q) * rsz, 256);
     L.root_partial = off;
@@ -167,6 +167,7 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
         a.scale[l] = (R)((double)g->cells[l] / (g->hi[l] - g->lo[l]));
         a.cmax_f[l] = (R)(g->cells[l] - 1);
         a.stride[l] = stride;
+        a.stride_f[l] = (R)stride;
         a.cells[l] = (uint32_t)g->cells[l];
         stride *= (uint32_t)g->cells[l];
     }
@@ -224,8 +225,7 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
     sa.mu = g->mu;
 }
 
-// Lanes per stratum: enough to give every lane one path up to a wavefront;
-// several strata share a 256-lane workgroup when M is small.
+// Lanes per stratum: enough to give every lane one path up to a wavefront.
 int auto_lanes(int M)
 {
     int L = 8;
@@ -233,10 +233,15 @@ int auto_lanes(int M)
     return L;
 }
 
+// One wavefront per workgroup when a stratum fits in one (several strata share
+// it when M is small): the regression's barriers are then wave-local, and the
+// wavefronts of a CU drift apart, so one wave's latency-bound regression
+// overlaps other waves' path arithmetic instead of the whole CU stalling at
+// the same barrier.
 bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube)
 {
     per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M), 16);
-    int cpw = std::max(1, 256 / L);
+    int cpw = std::max(1, 64 / L);
     const size_t lds_cap = 64 * 1024;
     while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;
     if ((size_t)cpw * per_cube > lds_cap) return false;
@@ -408,6 +413,7 @@ srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
     fill_step_args<R>(a, p, g, s, o);
     a.i = 0;
     a.tag = (o->instance << 16);
+    a.face_flags = nullptr;
     SetupArgs sa;
     fill_setup_args(sa, p, g, s);
     RootPoint rp{};

@@ -39,6 +39,7 @@ struct StepArgs {
     R lo[kMaxDim];        // domain lower corner
     R scale[kMaxDim];     // cells / (hi - lo)
     R cmax_f[kMaxDim];    // cells - 1
+    R stride_f[kMaxDim];  // stride of the stratum index (exact: K <= 2^24)
     uint32_t stride[kMaxDim];
     uint32_t cells[kMaxDim];
     int cmax;             // max cells over the dimensions (row length of the cell table)

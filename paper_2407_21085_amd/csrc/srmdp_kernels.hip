@@ -31,12 +31,10 @@ __device__ __forceinline__ CellF<R> cell_constants(const SetupArgs &a, int l, in
     // F differences from the side where F (or 1 - F) is small, to avoid cancellation
     const double delta = xm >= 0.0 ? G_m - G_p : F_p - F_m;
     const double to_c = xm >= 0.0 ? G_m - G_c : F_c - F_m;
-    v.delta = (R)delta;
     v.uc = (R)(to_c / delta);
     v.rp = (R)(delta / F_c);
     v.rs = (R)(delta / G_c);
     v.centre = (R)xc;
-    v.two_over_h = (R)(2.0 / h);
     return v;
 }
 
@@ -123,24 +121,39 @@ __device__ __forceinline__ bool near_interior_face(R t, R c, R cmax, R eps)
     return (frac < eps && c > (R)0 && t >= (R)0) || (frac > (R)1 - eps && c < cmax);
 }
 
+template <typename R, int D>
+__device__ __forceinline__ bool near_face(const StepArgs<R> &a, const R *x)
+{
+    bool near = false;
+    for (int l = 0; l < D; ++l) {
+        const R t = (x[l] - a.lo[l]) * a.scale[l];
+        near |= near_interior_face<R>(t, RealOps<R>::clamp_cell(t, a.cmax_f[l]), a.cmax_f[l],
+                                      a.face_eps);
+    }
+    return near;
+}
+
+// Fitted y_j(x) and sum_l z_{j,l}(x) from look-up row j (`row` points at it).
+// Cell of x per dimension: floor((x - lo) cells / (hi - lo)) clamped to the
+// grid; xi = 2 (t - cell) - 1.  The stratum index is accumulated in the working
+// precision, exact because K <= 2^24.
 template <typename R, int D, int NB, int LK>
-__device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__restrict__ lk, int j,
-                                            const R *x, R &y, R &zsum, bool &near)
+__device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__restrict__ row, const R *x,
+                                            R &y, R &zsum)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     R xi[D];
-    uint32_t k = 0;
+    R kf = (R)0;
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         const R t = (x[l] - a.lo[l]) * a.scale[l];
         // fmax/fmin also map NaN and +-inf into [0, cells-1]
         const R c = RealOps<R>::clamp_cell(t, a.cmax_f[l]);
         xi[l] = (R)2 * (t - c) - (R)1;
-        k += (uint32_t)c * a.stride[l];
-        if (a.face_flags) near |= near_interior_face<R>(t, c, a.cmax_f[l], a.face_eps);
+        kf = c * a.stride_f[l] + kf;
     }
     R rec[W];
-    load_record<R, W>(lk + ((size_t)j * a.K + k) * W, rec);
+    load_record<R, W>(row + (uint32_t)kf * (uint32_t)W, rec);
     R yv = rec[0];
     if constexpr (NB > 1) {
 #pragma unroll
@@ -171,10 +184,100 @@ __device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__res
     }
 }
 
-// One simulation of stratum k from step i (eq. (PsiM)): draws X_i ~ nu_k, runs
-// the Euler scheme to X_N and returns phi(X_i), dW_i, the tail response
-// S' = g(X_N) + sum_{j=i+1}^{N-1} f_j(X_j, y_{j+1}(X_{j+1}), z_j(X_j)) dt and
-// y_{i+1}(X_{i+1}) (g(X_N) when i + 1 = N).
+// X_{j+1} = X_j + b dt + sigma dW_j (Algorithm "Euler dynamics", read with the
+// time index of the current step; exact for the constant coefficients here).
+template <typename R, int D>
+__device__ __forceinline__ void euler_step(const StepArgs<R> &a, const R *__restrict__ bsig,
+                                           const R *x, const R *dW, R *xn)
+{
+    if (a.identity_sigma) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) xn[l] = x[l] + dW[l];
+    } else {
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            R acc = x[l];
+#pragma unroll
+            for (int c = 0; c < D; ++c) acc += bsig[D + l * D + c] * dW[c];
+            xn[l] = acc;
+        }
+    }
+    if (a.has_drift) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) xn[l] += bsig[l] * a.dt;
+    }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ R terminal_at(const StepArgs<R> &a, const R *x)
+{
+    R s = (R)0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) s += x[l];
+    return terminal_g<R>(a.terminal, a.T, s);
+}
+
+// One simulation from X_i = x (eq. (PsiM)): the Euler scheme to X_N with the
+// fitted rows i+1..N-1, returning dW_i, y_{i+1}(X_{i+1}) (g(X_N) when
+// i + 1 = N) and the tail response
+//   S' = g(X_N) + sum_{j=i+1}^{N-1} f_j(X_j, y_{j+1}(X_{j+1}), z_j(X_j)) dt.
+// The first and last steps are peeled off so that the steady loop has no
+// branch that depends on j.
+template <typename R, int D, int NB, int LK>
+__device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
+                                         const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
+                                         R *dWi_out, R &y1, R &Sp, bool &near)
+{
+    constexpr int W = LookupWidth<R, D, NB, LK>::value;
+    const int i = a.i, N = a.N;
+    const size_t row_elems = (size_t)a.K * W;
+    const R dt = a.dt;
+    R dW[D], xn[D];
+
+    ns.step(0u, dW);
+    euler_step<R, D>(a, bsig, x, dW, xn);
+    R zsum_cur = (R)0;
+    if (i + 1 < N) {
+        lookup_eval<R, D, NB, LK>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
+        if (a.face_flags) near |= near_face<R, D>(a, xn);
+    } else {
+        y1 = terminal_at<R, D>(a, xn);
+    }
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        dWi_out[l] = dW[l];
+        x[l] = xn[l];
+    }
+
+    R S = (R)0;
+    for (int j = i + 1; j < N - 1; ++j) {
+        ns.step((uint32_t)(j - i), dW);
+        euler_step<R, D>(a, bsig, x, dW, xn);
+        R yn, zn;
+        lookup_eval<R, D, NB, LK>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
+        if (a.face_flags) near |= near_face<R, D>(a, xn);
+        S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+        zsum_cur = zn;
+#pragma unroll
+        for (int l = 0; l < D; ++l) x[l] = xn[l];
+    }
+
+    R gN;
+    if (i < N - 1) {
+        ns.step((uint32_t)(N - 1 - i), dW);
+        euler_step<R, D>(a, bsig, x, dW, xn);
+        gN = terminal_at<R, D>(a, xn);
+        S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, gN, zsum_cur) * dt;
+    } else {
+        gN = y1;  // i = N-1: the first step already reached X_N
+    }
+    Sp = gN + S;
+}
+
+// One simulation of stratum k from step i: X_i ~ nu_k by Algorithm
+// "stratify" (phi(X_i) to full precision from the centred offset), then
+// run_path.  phi(X_i) and dW_i go to the stratum's LDS row as soon as they are
+// known, so they do not occupy registers during the path.
 template <typename R, int D, int NB, int LK>
 __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
@@ -183,7 +286,6 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
 {
     const Key key{a.key0, a.key1};
     R x[D];
-    // start point, Algorithm "stratify"
 #pragma unroll
     for (int b = 0; b < (D + 3) / 4; ++b) {
         const uint4 w = philox4x32_10(make_uint4((uint32_t)b, m, k, a.tag), key);
@@ -196,112 +298,26 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
                 const CellF<R> cf = cellF[l * a.cmax + cell];
                 const R off = stratified_offset<R>(cf, open_uniform<R>(ws[t]), a.inv_mu);
                 x[l] = cf.centre + off;
-                if constexpr (NB > 1) phi_out[1 + l] = off * cf.two_over_h;
+                // xi = 2 (x - c) / h, and 1/h = scale
+                if constexpr (NB > 1) phi_out[1 + l] = (off + off) * a.scale[l];
             }
         }
     }
     phi_out[0] = (R)1;
-
     NormalStream<R, D> ns;
-    ns.init(key, m, k, a.tag);
-    R S = (R)0, zsum_cur = (R)0;
-    const R dt = a.dt;
-    for (int j = a.i; j < a.N; ++j) {
-        R dW[D];
-        ns.step((uint32_t)(j - a.i), dW);
-#pragma unroll
-        for (int l = 0; l < D; ++l) dW[l] *= a.sqrt_dt;
-        R xn[D];
-        if (a.identity_sigma) {
-#pragma unroll
-            for (int l = 0; l < D; ++l) xn[l] = x[l] + dW[l];
-        } else {
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-                R acc = x[l];
-#pragma unroll
-                for (int c = 0; c < D; ++c) acc += bsig[D + l * D + c] * dW[c];
-                xn[l] = acc;
-            }
-        }
-        if (a.has_drift) {
-#pragma unroll
-            for (int l = 0; l < D; ++l) xn[l] += bsig[l] * dt;
-        }
-        R ynext, znext = (R)0;
-        if (j + 1 < a.N) {
-            lookup_eval<R, D, NB, LK>(a, lk, j + 1, xn, ynext, znext, near);
-        } else {
-            R s = (R)0;
-#pragma unroll
-            for (int l = 0; l < D; ++l) s += xn[l];
-            ynext = terminal_g<R>(a.terminal, a.T, s);
-        }
-        if (j == a.i) {
-#pragma unroll
-            for (int l = 0; l < D; ++l) dWi_out[l] = dW[l];
-            y1 = ynext;
-        } else {
-            S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, ynext, zsum_cur) * dt;
-        }
-        zsum_cur = znext;
-#pragma unroll
-        for (int l = 0; l < D; ++l) x[l] = xn[l];
-    }
-    R s = (R)0;
-#pragma unroll
-    for (int l = 0; l < D; ++l) s += x[l];
-    Sp = terminal_g<R>(a.terminal, a.T, s) + S;
-}
-
-// Serial Cholesky of the NB x NB Gram matrix in LDS (binary64, lower factor
-// written over G).  Returns false when a pivot is <= tol.
-template <int NB>
-__device__ __forceinline__ bool cholesky_lds(double *G, double tol)
-{
-    for (int r = 0; r < NB; ++r) {
-        for (int c = 0; c <= r; ++c) {
-            double s = G[r * NB + c];
-            for (int t = 0; t < c; ++t) s -= G[r * NB + t] * G[c * NB + t];
-            if (r == c) {
-                if (!(s > tol)) return false;
-                G[r * NB + r] = sqrt(s);
-            } else {
-                G[r * NB + c] = s / G[c * NB + c];
-            }
-        }
-    }
-    return true;
-}
-
-template <int NB>
-__device__ __forceinline__ void chol_solve_lds(const double *L, const double *rhs, double *out)
-{
-    double w[NB];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        double s = rhs[r];
-#pragma unroll
-        for (int t = 0; t < r; ++t) s -= L[r * NB + t] * w[t];
-        w[r] = s / L[r * NB + r];
-    }
-#pragma unroll
-    for (int r = NB - 1; r >= 0; --r) {
-        double s = w[r];
-#pragma unroll
-        for (int t = r + 1; t < NB; ++t) s -= L[t * NB + r] * out[t];
-        out[r] = s / L[r * NB + r];
-    }
+    ns.init(key, m, k, a.tag, a.sqrt_dt);
+    run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dWi_out, y1, Sp, near);
 }
 
 // LDS layout of one stratum: path rows [M][SW] in the working precision
 // (phi: NB, dW_i: D, S': 1, y1: 1), then the binary64 block
-// G[NB*NB] | RHS[(1+D)*NB] (y first, then z_1..z_D) | beta[(1+D)*NB] | flag[2]
+// G[NB*NB] | H[NB*NB] (the two buffers of the in-place inversion)
+// | RHS[(1+D)*NB] (y first, then z_1..z_D) | beta[(1+D)*NB] | flag[2]
 // | zsum[NB] (sum over l of the z_l coefficients).
 template <typename R, int D, int NB>
 struct CubeLds {
     static constexpr int SW = NB + D + 2;
-    static constexpr int F64 = NB * NB + 2 * (1 + D) * NB + 2 + NB;
+    static constexpr int F64 = 2 * NB * NB + 2 * (1 + D) * NB + 2 + NB;
     static __host__ __device__ size_t bytes(int M)
     {
         size_t rows = (size_t)M * SW * sizeof(R);
@@ -346,7 +362,8 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     R *rows = reinterpret_cast<R *>(base);
     double *f64 = reinterpret_cast<double *>(base + (((size_t)M * SW * sizeof(R) + 15) & ~(size_t)15));
     double *G = f64;
-    double *RHS = G + NB * NB;
+    double *H = G + NB * NB;
+    double *RHS = H + NB * NB;
     double *beta = RHS + REC;
     double *flag = beta + REC;
     double *zsum = flag + 2;
@@ -359,18 +376,15 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS
     if (live) {
         for (int m = t; m < M; m += L) {
-            R phi[NB], dWi[D], Sp, y1;
+            R *row = rows + (size_t)m * SW;
+            R Sp, y1;
             bool near = false;
-            simulate_path<R, D, NB, LK>(a, cellF, bsig, lk, k, (uint32_t)m, phi, dWi, Sp, y1, near);
+            simulate_path<R, D, NB, LK>(a, cellF, bsig, lk, k, (uint32_t)m, row, row + NB, Sp, y1,
+                                        near);
             if (near) {
                 flag[1] = 1.0;
                 atomicAdd(counters + kCounterNearFace, 1ull);
             }
-            R *row = rows + (size_t)m * SW;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) row[b] = phi[b];
-#pragma unroll
-            for (int l = 0; l < D; ++l) row[NB + l] = dWi[l];
             row[NB + D] = Sp;
             row[NB + D + 1] = y1;
         }
@@ -409,30 +423,54 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     }
     __syncthreads();
 
-    // 3. Cholesky factor (binary64), singular pivot -> LP0 mean fallback
-    if (live && t == 0) {
-        double tr = 0.0;
+    // 3. G^{-1} by Gauss-Jordan elimination without pivoting (G is symmetric
+    //    positive definite), binary64, one entry per lane per pivot, two LDS
+    //    buffers.  The pivots are the Schur complements, i.e. the squared
+    //    diagonal of the Cholesky factor; a pivot <= 1e-12 trace(G) marks the
+    //    stratum singular and it falls back to the LP0 mean.
+    double tol = 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) tr += G[b * NB + b];
-        const bool ok = cholesky_lds<NB>(G, 1e-12 * tr);
-        flag[0] = ok ? 1.0 : 0.0;
-        if (!ok) atomicAdd(counters + kCounterSingular, 1ull);
-    }
-    __syncthreads();
-
-    // 4. z regressions: one lane per component
-    const bool ok = live && flag[0] != 0.0;
-    if (live) {
-        for (int c = t; c < D; c += L) {
-            const double *rhs = RHS + (1 + c) * NB;
-            double *bz = beta + (1 + c) * NB;
-            if (ok) {
-                chol_solve_lds<NB>(G, rhs, bz);
-            } else {
-                bz[0] = rhs[0] / M;
-#pragma unroll
-                for (int b = 1; b < NB; ++b) bz[b] = 0.0;
+    for (int b = 0; b < NB; ++b) tol += G[b * NB + b];
+    tol *= 1e-12;
+    bool ok = live;
+    double *src = G, *dst = H;
+    for (int p = 0; p < NB; ++p) {
+        const double piv = src[p * NB + p];
+        ok = ok && piv > tol;
+        const double inv = 1.0 / piv;
+        if (live) {
+            for (int e = t; e < NB * NB; e += L) {
+                const int r = e / NB, c = e % NB;
+                double v;
+                if (r == p && c == p) v = inv;
+                else if (r == p) v = src[p * NB + c] * inv;
+                else if (c == p) v = -src[r * NB + p] * inv;
+                else v = src[r * NB + c] - src[r * NB + p] * src[p * NB + c] * inv;
+                dst[e] = v;
             }
+        }
+        __syncthreads();
+        double *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    const double *Ginv = src;
+    if (live && !ok && t == 0) atomicAdd(counters + kCounterSingular, 1ull);
+
+    // 4. z regressions: beta_{z_l} = G^{-1} RHS_{z_l}, one coefficient per lane
+    if (live) {
+        for (int e = t; e < D * NB; e += L) {
+            const int c = e / NB, b = e % NB;
+            const double *rhs = RHS + (1 + c) * NB;
+            double v;
+            if (ok) {
+                v = 0.0;
+#pragma unroll
+                for (int u = 0; u < NB; ++u) v += Ginv[b * NB + u] * rhs[u];
+            } else {
+                v = b == 0 ? rhs[0] / M : 0.0;
+            }
+            beta[(1 + c) * NB + b] = v;
         }
     }
     __syncthreads();
@@ -482,13 +520,17 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
         }
     }
     __syncthreads();
-    if (live && t == 0) {
-        if (ok) {
-            chol_solve_lds<NB>(G, RHS, beta);
-        } else {
-            beta[0] = RHS[0] / M;
+    if (live) {
+        for (int b = t; b < NB; b += L) {
+            double v;
+            if (ok) {
+                v = 0.0;
 #pragma unroll
-            for (int b = 1; b < NB; ++b) beta[b] = 0.0;
+                for (int u = 0; u < NB; ++u) v += Ginv[b * NB + u] * RHS[u];
+            } else {
+                v = b == 0 ? RHS[0] / M : 0.0;
+            }
+            beta[b] = v;
         }
     }
     __syncthreads();
@@ -607,51 +649,10 @@ __global__ void __launch_bounds__(256) root_paths_kernel(const StepArgs<R> a, co
 #pragma unroll
         for (int l = 0; l < D; ++l) x[l] = (R)x0.x[l];
         NormalStream<R, D> ns;
-        ns.init(key, (uint32_t)m, 0xFFFFFFFFu, a.tag);
-        R S = (R)0, zsum_cur = (R)0, y1 = (R)0, dW0[D];
-        for (int j = 0; j < a.N; ++j) {
-            R dW[D];
-            ns.step((uint32_t)j, dW);
-#pragma unroll
-            for (int l = 0; l < D; ++l) dW[l] *= a.sqrt_dt;
-            R xn[D];
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-                R accx = x[l];
-                if (a.identity_sigma) {
-                    accx += dW[l];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < D; ++c) accx += bsig[D + l * D + c] * dW[c];
-                }
-                if (a.has_drift) accx += bsig[l] * a.dt;
-                xn[l] = accx;
-            }
-            R ynext, znext = (R)0;
-            if (j + 1 < a.N) {
-                bool near = false;
-                lookup_eval<R, D, NB, LK>(a, lk, j + 1, xn, ynext, znext, near);
-            } else {
-                R s = (R)0;
-#pragma unroll
-                for (int l = 0; l < D; ++l) s += xn[l];
-                ynext = terminal_g<R>(a.terminal, a.T, s);
-            }
-            if (j == 0) {
-#pragma unroll
-                for (int l = 0; l < D; ++l) dW0[l] = dW[l];
-                y1 = ynext;
-            } else {
-                S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, ynext, zsum_cur) * a.dt;
-            }
-            zsum_cur = znext;
-#pragma unroll
-            for (int l = 0; l < D; ++l) x[l] = xn[l];
-        }
-        R s = (R)0;
-#pragma unroll
-        for (int l = 0; l < D; ++l) s += x[l];
-        const R Sp = terminal_g<R>(a.terminal, a.T, s) + S;
+        ns.init(key, (uint32_t)m, 0xFFFFFFFFu, a.tag, a.sqrt_dt);
+        R dW0[D], y1, Sp;
+        bool near = false;
+        run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dW0, y1, Sp, near);
         acc[0] += (double)Sp;
         acc[1] += (double)y1;
 #pragma unroll
@@ -712,7 +713,7 @@ __global__ void draw_kernel(const StepArgs<R> a, const SetupArgs sa, int kind,
                 o[u] = (double)open_uniform<R>(stream_word(key, m, k, a.tag, (uint32_t)u));
         } else if (kind == 1) {
             NormalStream<R, D> ns;
-            ns.init(key, m, k, a.tag);
+            ns.init(key, m, k, a.tag, (R)1);
             for (int s = 0; s * D < count; ++s) {
                 R v[D];
                 ns.step((uint32_t)s, v);
@@ -923,7 +924,7 @@ size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M)
     const size_t rsz = prec_is_float ? 4 : 8;
     size_t rows = (size_t)M * (nb + d + 2) * rsz;
     rows = (rows + 15) & ~(size_t)15;
-    return rows + (size_t)(nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
+    return rows + (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
 }
 
 #define SRMDP_INSTANTIATE(R)                                                                        \
