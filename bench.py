@@ -114,7 +114,19 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--root-paths", type=int, default=1 << 20)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run 10 plain device-to-device copies of this many bytes "
+                         "(calibrates the HBM byte counters of the profiler)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        import torch
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 10}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sweep's "
               "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)

@@ -300,6 +300,10 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
         HIP_TRY(launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
                                table, ws + lay.counters, st),
                 "sweep step");
+        if (a.face_flags)
+            HIP_TRY(launch_face_flags<R>(s.d, o->basis, a, ws + lay.cellF, ws + lay.bsig,
+                                         ws + lay.counters, st),
+                    "near-face flags");
     }
     if (steps1) HIP_TRY(hipEventRecord(steps1, st), "hipEventRecord");
     return SRMDP_OK;

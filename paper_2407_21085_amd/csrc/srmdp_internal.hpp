@@ -72,7 +72,7 @@ struct RootPoint {
 };
 
 struct LaunchShape {
-    unsigned blocks, threads;
+    unsigned blocks, threads;  // groups of strata, threads per workgroup
     size_t lds_bytes;
 };
 
@@ -82,6 +82,9 @@ template <typename R>
 hipError_t launch_step(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                        const void *cellF, const void *bsig, void *lk, void *table, void *counters,
                        hipStream_t st);
+template <typename R>
+hipError_t launch_face_flags(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                             void *counters, hipStream_t st);
 template <typename R>
 hipError_t launch_lookup_rows(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K,
                               int i_lo, int i_hi, hipStream_t st);

@@ -97,9 +97,11 @@ struct RealOps;
 // clamped to [0, cells - 1] (points outside the domain use the boundary cell).
 template <>
 struct RealOps<float> {
+    // v_med3_f32 also maps +-inf into [0, cmax]; a NaN stays NaN and the index
+    // conversion then yields stratum 0
     static __device__ __forceinline__ float clamp_cell(float t, float cmax)
     {
-        return fminf(fmaxf(floorf(t), 0.0f), cmax);
+        return __builtin_amdgcn_fmed3f(floorf(t), 0.0f, cmax);
     }
 };
 template <>
@@ -133,27 +135,30 @@ __device__ __forceinline__ bool near_face(const StepArgs<R> &a, const R *x)
     return near;
 }
 
-// Fitted y_j(x) and sum_l z_{j,l}(x) from look-up row j (`row` points at it).
 // Cell of x per dimension: floor((x - lo) cells / (hi - lo)) clamped to the
-// grid; xi = 2 (t - cell) - 1.  The stratum index is accumulated in the working
-// precision, exact because K <= 2^24.
+// grid, xi = 2 (t - cell) - 1, and the offset of the stratum's look-up record
+// in a row.  The stratum index is accumulated in the working precision, exact
+// because K <= 2^24; K W < 2^32 so the offset is a 24-bit product.
 template <typename R, int D, int NB, int LK>
-__device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__restrict__ row, const R *x,
-                                            R &y, R &zsum)
+__device__ __forceinline__ uint32_t locate(const StepArgs<R> &a, const R *x, R *xi)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
-    R xi[D];
     R kf = (R)0;
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         const R t = (x[l] - a.lo[l]) * a.scale[l];
-        // fmax/fmin also map NaN and +-inf into [0, cells-1]
         const R c = RealOps<R>::clamp_cell(t, a.cmax_f[l]);
         xi[l] = (R)2 * (t - c) - (R)1;
         kf = c * a.stride_f[l] + kf;
     }
-    R rec[W];
-    load_record<R, W>(row + (uint32_t)kf * (uint32_t)W, rec);
+    return __umul24((uint32_t)kf, (uint32_t)W);
+}
+
+// Fitted y_j(x) (truncated) and sum_l z_{j,l}(x) from a look-up record.
+template <typename R, int D, int NB, int LK>
+__device__ __forceinline__ void eval_record(const StepArgs<R> &a, const R *rec, const R *xi, R &y,
+                                            R &zsum)
+{
     R yv = rec[0];
     if constexpr (NB > 1) {
 #pragma unroll
@@ -182,6 +187,16 @@ __device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__res
         }
         zsum = acc;
     }
+}
+
+template <typename R, int D, int NB, int LK>
+__device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__restrict__ row, const R *x,
+                                            R &y, R &zsum)
+{
+    constexpr int W = LookupWidth<R, D, NB, LK>::value;
+    R xi[D], rec[W];
+    load_record<R, W>(row + locate<R, D, NB, LK>(a, x, xi), rec);
+    eval_record<R, D, NB, LK>(a, rec, xi, y, zsum);
 }
 
 // X_{j+1} = X_j + b dt + sigma dW_j (Algorithm "Euler dynamics", read with the
@@ -226,20 +241,18 @@ __device__ __forceinline__ R terminal_at(const StepArgs<R> &a, const R *x)
 template <typename R, int D, int NB, int LK>
 __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
                                          const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
-                                         R *dWi_out, R &y1, R &Sp, bool &near)
+                                         R *dWi_out, R &y1, R &Sp)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     const int i = a.i, N = a.N;
     const size_t row_elems = (size_t)a.K * W;
     const R dt = a.dt;
     R dW[D], xn[D];
-
     ns.step(0u, dW);
     euler_step<R, D>(a, bsig, x, dW, xn);
     R zsum_cur = (R)0;
     if (i + 1 < N) {
         lookup_eval<R, D, NB, LK>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
-        if (a.face_flags) near |= near_face<R, D>(a, xn);
     } else {
         y1 = terminal_at<R, D>(a, xn);
     }
@@ -248,20 +261,17 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         dWi_out[l] = dW[l];
         x[l] = xn[l];
     }
-
     R S = (R)0;
     for (int j = i + 1; j < N - 1; ++j) {
         ns.step((uint32_t)(j - i), dW);
         euler_step<R, D>(a, bsig, x, dW, xn);
         R yn, zn;
         lookup_eval<R, D, NB, LK>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
-        if (a.face_flags) near |= near_face<R, D>(a, xn);
         S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
         zsum_cur = zn;
 #pragma unroll
         for (int l = 0; l < D; ++l) x[l] = xn[l];
     }
-
     R gN;
     if (i < N - 1) {
         ns.step((uint32_t)(N - 1 - i), dW);
@@ -269,7 +279,7 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         gN = terminal_at<R, D>(a, xn);
         S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, gN, zsum_cur) * dt;
     } else {
-        gN = y1;  // i = N-1: the first step already reached X_N
+        gN = y1;
     }
     Sp = gN + S;
 }
@@ -278,14 +288,11 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
 // "stratify" (phi(X_i) to full precision from the centred offset), then
 // run_path.  phi(X_i) and dW_i go to the stratum's LDS row as soon as they are
 // known, so they do not occupy registers during the path.
-template <typename R, int D, int NB, int LK>
-__device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
-                                              const R *__restrict__ bsig, const R *__restrict__ lk,
-                                              uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
-                                              R &Sp, R &y1, bool &near)
+template <typename R, int D, int NB>
+__device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
+                                             uint32_t k, uint32_t m, R *x, R *phi_out)
 {
     const Key key{a.key0, a.key1};
-    R x[D];
 #pragma unroll
     for (int b = 0; b < (D + 3) / 4; ++b) {
         const uint4 w = philox4x32_10(make_uint4((uint32_t)b, m, k, a.tag), key);
@@ -304,9 +311,58 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
         }
     }
     phi_out[0] = (R)1;
+}
+
+template <typename R, int D, int NB, int LK>
+__device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
+                                              const R *__restrict__ bsig, const R *__restrict__ lk,
+                                              uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
+                                              R &Sp, R &y1)
+{
+    R x[D];
+    sample_start<R, D, NB>(a, cellF, k, m, x, phi_out);
     NormalStream<R, D> ns;
-    ns.init(key, m, k, a.tag, a.sqrt_dt);
-    run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dWi_out, y1, Sp, near);
+    ns.init(Key{a.key0, a.key1}, m, k, a.tag, a.sqrt_dt);
+    run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dWi_out, y1, Sp);
+}
+
+// Near-face diagnostic of step i: the positions of a simulation do not depend
+// on the fitted rows, so they are recomputed here with the same draws and the
+// same Euler steps as the sweep, and stratum k is marked when one of its
+// simulations reaches a look-up point within face_eps of an interior face.
+// One wavefront per stratum.
+template <typename R, int D, int NB>
+__global__ void __launch_bounds__(64) face_flags_kernel(const StepArgs<R> a,
+                                                       const CellF<R> *__restrict__ cellF,
+                                                       const R *__restrict__ bsig,
+                                                       unsigned long long *__restrict__ counters)
+{
+    const uint32_t k = blockIdx.x;
+    int count = 0;
+    for (int m = threadIdx.x; m < a.M; m += 64) {
+        R x[D], phi[NB], dW[D], xn[D];
+        sample_start<R, D, NB>(a, cellF, k, (uint32_t)m, x, phi);
+        NormalStream<R, D> ns;
+        ns.init(Key{a.key0, a.key1}, (uint32_t)m, k, a.tag, a.sqrt_dt);
+        bool near = false;
+        for (int j = a.i; j < a.N - 1; ++j) {
+            ns.step((uint32_t)(j - a.i), dW);
+            euler_step<R, D>(a, bsig, x, dW, xn);
+            near |= near_face<R, D>(a, xn);
+#pragma unroll
+            for (int l = 0; l < D; ++l) x[l] = xn[l];
+        }
+        count += near ? 1 : 0;
+    }
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    if (count) atomicAdd(&total, count);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.face_flags[(size_t)a.i * a.K + k] = total ? 1 : 0;
+        if (total) atomicAdd(counters + kCounterNearFace, (unsigned long long)total);
+    }
 }
 
 // LDS layout of one stratum: path rows [M][SW] in the working precision
@@ -354,9 +410,10 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     const int cpw = blockDim.x / L;
     const int slot = threadIdx.x / L;
     const int t = threadIdx.x % L;
+    const int M = a.M;
+
     const uint32_t k = xcd_block_order(blockIdx.x, gridDim.x) * (uint32_t)cpw + (uint32_t)slot;
     const bool live = k < a.K;
-    const int M = a.M;
 
     unsigned char *base = smem + (size_t)slot * a.lds_per_cube;
     R *rows = reinterpret_cast<R *>(base);
@@ -368,23 +425,12 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     double *flag = beta + REC;
     double *zsum = flag + 2;
 
-    if (a.face_flags) {
-        if (t == 0) flag[1] = 0.0;
-        __syncthreads();
-    }
-
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS
     if (live) {
         for (int m = t; m < M; m += L) {
             R *row = rows + (size_t)m * SW;
             R Sp, y1;
-            bool near = false;
-            simulate_path<R, D, NB, LK>(a, cellF, bsig, lk, k, (uint32_t)m, row, row + NB, Sp, y1,
-                                        near);
-            if (near) {
-                flag[1] = 1.0;
-                atomicAdd(counters + kCounterNearFace, 1ull);
-            }
+            simulate_path<R, D, NB, LK>(a, cellF, bsig, lk, k, (uint32_t)m, row, row + NB, Sp, y1);
             row[NB + D] = Sp;
             row[NB + D + 1] = y1;
         }
@@ -537,7 +583,6 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
 
     // 7. store the record and its look-up projection
     if (live) {
-        if (a.face_flags && t == 0) a.face_flags[(size_t)a.i * a.K + k] = flag[1] != 0.0 ? 1 : 0;
         R *out = table + ((size_t)a.i * a.K + k) * REC;
         for (int e = t; e < REC; e += L) {
             const double v = beta[e];
@@ -651,8 +696,7 @@ __global__ void __launch_bounds__(256) root_paths_kernel(const StepArgs<R> a, co
         NormalStream<R, D> ns;
         ns.init(key, (uint32_t)m, 0xFFFFFFFFu, a.tag, a.sqrt_dt);
         R dW0[D], y1, Sp;
-        bool near = false;
-        run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dW0, y1, Sp, near);
+        run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dW0, y1, Sp);
         acc[0] += (double)Sp;
         acc[1] += (double)y1;
 #pragma unroll
@@ -743,6 +787,15 @@ static hipError_t launch_step_impl(const StepArgs<R> &a, const LaunchShape &s, c
     return hipGetLastError();
 }
 
+template <typename R, int D, int NB>
+static hipError_t launch_face_flags_impl(const StepArgs<R> &a, const void *cellF, const void *bsig,
+                                         void *counters, hipStream_t st)
+{
+    hipLaunchKernelGGL((face_flags_kernel<R, D, NB>), dim3(a.K), dim3(64), 0, st, a,
+                       (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
+    return hipGetLastError();
+}
+
 template <typename R, int D, int NB, int LK>
 static hipError_t launch_lookup_rows_impl(const void *table, void *lk, uint32_t K, int i_lo, int i_hi,
                                           hipStream_t st)
@@ -826,6 +879,21 @@ hipError_t launch_step(int d, const StepArgs<R> &a, const LaunchShape &s, int ba
     switch (d) {
 #define X(DD) \
     case DD: return dispatch_step_d<R, DD>(a, s, basis, lkmode, cellF, bsig, lk, table, counters, st);
+        SRMDP_FOR_EACH_D(X)
+#undef X
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t launch_face_flags(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                             void *counters, hipStream_t st)
+{
+    switch (d) {
+#define X(DD)                                                                              \
+    case DD:                                                                               \
+        if (basis == 0) return launch_face_flags_impl<R, DD, 1>(a, cellF, bsig, counters, st); \
+        return launch_face_flags_impl<R, DD, DD + 1>(a, cellF, bsig, counters, st);
         SRMDP_FOR_EACH_D(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -931,6 +999,8 @@ size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M)
     template hipError_t launch_step<R>(int, const StepArgs<R> &, const LaunchShape &, int, int,     \
                                        const void *, const void *, void *, void *, void *,           \
                                        hipStream_t);                                                 \
+    template hipError_t launch_face_flags<R>(int, int, const StepArgs<R> &, const void *,           \
+                                             const void *, void *, hipStream_t);                     \
     template hipError_t launch_lookup_rows<R>(int, int, int, const void *, void *, uint32_t, int,   \
                                               int, hipStream_t);                                     \
     template hipError_t launch_root<R>(int, int, int, const StepArgs<R> &, const void *,            \
