@@ -73,6 +73,7 @@ class _Problem(ctypes.Structure):
         ("M", ctypes.c_int32), ("basis", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("inst", ctypes.c_uint32),
         ("cv_params", ctypes.POINTER(ctypes.c_double)), ("cv_hidden", ctypes.c_int32),
+        ("cv_bf16", ctypes.c_int32),
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
     ]
 
@@ -115,6 +116,10 @@ def _bind(L):
     L.orc_mlp_param_count.restype = ctypes.c_int64
     L.orc_mlp_forward.argtypes = [ctypes.c_int32] * 3 + [dp, dp, ctypes.c_int64, dp]
     L.orc_mlp_backward.argtypes = [ctypes.c_int32] * 3 + [dp, dp, dp, ctypes.c_int64, dp]
+    L.orc_mlp_forward_bf.argtypes = [ctypes.c_int32] * 3 + [dp, dp, ctypes.c_int64, dp,
+                                                            ctypes.c_int32]
+    L.orc_mlp_backward_bf.argtypes = [ctypes.c_int32] * 3 + [dp, dp, dp, ctypes.c_int64, dp,
+                                                             ctypes.c_int32]
     _lib = L
 
 
@@ -147,6 +152,7 @@ class Problem:
     inst: int = 0
     cv_params: Optional[np.ndarray] = None
     cv_hidden: int = 0
+    cv_bf16: int = 0
     face_flags: Optional[np.ndarray] = None   # uint8 [N, K] diagnostic output
     face_eps: float = 1e-5
     _keep: list = field(default_factory=list, repr=False)
@@ -196,6 +202,7 @@ class Problem:
         s.seed, s.inst = self.seed, self.inst
         s.cv_params = _dp(cvp) if cvp is not None else None
         s.cv_hidden = self.cv_hidden if cvp is not None else 0
+        s.cv_bf16 = self.cv_bf16
         if self.face_flags is not None:
             assert self.face_flags.dtype == np.uint8 and self.face_flags.flags["C_CONTIGUOUS"]
             assert self.face_flags.shape == (self.N, self.K)
@@ -307,19 +314,25 @@ def mlp_param_count(n_in: int, H: int, n_out: int) -> int:
     return int(lib().orc_mlp_param_count(n_in, H, n_out))
 
 
-def mlp_forward(n_in: int, H: int, n_out: int, params: np.ndarray, x: np.ndarray) -> np.ndarray:
+BF_WEIGHTS, BF_INPUT, BF_HIDDEN, BF_GRADS = 1, 2, 4, 8
+BF_ALL = BF_WEIGHTS | BF_INPUT | BF_HIDDEN | BF_GRADS
+
+
+def mlp_forward(n_in: int, H: int, n_out: int, params: np.ndarray, x: np.ndarray,
+                bf: int = 0) -> np.ndarray:
     params = np.ascontiguousarray(params, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, n_in)
     y = np.empty((x.shape[0], n_out))
-    lib().orc_mlp_forward(n_in, H, n_out, _dp(params), _dp(x), x.shape[0], _dp(y))
+    lib().orc_mlp_forward_bf(n_in, H, n_out, _dp(params), _dp(x), x.shape[0], _dp(y), bf)
     return y
 
 
 def mlp_backward(n_in: int, H: int, n_out: int, params: np.ndarray, x: np.ndarray,
-                 dy: np.ndarray) -> np.ndarray:
+                 dy: np.ndarray, bf: int = 0) -> np.ndarray:
     params = np.ascontiguousarray(params, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, n_in)
     dy = np.ascontiguousarray(dy, dtype=np.float64).reshape(-1, n_out)
     g = np.empty(params.size)
-    lib().orc_mlp_backward(n_in, H, n_out, _dp(params), _dp(x), _dp(dy), x.shape[0], _dp(g))
+    lib().orc_mlp_backward_bf(n_in, H, n_out, _dp(params), _dp(x), _dp(dy), x.shape[0], _dp(g),
+                              bf)
     return g

@@ -262,6 +262,25 @@ static double clampv(double v, double L)
 
 /* ---------------------------------------------------------- the MLP ---- */
 
+/* Round a value to bfloat16 (8-bit significand), round to nearest even, as
+ * the GPU does when it feeds a value to a bfloat16 matrix instruction.  The
+ * value is first rounded to binary32 (the GPU holds it in binary32). */
+static double bf16_round(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return v; /* inf / nan */
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* Which values the bfloat16 emulation rounds (bit mask). */
+enum { ORC_BF_WEIGHTS = 1, ORC_BF_INPUT = 2, ORC_BF_HIDDEN = 4, ORC_BF_GRADS = 8 };
+
 int64_t orc_mlp_param_count(int32_t in, int32_t H, int32_t out)
 {
     return (int64_t)H * in + H + (int64_t)H * H + H + (int64_t)out * H + out;
@@ -274,81 +293,115 @@ static double silu_grad(double a)
     return s * (1.0 + a * (1.0 - s));
 }
 
+static double maybe_bf16(double v, int on) { return on ? bf16_round(v) : v; }
+
 /* One sample through in -> H -> H -> out with SiLU after both hidden layers;
- * pre-activations are returned in a1, a2 (length H) when non-NULL. */
-static void mlp_one(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
-                    double *y, double *a1, double *a2, double *h1, double *h2)
+ * pre-activations a1, a2 and the (possibly rounded) layer inputs h1, h2 are
+ * returned.  `bf` selects the values rounded to bfloat16: weights (biases are
+ * kept), the input vector, the hidden activations fed to the next layer. */
+static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
+                       double *y, double *a1, double *a2, double *h1, double *h2, int bf)
 {
     const double *W1 = p, *b1 = W1 + (int64_t)H * in, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H,
                  *W3 = b2 + H, *b3 = W3 + (int64_t)out * H;
+    const int rw = bf & ORC_BF_WEIGHTS, rx = bf & ORC_BF_INPUT, rh = bf & ORC_BF_HIDDEN;
     for (int a = 0; a < H; ++a) {
         double s = b1[a];
-        for (int c = 0; c < in; ++c) s += W1[(int64_t)a * in + c] * x[c];
+        for (int c = 0; c < in; ++c)
+            s += maybe_bf16(W1[(int64_t)a * in + c], rw) * maybe_bf16(x[c], rx);
         a1[a] = s;
-        h1[a] = silu(s);
+        h1[a] = maybe_bf16(silu(s), rh);
     }
     for (int a = 0; a < H; ++a) {
         double s = b2[a];
-        for (int c = 0; c < H; ++c) s += W2[(int64_t)a * H + c] * h1[c];
+        for (int c = 0; c < H; ++c) s += maybe_bf16(W2[(int64_t)a * H + c], rw) * h1[c];
         a2[a] = s;
-        h2[a] = silu(s);
+        h2[a] = maybe_bf16(silu(s), rh);
     }
     for (int o = 0; o < out; ++o) {
         double s = b3[o];
-        for (int c = 0; c < H; ++c) s += W3[(int64_t)o * H + c] * h2[c];
+        for (int c = 0; c < H; ++c) s += maybe_bf16(W3[(int64_t)o * H + c], rw) * h2[c];
         y[o] = s;
     }
+}
+
+static void mlp_one(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
+                    double *y, double *a1, double *a2, double *h1, double *h2)
+{
+    mlp_one_bf(in, H, out, p, x, y, a1, a2, h1, h2, 0);
+}
+
+void orc_mlp_forward_bf(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
+                        int64_t B, double *y, int32_t bf)
+{
+    double *buf = (double *)malloc(sizeof(double) * 4 * (size_t)H);
+    for (int64_t s = 0; s < B; ++s)
+        mlp_one_bf(in, H, out, params, x + s * in, y + s * out, buf, buf + H, buf + 2 * H,
+                   buf + 3 * H, bf);
+    free(buf);
 }
 
 void orc_mlp_forward(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
                      int64_t B, double *y)
 {
-    double *buf = (double *)malloc(sizeof(double) * 4 * (size_t)H);
-    for (int64_t s = 0; s < B; ++s)
-        mlp_one(in, H, out, params, x + s * in, y + s * out, buf, buf + H, buf + 2 * H,
-                buf + 3 * H);
-    free(buf);
+    orc_mlp_forward_bf(in, H, out, params, x, B, y, 0);
 }
 
 /* Gradient of sum_s <dy_s, y_s> with respect to the parameters (dy is the
- * upstream gradient), by the chain rule written layer by layer. */
-void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
-                      const double *dy, int64_t B, double *grad)
+ * upstream gradient), by the chain rule written layer by layer.  With `bf`,
+ * the forward values are the rounded ones of mlp_one_bf, and ORC_BF_GRADS also
+ * rounds the upstream gradient and the hidden-layer gradients where they feed a
+ * product (the weight-gradient and back-propagation contractions). */
+void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *params,
+                         const double *x, const double *dy, int64_t B, double *grad, int32_t bf)
 {
-    const double *W2 = params + (int64_t)H * in + H, *W3 = W2 + (int64_t)H * H + H;
+    const double *W2p = params + (int64_t)H * in + H, *W3p = W2p + (int64_t)H * H + H;
+    const int rw = bf & ORC_BF_WEIGHTS, rx = bf & ORC_BF_INPUT, rg = bf & ORC_BF_GRADS;
     double *gW1 = grad, *gb1 = gW1 + (int64_t)H * in, *gW2 = gb1 + H,
            *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H, *gb3 = gW3 + (int64_t)out * H;
     memset(grad, 0, sizeof(double) * (size_t)orc_mlp_param_count(in, H, out));
     double *buf = (double *)malloc(sizeof(double) * (6 * (size_t)H + (size_t)out));
     double *a1 = buf, *a2 = a1 + H, *h1 = a2 + H, *h2 = h1 + H, *d2 = h2 + H, *d1 = d2 + H,
            *yy = d1 + H;
+    double *gq = (double *)malloc(sizeof(double) * (size_t)(out + 2 * H));
+    double *gr = gq + out, *d2r = gr + H;
     for (int64_t s = 0; s < B; ++s) {
         const double *xs = x + s * in, *g = dy + s * out;
-        mlp_one(in, H, out, params, xs, yy, a1, a2, h1, h2);
+        mlp_one_bf(in, H, out, params, xs, yy, a1, a2, h1, h2, bf);
+        for (int o = 0; o < out; ++o) gq[o] = maybe_bf16(g[o], rg);
         for (int o = 0; o < out; ++o) {
             gb3[o] += g[o];
-            for (int c = 0; c < H; ++c) gW3[(int64_t)o * H + c] += g[o] * h2[c];
+            for (int c = 0; c < H; ++c) gW3[(int64_t)o * H + c] += gq[o] * h2[c];
         }
         for (int c = 0; c < H; ++c) {
             double acc = 0.0;
-            for (int o = 0; o < out; ++o) acc += W3[(int64_t)o * H + c] * g[o];
+            for (int o = 0; o < out; ++o) acc += maybe_bf16(W3p[(int64_t)o * H + c], rw) * gq[o];
             d2[c] = acc * silu_grad(a2[c]);
+            d2r[c] = maybe_bf16(d2[c], rg);
         }
         for (int a = 0; a < H; ++a) {
             gb2[a] += d2[a];
-            for (int c = 0; c < H; ++c) gW2[(int64_t)a * H + c] += d2[a] * h1[c];
+            for (int c = 0; c < H; ++c) gW2[(int64_t)a * H + c] += d2r[a] * h1[c];
         }
         for (int c = 0; c < H; ++c) {
             double acc = 0.0;
-            for (int a = 0; a < H; ++a) acc += W2[(int64_t)a * H + c] * d2[a];
+            for (int a = 0; a < H; ++a) acc += maybe_bf16(W2p[(int64_t)a * H + c], rw) * d2r[a];
             d1[c] = acc * silu_grad(a1[c]);
+            gr[c] = maybe_bf16(d1[c], rg);
         }
         for (int a = 0; a < H; ++a) {
             gb1[a] += d1[a];
-            for (int c = 0; c < in; ++c) gW1[(int64_t)a * in + c] += d1[a] * xs[c];
+            for (int c = 0; c < in; ++c) gW1[(int64_t)a * in + c] += gr[a] * maybe_bf16(xs[c], rx);
         }
     }
+    free(gq);
     free(buf);
+}
+
+void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
+                      const double *dy, int64_t B, double *grad)
+{
+    orc_mlp_backward_bf(in, H, out, params, x, dy, B, grad, 0);
 }
 
 /* Control-variate term z_theta(t, x) . dW with the frozen network. */
@@ -358,8 +411,8 @@ static double cv_term(const orc_problem *P, double t, const double *x, const dou
     if (P->cv_hidden > 256) return NAN;
     inp[0] = t;
     for (int l = 0; l < P->d; ++l) inp[1 + l] = x[l];
-    mlp_one(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, out, buf, buf + P->cv_hidden,
-            buf + 2 * P->cv_hidden, buf + 3 * P->cv_hidden);
+    mlp_one_bf(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, out, buf, buf + P->cv_hidden,
+               buf + 2 * P->cv_hidden, buf + 3 * P->cv_hidden, P->cv_bf16);
     double s = 0.0;
     for (int l = 0; l < P->q; ++l) s += out[l] * dW[l];
     return s;

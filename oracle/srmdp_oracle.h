@@ -47,6 +47,7 @@ typedef struct {
     /* frozen control-variate network; NULL disables the control variate */
     const double *cv_params; /* MLP parameters, layout of orc_mlp_forward */
     int32_t cv_hidden;
+    int32_t cv_bf16;         /* bfloat16 emulation mask of orc_mlp_forward_bf (0: exact) */
     /* diagnostic output: face_flags[i*K + k] = 1 when a simulation of stratum k
      * at step i looked up a fitted row at a point within face_eps cell widths of
      * an interior cell face; NULL disables */
@@ -109,6 +110,14 @@ void orc_mlp_forward(int32_t in, int32_t H, int32_t out, const double *params,
                      const double *x, int64_t B, double *y);
 void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params,
                       const double *x, const double *dy, int64_t B, double *grad);
+
+/* The same with bfloat16 rounding at the points a bfloat16 matrix-instruction
+ * implementation rounds (mask: 1 weights, 2 inputs, 4 hidden activations,
+ * 8 upstream and hidden-layer gradients; biases are never rounded). */
+void orc_mlp_forward_bf(int32_t in, int32_t H, int32_t out, const double *params,
+                        const double *x, int64_t B, double *y, int32_t bf);
+void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *params,
+                         const double *x, const double *dy, int64_t B, double *grad, int32_t bf);
 
 #ifdef __cplusplus
 }

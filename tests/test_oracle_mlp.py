@@ -2,6 +2,7 @@
 parameter gradients against central finite differences of the forward pass,
 and the forward pass against a layer-by-layer numpy evaluation."""
 import numpy as np
+import pytest
 
 import oracle as O
 
@@ -41,3 +42,40 @@ def test_gradient_matches_central_differences():
         fd[a] = (np.sum(dy * O.mlp_forward(n_in, H, n_out, pp, x)) -
                  np.sum(dy * O.mlp_forward(n_in, H, n_out, pm, x))) / (2 * eps)
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    # 1 + 2^-8 is exactly halfway between bf16 neighbours 1 and 1 + 2^-7: ties to even (1)
+    n_in, H, n_out = 1, 1, 1
+    # a network that returns its input: W1 = 1, b1 = 0 ... not available (SiLU), so check the
+    # input rounding through a zero-weight first layer and a bias-only output
+    p = np.zeros(O.mlp_param_count(n_in, H, n_out))
+    x = np.array([[1.0 + 2.0 ** -8], [1.0 + 3 * 2.0 ** -8]])
+    # forward with weights 1 in layer 1 picks up the rounded input: y = b3 + W3 silu(W2 silu(W1 x))
+    p[0] = 1.0                      # W1
+    p[2] = 1.0                      # W2
+    p[4] = 1.0                      # W3
+    y_exact = O.mlp_forward(n_in, H, n_out, p, x)
+    y_round = O.mlp_forward(n_in, H, n_out, p, x, bf=O.BF_INPUT)
+    x_r = np.array([[1.0], [1.0 + 4 * 2.0 ** -8]])  # ties to even
+    np.testing.assert_allclose(y_round, O.mlp_forward(n_in, H, n_out, p, x_r), rtol=1e-15)
+    assert not np.allclose(y_exact, y_round)
+
+
+def test_bf16_emulated_gradient_matches_central_differences_of_its_forward():
+    """With weights and inputs rounded (not the hidden values, whose rounding is
+    piecewise constant), the emulated backward is the exact gradient of the
+    emulated forward with respect to the biases and the output layer."""
+    n_in, H, n_out, p, x, dy = _setup(seed=3)
+    bf = O.BF_WEIGHTS | O.BF_INPUT
+    g = O.mlp_backward(n_in, H, n_out, p, x, dy, bf=bf)
+    n = p.size
+    o_b3 = n - n_out
+    eps = 1e-6
+    for a in list(range(o_b3, n)) + [H * n_in + 3]:   # output biases and one first-layer bias
+        pp, pm = p.copy(), p.copy()
+        pp[a] += eps
+        pm[a] -= eps
+        fd = (np.sum(dy * O.mlp_forward(n_in, H, n_out, pp, x, bf=bf)) -
+              np.sum(dy * O.mlp_forward(n_in, H, n_out, pm, x, bf=bf))) / (2 * eps)
+        assert g[a] == pytest.approx(fd, rel=1e-6, abs=1e-8)
