@@ -40,6 +40,26 @@ UNIFORM_OPS = 4                  # shift, or, convert, scale
 BOX_MULLER_OPS = 8               # log, sqrt, sincos (2), 4 multiplies per pair
 LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma, xi fma
 
+# Bytes beyond L2 per launch of the sweep-step kernel of the default workload, from
+# FETCH_SIZE / WRITE_SIZE counter passes scaled by a plain copy's readings (fetch 2.0,
+# write 1.0), keyed by a hash of the sources the kernel is compiled from.  A kernel
+# built from other sources reports null until it is profiled again.
+KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_device.hpp", "srmdp_internal.hpp")
+MEASURED_TRAFFIC = {
+    "72ca1d649e4d7bc9": {"bytes": 5.632168e9,
+                         "profile": "profiles/sweep_step_kernel_logistic_d8_K65536_M64_N50.md"},
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(_ROOT, "paper_2407_21085_amd", "csrc")
+    for name in sorted(KERNEL_SOURCES):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def algorithmic_ops(cfg: dict, lookup_terms: int):
     """Lane operations the method needs (lower bound, before compiler overhead).
@@ -172,6 +192,8 @@ def main() -> int:
     avg_launch_s = ms_steps / launches / 1e3
     achieved = ops_sweep / launches / avg_launch_s
 
+    traffic = MEASURED_TRAFFIC.get(kernel_source_hash()) if cfg["name"] == W.config("cfg5")["name"] else None
+
     y0_root, z0_root = S.root(P, G, Opt, table, cfg["x0"], args.root_paths, workspace=ws)
     x0 = torch.tensor([cfg["x0"]], dtype=torch.float64, device=dev)
     y0_tab, _ = S.evaluate(P, G, Opt.basis, Opt.prec, table, 0, x0)
@@ -193,7 +215,10 @@ def main() -> int:
                    "N": cfg["N"], "basis": cfg["basis"], "precision": "fp32 paths, fp64 solves",
                    "form": "plain", "parallelism": "1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_unit": "bytes beyond L2 per launch",
+                     "traffic_profile": traffic["profile"] if traffic else None,
                      "kernel": "sweep_step_kernel", "avg_launch_ms": avg_launch_s * 1e3,
                      "launches_per_sweep": launches, "ops_per_path_step": ops_step,
                      "ops_per_sample": ops_sample,
