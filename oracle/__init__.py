@@ -75,6 +75,7 @@ class _Problem(ctypes.Structure):
         ("cv_params", ctypes.POINTER(ctypes.c_double)), ("cv_hidden", ctypes.c_int32),
         ("cv_bf16", ctypes.c_int32),
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
+        ("cv_stride", ctypes.c_int32), ("z_center", ctypes.c_int32),
     ]
 
 
@@ -155,6 +156,8 @@ class Problem:
     cv_bf16: int = 0
     face_flags: Optional[np.ndarray] = None   # uint8 [N, K] diagnostic output
     face_eps: float = 1e-5
+    cv_stride: int = 1
+    z_center: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -208,6 +211,8 @@ class Problem:
             assert self.face_flags.shape == (self.N, self.K)
             s.face_flags = self.face_flags.ctypes.data
         s.face_eps = self.face_eps
+        s.cv_stride = self.cv_stride
+        s.z_center = self.z_center
         self._keep = keep
         return s
 
@@ -314,8 +319,10 @@ def mlp_param_count(n_in: int, H: int, n_out: int) -> int:
     return int(lib().orc_mlp_param_count(n_in, H, n_out))
 
 
-BF_WEIGHTS, BF_INPUT, BF_HIDDEN, BF_GRADS = 1, 2, 4, 8
-BF_ALL = BF_WEIGHTS | BF_INPUT | BF_HIDDEN | BF_GRADS
+BF_WEIGHTS, BF_INPUT, BF_HIDDEN, BF_GRADS, BF_PAIR = 1, 2, 4, 8, 16
+# the arithmetic of the library's network: bf16 weights, inputs as bf16 pairs,
+# bf16 hidden activations and gradient operands
+BF_ALL = BF_WEIGHTS | BF_PAIR | BF_HIDDEN | BF_GRADS
 
 
 def mlp_forward(n_in: int, H: int, n_out: int, params: np.ndarray, x: np.ndarray,

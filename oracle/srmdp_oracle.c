@@ -278,8 +278,26 @@ static double bf16_round(double v)
     return (double)f;
 }
 
-/* Which values the bfloat16 emulation rounds (bit mask). */
-enum { ORC_BF_WEIGHTS = 1, ORC_BF_INPUT = 2, ORC_BF_HIDDEN = 4, ORC_BF_GRADS = 8 };
+/* Which values the bfloat16 emulation rounds (bit mask).  ORC_BF_PAIR
+ * represents each input by two bfloat16 numbers, hi = bf16(x) and
+ * lo = bf16(x - hi) (x taken in binary32, where x - hi is exact), and feeds
+ * hi + lo: about 16 significant bits. */
+enum { ORC_BF_WEIGHTS = 1, ORC_BF_INPUT = 2, ORC_BF_HIDDEN = 4, ORC_BF_GRADS = 8, ORC_BF_PAIR = 16 };
+
+static double bf16_pair(double v)
+{
+    const double x = (double)(float)v;
+    const double hi = bf16_round(x);
+    return hi + bf16_round(x - hi);
+}
+
+/* The network's view of input value v under the emulation mask bf. */
+static double input_value(double v, int bf)
+{
+    if (bf & ORC_BF_PAIR) return bf16_pair(v);
+    if (bf & ORC_BF_INPUT) return bf16_round(v);
+    return v;
+}
 
 int64_t orc_mlp_param_count(int32_t in, int32_t H, int32_t out)
 {
@@ -304,11 +322,11 @@ static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, cons
 {
     const double *W1 = p, *b1 = W1 + (int64_t)H * in, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H,
                  *W3 = b2 + H, *b3 = W3 + (int64_t)out * H;
-    const int rw = bf & ORC_BF_WEIGHTS, rx = bf & ORC_BF_INPUT, rh = bf & ORC_BF_HIDDEN;
+    const int rw = bf & ORC_BF_WEIGHTS, rh = bf & ORC_BF_HIDDEN;
     for (int a = 0; a < H; ++a) {
         double s = b1[a];
         for (int c = 0; c < in; ++c)
-            s += maybe_bf16(W1[(int64_t)a * in + c], rw) * maybe_bf16(x[c], rx);
+            s += maybe_bf16(W1[(int64_t)a * in + c], rw) * input_value(x[c], bf);
         a1[a] = s;
         h1[a] = maybe_bf16(silu(s), rh);
     }
@@ -351,12 +369,13 @@ void orc_mlp_forward(int32_t in, int32_t H, int32_t out, const double *params, c
  * upstream gradient), by the chain rule written layer by layer.  With `bf`,
  * the forward values are the rounded ones of mlp_one_bf, and ORC_BF_GRADS also
  * rounds the upstream gradient and the hidden-layer gradients where they feed a
- * product (the weight-gradient and back-propagation contractions). */
+ * product (the weight-gradient and back-propagation contractions) and in the
+ * bias gradients, which sum the same rounded values. */
 void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *params,
                          const double *x, const double *dy, int64_t B, double *grad, int32_t bf)
 {
     const double *W2p = params + (int64_t)H * in + H, *W3p = W2p + (int64_t)H * H + H;
-    const int rw = bf & ORC_BF_WEIGHTS, rx = bf & ORC_BF_INPUT, rg = bf & ORC_BF_GRADS;
+    const int rw = bf & ORC_BF_WEIGHTS, rg = bf & ORC_BF_GRADS;
     double *gW1 = grad, *gb1 = gW1 + (int64_t)H * in, *gW2 = gb1 + H,
            *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H, *gb3 = gW3 + (int64_t)out * H;
     memset(grad, 0, sizeof(double) * (size_t)orc_mlp_param_count(in, H, out));
@@ -370,7 +389,7 @@ void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *param
         mlp_one_bf(in, H, out, params, xs, yy, a1, a2, h1, h2, bf);
         for (int o = 0; o < out; ++o) gq[o] = maybe_bf16(g[o], rg);
         for (int o = 0; o < out; ++o) {
-            gb3[o] += g[o];
+            gb3[o] += gq[o];
             for (int c = 0; c < H; ++c) gW3[(int64_t)o * H + c] += gq[o] * h2[c];
         }
         for (int c = 0; c < H; ++c) {
@@ -380,7 +399,7 @@ void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *param
             d2r[c] = maybe_bf16(d2[c], rg);
         }
         for (int a = 0; a < H; ++a) {
-            gb2[a] += d2[a];
+            gb2[a] += d2r[a];
             for (int c = 0; c < H; ++c) gW2[(int64_t)a * H + c] += d2r[a] * h1[c];
         }
         for (int c = 0; c < H; ++c) {
@@ -390,8 +409,8 @@ void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *param
             gr[c] = maybe_bf16(d1[c], rg);
         }
         for (int a = 0; a < H; ++a) {
-            gb1[a] += d1[a];
-            for (int c = 0; c < in; ++c) gW1[(int64_t)a * in + c] += gr[a] * maybe_bf16(xs[c], rx);
+            gb1[a] += gr[a];
+            for (int c = 0; c < in; ++c) gW1[(int64_t)a * in + c] += gr[a] * input_value(xs[c], bf);
         }
     }
     free(gq);
@@ -404,18 +423,14 @@ void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params, 
     orc_mlp_backward_bf(in, H, out, params, x, dy, B, grad, 0);
 }
 
-/* Control-variate term z_theta(t, x) . dW with the frozen network. */
-static double cv_term(const orc_problem *P, double t, const double *x, const double *dW)
+/* The frozen network z_theta(t, x) (q values). */
+static void cv_net(const orc_problem *P, double t, const double *x, double *z)
 {
-    double inp[65], out[64], buf[4 * 256];
-    if (P->cv_hidden > 256) return NAN;
+    double inp[65], buf[4 * 256];
     inp[0] = t;
     for (int l = 0; l < P->d; ++l) inp[1 + l] = x[l];
-    mlp_one_bf(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, out, buf, buf + P->cv_hidden,
+    mlp_one_bf(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, z, buf, buf + P->cv_hidden,
                buf + 2 * P->cv_hidden, buf + 3 * P->cv_hidden, P->cv_bf16);
-    double s = 0.0;
-    for (int l = 0; l < P->q; ++l) s += out[l] * dW[l];
-    return s;
 }
 
 /* -------------------------------------------------------- validation -- */
@@ -427,7 +442,7 @@ static int check_problem(const orc_problem *P, grid_t *G)
     if (P->basis != ORC_LP0 && P->basis != ORC_LP1) return -1;
     if (!P->sigma && P->q != P->d) return -1;
     if (P->M < basis_size(P)) return -1; /* M >= dim of the local space */
-    if (P->cv_params && (P->cv_hidden < 1 || P->cv_hidden > 256)) return -1;
+    if (P->cv_params && (P->cv_hidden < 1 || P->cv_hidden > 256 || P->q > 64)) return -1;
     return grid_init(P, G);
 }
 
@@ -541,7 +556,8 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
 {
     const int d = P->d, q = P->q;
     const double dt = P->T / P->N, sdt = sqrt(dt);
-    double x[64], xn[64], dW[64], z[64];
+    const int stride = P->cv_stride > 1 ? P->cv_stride : 1;
+    double x[64], xn[64], dW[64], z[64], zcv[64];
     memcpy(x, x0, sizeof(double) * d);
     double S = 0.0, cv_tail = 0.0;
     *cvi = 0.0;
@@ -559,14 +575,19 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
         }
         double ynext = y_at(P, G, table, j + 1, xn);
         if (near && j + 1 < P->N && near_interior_face(G, xn, P->face_eps)) *near = 1;
+        double cv = 0.0;
+        if (P->cv_params) {
+            if ((j - i) % stride == 0) cv_net(P, j * dt, x, zcv);
+            for (int l = 0; l < q; ++l) cv += zcv[l] * dW[l];
+        }
         if (j == i) {
             memcpy(dWi, dW, sizeof(double) * q);
             *y1 = ynext;
-            if (P->cv_params) *cvi = cv_term(P, j * dt, x, dW);
+            *cvi = cv;
         } else {
             z_at(P, G, table, j, x, z);
             S += orc_driver(P, j * dt, x, ynext, z) * dt;
-            if (P->cv_params) cv_tail += cv_term(P, j * dt, x, dW);
+            cv_tail += cv;
         }
         memcpy(x, xn, sizeof(double) * d);
     }
@@ -655,11 +676,16 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
     for (int a = 0; a < nb; ++a) trace += Gm[a * nb + a];
     int singular = cholesky(nb, Gm, L, 1e-12 * trace);
 
-    /* z first: q scalar regressions sharing the Gram matrix. */
+    /* z first: q scalar regressions sharing the Gram matrix.  With z_center the
+     * response loses y_{i+1}(X_i) dW_i / dt, whose conditional mean given X_i is
+     * zero (y_{i+1} comes from clouds of later steps). */
+    double *cz = cvi + M;
+    for (int m = 0; m < M; ++m)
+        cz[m] = P->z_center ? y_at(P, G, table, i + 1, Xi + (int64_t)m * d) : 0.0;
     for (int l = 0; l < q; ++l) {
         memset(rhs, 0, sizeof(rhs));
         for (int m = 0; m < M; ++m) {
-            double resp = Sp[m] * dWi[(int64_t)m * q + l] / dt;
+            double resp = (Sp[m] - cz[m]) * dWi[(int64_t)m * q + l] / dt;
             basis_eval(P, G, k, Xi + (int64_t)m * d, phi);
             for (int a = 0; a < nb; ++a) rhs[a] += phi[a] * resp;
         }
@@ -702,7 +728,7 @@ int orc_solve(const orc_problem *P, double *table, int32_t i_hi, int32_t i_lo, i
     if (i_hi >= P->N || i_lo < 0 || i_lo > i_hi) return -1;
     if (P->d > 64 || basis_size(P) > 65) return -1;
     int64_t nsing = 0;
-    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 3);
+    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 4);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #else

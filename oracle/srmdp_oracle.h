@@ -53,6 +53,12 @@ typedef struct {
      * an interior cell face; NULL disables */
     uint8_t *face_flags;
     double face_eps;
+    /* control-variate variants: the network is evaluated at t_j for
+     * j - i = 0, cv_stride, 2 cv_stride, ... and its last value weighs dW_j in
+     * between (<= 1: every step); z_center subtracts y_{i+1}(X_i) dW_i / dt
+     * (g(X_i) when i + 1 = N) from the z response */
+    int32_t cv_stride;
+    int32_t z_center;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */
@@ -113,7 +119,9 @@ void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params,
 
 /* The same with bfloat16 rounding at the points a bfloat16 matrix-instruction
  * implementation rounds (mask: 1 weights, 2 inputs, 4 hidden activations,
- * 8 upstream and hidden-layer gradients; biases are never rounded). */
+ * 8 upstream and hidden-layer gradients (also in the bias gradients), 16 inputs as a pair of bfloat16
+ * numbers hi + lo with hi = bf16(x), lo = bf16(x - hi); biases are never
+ * rounded). */
 void orc_mlp_forward_bf(int32_t in, int32_t H, int32_t out, const double *params,
                         const double *x, int64_t B, double *y, int32_t bf);
 void orc_mlp_backward_bf(int32_t in, int32_t H, int32_t out, const double *params,

@@ -79,3 +79,22 @@ def test_bf16_emulated_gradient_matches_central_differences_of_its_forward():
         fd = (np.sum(dy * O.mlp_forward(n_in, H, n_out, pp, x, bf=bf)) -
               np.sum(dy * O.mlp_forward(n_in, H, n_out, pm, x, bf=bf))) / (2 * eps)
         assert g[a] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_bf16_pair_input_keeps_sixteen_bits():
+    """Input as hi + lo with hi = bf16(x), lo = bf16(x - hi): worked values.
+    x = 1 + 2^-8 + 2^-12: hi = 1 + 2^-7 (above the tie), lo = bf16(2^-12 - 2^-8) = -(2^-8 - 2^-12)
+    exactly (5 significant bits), so the pair is exact.  x = 3 + 2^-20 (binary32 exact): hi = 3,
+    lo = 2^-20 exactly.  x = 1 + 2^-9 + 2^-17 + 2^-19: hi = 1, lo = bf16(2^-9 + 2^-17 + 2^-19);
+    the ulp of lo is 2^-16 and the tail is 0.625 ulp, so lo = 2^-9 + 2^-16."""
+    n_in, H, n_out = 1, 1, 1
+    p = np.zeros(O.mlp_param_count(n_in, H, n_out))
+    p[0] = 1.0
+    p[2] = 1.0
+    p[4] = 1.0
+    xs = np.array([[1 + 2.0 ** -8 + 2.0 ** -12], [3 + 2.0 ** -20], [1 + 2.0 ** -9 + 2.0 ** -17 + 2.0 ** -19]])
+    eff = np.array([[1 + 2.0 ** -8 + 2.0 ** -12], [3 + 2.0 ** -20], [1 + 2.0 ** -9 + 2.0 ** -16]])
+    y_pair = O.mlp_forward(n_in, H, n_out, p, xs, bf=O.BF_PAIR)
+    np.testing.assert_allclose(y_pair, O.mlp_forward(n_in, H, n_out, p, eff), rtol=1e-15)
+    # a single bf16 would lose the low bits
+    assert not np.allclose(O.mlp_forward(n_in, H, n_out, p, xs, bf=O.BF_INPUT), y_pair, rtol=1e-6)

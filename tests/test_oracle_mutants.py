@@ -36,8 +36,8 @@ MUTANTS = [
      "return -P->r * y - P->kappa * sz;",
      CF.test_coupled_driver_matches_discrete_closed_form),
     ("z response scaled by 1/sqrt(dt)",
-     "double resp = Sp[m] * dWi[(int64_t)m * q + l] / dt;",
-     "double resp = Sp[m] * dWi[(int64_t)m * q + l] / sqrt(dt);",
+     "double resp = (Sp[m] - cz[m]) * dWi[(int64_t)m * q + l] / dt;",
+     "double resp = (Sp[m] - cz[m]) * dWi[(int64_t)m * q + l] / sqrt(dt);",
      _pure_expectation),
     ("Brownian increment scaled by dt",
      "const double dt = P->T / P->N, sdt = sqrt(dt);",
