@@ -97,9 +97,44 @@ typedef struct {
     double mu;               /* logistic parameter > 0 */
 } srmdp_grid;
 
+/* Learned martingale control variate (not part of the paper's scheme).  A
+ * network z_theta(t, x): (d+1) -> 64 -> 64 -> q, SiLU after both hidden
+ * layers, bfloat16 weights and layer inputs, binary32 accumulation and biases,
+ * evaluated on the matrix cores.  Each simulation of step i subtracts
+ * sum_{j>i} z_theta(t_j, X_j) . dW_j from its response S' and, for the y
+ * regression only, z_theta(t_i, X_i) . dW_i as well.  Every subtracted term has
+ * conditional mean zero given X_i because dW_j is independent of X_j and of
+ * the network, which is fixed during the step, so the regressions of eq.
+ * (PsiM) keep their targets (the martingale representation behind eq.
+ * (MDP:intro)) and only their variance changes.
+ *   FROZEN: the network cv_params is used unchanged at every step.
+ *   ONLINE: cv_params is the initial network; after each backward step i the
+ *           network takes cv_train.updates_per_step Adam steps on pairs
+ *           (t_i, X_i^(m), z_i(X_i^(m))) of that step's clouds (srmdp_cv_pairs)
+ *           and is used from step i-1 on; cv_params holds the trained network
+ *           when the call returns.
+ * With cv_stride = s > 1 the network is evaluated at t_j for
+ * j - i = 0, s, 2s, ... and its last value weighs dW_j in between (still
+ * adapted, so still of mean zero), dividing its cost by s.  With
+ * SRMDP_F_CV_CENTER_Z the z response S' dW_i / dt also loses
+ * y_{i+1}(X_i) dW_i / dt (g(X_i) when i + 1 = N), of conditional mean zero too.
+ * Binary32 sweeps only; M must be a multiple of 8 and of the lanes per
+ * stratum, which must divide 64.  The ROOT read-out does not use it. */
+typedef enum { SRMDP_CV_NONE = 0, SRMDP_CV_FROZEN = 1, SRMDP_CV_ONLINE = 2 } srmdp_cv;
+
+#define SRMDP_MLP_HIDDEN 64
+#define SRMDP_CV_PAIR_STRATUM 0xFFFFFFFEu  /* counter stratum of the training-pair draws */
+
+typedef struct {
+    int32_t updates_per_step;  /* Adam steps after each backward step, 1..4096 */
+    int32_t batch;             /* pairs per step of Adam: multiple of 256, <= 65536 */
+    float lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015); lr > 0, betas in [0, 1), eps > 0 */
+} srmdp_mlp_train_config;
+
 /* Option flags. */
 #define SRMDP_F_GRAPH        0x1u  /* capture the N step launches in a cached hipGraph */
 #define SRMDP_F_CHECK_FINITE 0x2u  /* fail with SRMDP_E_NUMERIC on a non-finite coefficient */
+#define SRMDP_F_CV_CENTER_Z  0x4u  /* control variate: centre the z response (see srmdp_cv) */
 
 typedef struct {
     int32_t M;              /* simulations per stratum, >= nb (Definition of the clouds) */
@@ -118,6 +153,12 @@ typedef struct {
                              * interior cell face (where binary32 and binary64 positions may
                              * pick different cells), else 0 */
     double face_eps;        /* distance in cell widths; <= 0 means 1e-5 */
+    int32_t cv;             /* srmdp_cv */
+    float *cv_params;       /* device [srmdp_mlp_param_count(d+1, q)] binary32 network
+                             * parameters (layout of srmdp_mlp_param_count); read by FROZEN,
+                             * read and overwritten by ONLINE; NULL when cv is NONE */
+    srmdp_mlp_train_config cv_train;  /* ONLINE only */
+    int32_t cv_stride;      /* network evaluated every cv_stride steps; <= 1 = every step */
 } srmdp_options;
 
 typedef struct {
@@ -129,6 +170,9 @@ typedef struct {
     int32_t step_launches;     /* backward-step kernels launched */
     int32_t lanes_per_cube;    /* lanes per stratum actually used */
     uint64_t near_face_paths;  /* simulations with a near-face look-up (face_flags set) */
+    float cv_loss_first;       /* ONLINE: mean training loss over the updates after the first
+                                * step run, and after the last one (0 otherwise) */
+    float cv_loss_last;
 } srmdp_stats;
 
 /* Number of coefficients of the table: N * K * (1 + q) * nb.  Layout
@@ -184,6 +228,56 @@ srmdp_status srmdp_draw(const srmdp_problem *problem, const srmdp_grid *grid,
                         const srmdp_options *opts, int32_t kind, int32_t i, uint32_t k0,
                         uint32_t nk, uint32_t m0, uint32_t nm, int32_t count, double *out,
                         void *stream);
+
+/* Training pairs of the online control variate after step i: pair s draws a
+ * stratum k = floor(K u0) and a simulation m = floor(M u1) from the 32-bit
+ * words (u0, u1) of Philox4x32-10 counter (0, s, SRMDP_CV_PAIR_STRATUM,
+ * i | instance << 16), rebuilds that simulation's start X_i^(m) (the draw of
+ * the sweep) and takes the fitted, truncated z_i of stratum k there.
+ * x16 device [n][16] floats: (t_i, X_i, zero padding); z16 device [n][16]:
+ * (z_i, zero padding).  table device binary32 (opts->prec must be FP32), row i
+ * written; workspace as for srmdp_solve. */
+srmdp_status srmdp_cv_pairs(const srmdp_problem *problem, const srmdp_grid *grid,
+                            const srmdp_options *opts, const void *table, int32_t i, int64_t n,
+                            float *x16, float *z16, void *workspace, size_t ws_bytes, void *stream);
+
+/* --- the control-variate network on its own (shapes in <= 16, out <= 16) ---
+ * Parameters, binary32, row-major: W1 [64][in], b1 [64], W2 [64][64], b2 [64],
+ * W3 [out][64], b3 [out].  The packed form (srmdp_mlp_packed_bytes() bytes,
+ * device) holds the biases and the bf16 weight fragments the kernels read. */
+int64_t srmdp_mlp_param_count(int32_t in, int32_t out);
+size_t srmdp_mlp_packed_bytes(void);
+
+/* Glorot-uniform weights from Philox4x32-10 (key = seed), zero biases; with
+ * zero_output_layer the last layer's weights are zero too (z_theta = 0). */
+srmdp_status srmdp_mlp_init(int32_t in, int32_t out, uint64_t seed, int32_t zero_output_layer,
+                            float *params, void *stream);
+srmdp_status srmdp_mlp_pack(int32_t in, int32_t out, const float *params, void *packed, void *stream);
+
+/* y [n][out] = z_theta(x [n][in]) (device arrays). */
+srmdp_status srmdp_mlp_forward(int32_t in, int32_t out, const void *packed, const float *x, int64_t n,
+                               float *y, void *stream);
+
+/* grad [P] = d/dtheta sum_s <dy_s, z_theta(x_s)> with bf16 operands as in the
+ * forward pass (upstream and hidden-layer gradients rounded to bf16 where they
+ * enter a matrix product; bias gradients in binary32).  Device arrays;
+ * workspace of srmdp_mlp_backward_workspace(in, out, n) bytes. */
+size_t srmdp_mlp_backward_workspace(int32_t in, int32_t out, int64_t n);
+srmdp_status srmdp_mlp_backward(int32_t in, int32_t out, const void *packed, const float *x,
+                                const float *dy, int64_t n, float *grad, void *workspace,
+                                size_t ws_bytes, void *stream);
+
+/* cfg->updates_per_step Adam steps on the mean over a batch of
+ * sum_o (z_theta(x)_o - z_o)^2, batches taken cyclically from the n pairs
+ * x16 / z16 ([n][16] floats, 16-byte aligned, n a multiple of 64); adam_m and
+ * adam_v [P] are the moment estimates (zero before the first step) and adam_t0
+ * the number of steps taken before.  params is updated in place; packed_out
+ * receives the packed network; loss (device [updates] or NULL) the batch loss
+ * before each step.  One workgroup. */
+srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam_m, float *adam_v,
+                             int64_t adam_t0, const float *x16, const float *z16, int64_t n,
+                             const srmdp_mlp_train_config *cfg, void *packed_out, float *loss,
+                             void *stream);
 
 /* Releases cached hipGraph executables. */
 void srmdp_release_graphs(void);

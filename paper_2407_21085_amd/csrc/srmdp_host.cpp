@@ -12,10 +12,12 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
 #include "srmdp_internal.hpp"
+#include "srmdp_mlp.hpp"
 
 using namespace srmdp;
 
@@ -113,10 +115,37 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     const int L = o->lanes_per_cube;
     if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64 && L != 128 && L != 256)
         return fail(SRMDP_E_INVALID, "lanes_per_cube must be 0, 8, 16, 32, 64, 128 or 256");
-    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE))
+    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z))
         return fail(SRMDP_E_INVALID, "unknown flag bits");
+    if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
+        return fail(SRMDP_E_INVALID, "SRMDP_F_CV_CENTER_Z needs a control variate");
+    if (o->cv_stride > 65535) return fail(SRMDP_E_INVALID, "cv_stride above 65535");
     if (!(o->face_eps < 0.5) || std::isnan(o->face_eps))
         return fail(SRMDP_E_INVALID, "face_eps must be < 0.5 cell widths");
+    if (o->cv != SRMDP_CV_NONE && o->cv != SRMDP_CV_FROZEN && o->cv != SRMDP_CV_ONLINE)
+        return fail(SRMDP_E_INVALID, "unknown control variate %d", o->cv);
+    if (o->cv != SRMDP_CV_NONE) {
+        if (!o->cv_params) return fail(SRMDP_E_INVALID, "the control variate needs cv_params");
+        if (s.d + 1 > kMlpMaxIn || s.q > kMlpMaxOut)
+            return fail(SRMDP_E_UNSUPPORTED, "the control variate takes d + 1 <= %d inputs", kMlpMaxIn);
+        if (o->prec != SRMDP_FP32)
+            return fail(SRMDP_E_UNSUPPORTED, "the control variate runs in binary32 sweeps only");
+        if (o->M % 8 != 0)
+            return fail(SRMDP_E_UNSUPPORTED, "the control variate needs M a multiple of 8 (M = %d)", o->M);
+        if (L != 0 && (L > 64 || o->M % L != 0))
+            return fail(SRMDP_E_UNSUPPORTED,
+                        "the control variate needs lanes_per_cube <= 64 dividing M (%d, M = %d)", L, o->M);
+        if (o->cv == SRMDP_CV_ONLINE) {
+            const srmdp_mlp_train_config &c = o->cv_train;
+            if (c.updates_per_step < 1 || c.updates_per_step > 4096)
+                return fail(SRMDP_E_INVALID, "cv_train.updates_per_step outside 1..4096");
+            if (c.batch < 256 || c.batch > 65536 || c.batch % 256 != 0)
+                return fail(SRMDP_E_INVALID, "cv_train.batch must be a multiple of 256 up to 65536");
+            if (!(c.lr > 0.0f) || !(c.beta1 >= 0.0f && c.beta1 < 1.0f) || !(c.beta2 >= 0.0f && c.beta2 < 1.0f) ||
+                !(c.eps > 0.0f) || !std::isfinite(c.lr))
+                return fail(SRMDP_E_INVALID, "Adam needs lr > 0, betas in [0, 1) and eps > 0");
+        }
+    }
     return SRMDP_OK;
 }
 
@@ -131,10 +160,13 @@ int lookup_mode(const srmdp_problem *p)
 constexpr int kRootBlocks = 512;
 
 struct Layout {
-    size_t counters, cellF, bsig, lookup, root_partial, root_out, total;
+    size_t counters, cellF, bsig, lookup, root_partial, root_out;
+    size_t cv_packed, cv_m, cv_v, cv_x, cv_z, cv_loss;  // control variate (0 = absent)
+    int64_t cv_pairs;                                    // training pairs per step
+    size_t total;
 };
 
-Layout layout(const Shape &s, int nb, int is_float, int lk)
+Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options *o = nullptr)
 {
     const size_t rsz = is_float ? 4 : 8;
     Layout L{};
@@ -151,6 +183,24 @@ Layout layout(const Shape &s, int nb, int is_float, int lk)
     off = align_up(off + (size_t)(s.d + 1) * sizeof(double), 256);
     L.lookup = off;
     off = align_up(off + (size_t)s.N * s.K * lookup_width(is_float, s.d, nb, lk) * rsz, 256);
+    if (o && o->cv != SRMDP_CV_NONE) {
+        L.cv_packed = off;
+        off = align_up(off + kPackedBytes, 256);
+        if (o->cv == SRMDP_CV_ONLINE) {
+            const size_t P = (size_t)MlpShape{s.d + 1, s.q}.count();
+            L.cv_pairs = (int64_t)o->cv_train.updates_per_step * o->cv_train.batch;
+            L.cv_m = off;
+            off = align_up(off + P * sizeof(float), 256);
+            L.cv_v = off;
+            off = align_up(off + P * sizeof(float), 256);
+            L.cv_x = off;
+            off = align_up(off + (size_t)L.cv_pairs * 16 * sizeof(float), 256);
+            L.cv_z = off;
+            off = align_up(off + (size_t)L.cv_pairs * 16 * sizeof(float), 256);
+            L.cv_loss = off;
+            off = align_up(off + (size_t)s.N * o->cv_train.updates_per_step * sizeof(float), 256);
+        }
+    }
     L.total = off;
     return L;
 }
@@ -205,6 +255,10 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
         a.check_finite = (o->flags & SRMDP_F_CHECK_FINITE) ? 1 : 0;
         a.face_flags = o->face_flags;
         a.face_eps = (R)(o->face_eps > 0.0 ? o->face_eps : 1e-5);
+        a.cv_stride = o->cv_stride > 1 ? o->cv_stride : 1;
+        a.z_center = (o->flags & SRMDP_F_CV_CENTER_Z) ? 1 : 0;
+    } else {
+        a.cv_stride = 1;
     }
 }
 
@@ -226,11 +280,22 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
 }
 
 // Lanes per stratum: enough to give every lane one path up to a wavefront.
-int auto_lanes(int M)
+// With the control variate every lane of a wavefront must run the same number
+// of paths: the largest power of two up to 64 that divides M.
+int auto_lanes(int M, bool cv = false)
 {
     int L = 8;
+    if (cv) {
+        while (L < 64 && M % (2 * L) == 0) L *= 2;
+        return L;
+    }
     while (L < M && L < 64) L *= 2;
     return L;
+}
+
+int lanes_for(const srmdp_options *o)
+{
+    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M, o->cv != SRMDP_CV_NONE);
 }
 
 // One wavefront per workgroup when a stratum fits in one (several strata share
@@ -238,9 +303,22 @@ int auto_lanes(int M)
 // wavefronts of a CU drift apart, so one wave's latency-bound regression
 // overlaps other waves' path arithmetic instead of the whole CU stalling at
 // the same barrier.
-bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube)
+// With the control variate a workgroup of up to four wavefronts shares one LDS
+// copy of the network's forward weights.
+bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube,
+                bool cv = false)
 {
-    per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M), 16);
+    per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, cv), 16);
+    if (cv) {
+        const size_t cap = 64 * 1024 - kPackedFwdBytes;
+        int cpw = 256 / L;
+        while (cpw * L > 64 && (size_t)cpw * per_cube > cap) cpw /= 2;
+        if ((size_t)cpw * per_cube > cap) return false;
+        ls.threads = (unsigned)(cpw * L);
+        ls.blocks = (unsigned)((s.K + cpw - 1) / cpw);
+        ls.lds_bytes = kPackedFwdBytes + (size_t)cpw * per_cube;
+        return true;
+    }
     int cpw = std::max(1, 64 / L);
     const size_t lds_cap = 64 * 1024;
     while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;
@@ -273,10 +351,11 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
                            hipEvent_t steps1 = nullptr)
 {
     const int is_float = sizeof(R) == 4;
-    const int L = o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
+    const int L = lanes_for(o);
+    const bool cv = o->cv != SRMDP_CV_NONE;
     LaunchShape ls;
     size_t per_cube;
-    if (!make_shape(s, nb, is_float, o->M, L, ls, per_cube))
+    if (!make_shape(s, nb, is_float, o->M, L, ls, per_cube, cv))
         return fail(SRMDP_E_UNSUPPORTED, "M = %d does not fit the per-workgroup LDS budget", o->M);
     StepArgs<R> a;
     fill_step_args<R>(a, p, g, s, o);
@@ -289,6 +368,15 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
 
     HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
     HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    const MlpShape net{s.d + 1, s.q};
+    if (cv) {
+        a.cv_packed = ws + lay.cv_packed;
+        HIP_TRY(launch_mlp_pack(net.in, net.out, o->cv_params, ws + lay.cv_packed, st), "network pack");
+        if (o->cv == SRMDP_CV_ONLINE) {
+            HIP_TRY(launch_zero_f32((float *)(ws + lay.cv_m), net.count(), st), "Adam state");
+            HIP_TRY(launch_zero_f32((float *)(ws + lay.cv_v), net.count(), st), "Adam state");
+        }
+    }
     if (hi < s.N - 1)
         HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, hi + 1,
                                       s.N - 1, st),
@@ -297,9 +385,44 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
     for (int i = hi; i >= lo; --i) {
         a.i = i;
         a.tag = ((uint32_t)i & 0xFFFFu) | (o->instance << 16);
-        HIP_TRY(launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
-                               table, ws + lay.counters, st),
-                "sweep step");
+        bool launched = false;
+        if constexpr (std::is_same<R, float>::value) {
+            if (cv) {
+                HIP_TRY(launch_step_cv(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
+                                       table, ws + lay.counters, st),
+                        "sweep step");
+                if (o->cv == SRMDP_CV_ONLINE) {
+                    float *x16 = (float *)(ws + lay.cv_x), *z16 = (float *)(ws + lay.cv_z);
+                    HIP_TRY(launch_cv_pairs(s.d, o->basis, a, ws + lay.cellF, table, lay.cv_pairs, x16, z16, st),
+                            "training pairs");
+                    const int U = o->cv_train.updates_per_step;
+                    MlpTrainArgs t{};
+                    t.in = net.in;
+                    t.out = net.out;
+                    t.theta = o->cv_params;
+                    t.adam_m = (float *)(ws + lay.cv_m);
+                    t.adam_v = (float *)(ws + lay.cv_v);
+                    t.adam_t0 = (int64_t)(hi - i) * U;
+                    t.x16 = x16;
+                    t.z16 = z16;
+                    t.S = lay.cv_pairs;
+                    t.updates = U;
+                    t.batch = o->cv_train.batch;
+                    t.lr = o->cv_train.lr;
+                    t.beta1 = o->cv_train.beta1;
+                    t.beta2 = o->cv_train.beta2;
+                    t.eps = o->cv_train.eps;
+                    t.packed_out = ws + lay.cv_packed;
+                    t.loss = (float *)(ws + lay.cv_loss) + (size_t)(hi - i) * U;
+                    HIP_TRY(launch_mlp_train(t, st), "network training");
+                }
+                launched = true;
+            }
+        }
+        if (!launched)
+            HIP_TRY(launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
+                                   table, ws + lay.counters, st),
+                    "sweep step");
         if (a.face_flags)
             HIP_TRY(launch_face_flags<R>(s.d, o->basis, a, ws + lay.cellF, ws + lay.bsig,
                                          ws + lay.counters, st),
@@ -315,7 +438,7 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
                         hipStream_t st)
 {
     const int lk = lookup_mode(p);
-    const Layout lay = layout(s, nb, sizeof(R) == 4, lk);
+    const Layout lay = layout(s, nb, sizeof(R) == 4, lk, o);
     unsigned char *ws = (unsigned char *)workspace;
     hipEvent_t e0 = nullptr, e1 = nullptr, s0 = nullptr, s1 = nullptr;
     bool graph_used = false;
@@ -391,7 +514,21 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
             }
             stats->step_launches = hi - lo + 1;
             stats->near_face_paths = ctr[kCounterNearFace];
-            stats->lanes_per_cube = o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
+            stats->lanes_per_cube = lanes_for(o);
+            if (o->cv == SRMDP_CV_ONLINE) {
+                const int U = o->cv_train.updates_per_step;
+                std::vector<float> loss((size_t)(hi - lo + 1) * U);
+                HIP_TRY(hipMemcpy(loss.data(), ws + lay.cv_loss, loss.size() * sizeof(float),
+                                  hipMemcpyDeviceToHost),
+                        "loss copy");
+                double first = 0.0, last = 0.0;
+                for (int u = 0; u < U; ++u) {
+                    first += loss[u];
+                    last += loss[(size_t)(hi - lo) * U + u];
+                }
+                stats->cv_loss_first = (float)(first / U);
+                stats->cv_loss_last = (float)(last / U);
+            }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             (void)hipEventDestroy(s0);
@@ -444,7 +581,7 @@ srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 100; }
+int32_t srmdp_abi_version(void) { return 101; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 
@@ -464,7 +601,7 @@ size_t srmdp_workspace_bytes(const srmdp_problem *problem, const srmdp_grid *gri
     int nb;
     if (check_problem(problem, grid, s) != SRMDP_OK) return 0;
     if (check_options(opts, s, nb) != SRMDP_OK) return 0;
-    return layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+    return layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
 }
 
 srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
@@ -479,7 +616,7 @@ srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
     rc = check_options(opts, s, nb);
     if (rc != SRMDP_OK) return rc;
     if (!table || !workspace) return fail(SRMDP_E_INVALID, "table and workspace must be non-NULL");
-    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
     if (ws_bytes < need)
         return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
@@ -536,7 +673,7 @@ srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid, co
     if (M_root < 1) return fail(SRMDP_E_INVALID, "M_root must be >= 1");
     for (int l = 0; l < s.d; ++l)
         if (!std::isfinite(x0[l])) return fail(SRMDP_E_INVALID, "x0 must be finite");
-    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem)).total;
+    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
     if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
     hipStream_t st = (hipStream_t)stream;
@@ -545,6 +682,157 @@ srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid, co
                                 (unsigned char *)workspace, st);
     return root_impl<double>(problem, grid, opts, s, nb, table, x0, M_root, y0, z0,
                              (unsigned char *)workspace, st);
+}
+
+srmdp_status srmdp_cv_pairs(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
+                            const void *table, int32_t i, int64_t n, float *x16, float *z16, void *workspace,
+                            size_t ws_bytes, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    int nb;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    rc = check_options(opts, s, nb);
+    if (rc != SRMDP_OK) return rc;
+    if (opts->prec != SRMDP_FP32) return fail(SRMDP_E_UNSUPPORTED, "training pairs come from binary32 tables");
+    if (i < 0 || i >= s.N) return fail(SRMDP_E_INVALID, "step %d outside 0..%d", i, s.N - 1);
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(SRMDP_E_INVALID, "n outside 0..2^32-1");
+    if (s.d + 1 > kMlpMaxIn || s.q > kMlpMaxOut) return fail(SRMDP_E_UNSUPPORTED, "d + 1 > %d", kMlpMaxIn);
+    if (!table || !x16 || !z16 || !workspace) return fail(SRMDP_E_INVALID, "table, x16, z16 and workspace are required");
+    const size_t need = layout(s, nb, 1, lookup_mode(problem), opts).total;
+    if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!cv_dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    if (n == 0) return SRMDP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const Layout lay = layout(s, nb, 1, lookup_mode(problem), opts);
+    unsigned char *ws = (unsigned char *)workspace;
+    SetupArgs sa;
+    fill_setup_args(sa, problem, grid, s);
+    StepArgs<float> a;
+    fill_step_args<float>(a, problem, grid, s, opts);
+    a.i = i;
+    a.tag = ((uint32_t)i & 0xFFFFu) | (opts->instance << 16);
+    HIP_TRY(launch_setup<float>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    HIP_TRY(launch_cv_pairs(s.d, opts->basis, a, ws + lay.cellF, table, n, x16, z16, st), "training pairs");
+    return SRMDP_OK;
+}
+
+int64_t srmdp_mlp_param_count(int32_t in, int32_t out)
+{
+    if (in < 1 || in > kMlpMaxIn || out < 1 || out > kMlpMaxOut) return 0;
+    return MlpShape{in, out}.count();
+}
+
+size_t srmdp_mlp_packed_bytes(void) { return kPackedBytes; }
+
+static srmdp_status check_net(int32_t in, int32_t out)
+{
+    if (in < 1 || in > kMlpMaxIn || out < 1 || out > kMlpMaxOut)
+        return fail(SRMDP_E_INVALID, "network shape %d -> %d outside 1..%d -> 1..%d", in, out, kMlpMaxIn,
+                    kMlpMaxOut);
+    return SRMDP_OK;
+}
+
+srmdp_status srmdp_mlp_init(int32_t in, int32_t out, uint64_t seed, int32_t zero_output_layer, float *params,
+                            void *stream)
+{
+    g_error.clear();
+    srmdp_status rc = check_net(in, out);
+    if (rc != SRMDP_OK) return rc;
+    if (!params) return fail(SRMDP_E_INVALID, "params must be non-NULL");
+    HIP_TRY(launch_mlp_init(in, out, seed, zero_output_layer, params, (hipStream_t)stream), "network init");
+    return SRMDP_OK;
+}
+
+srmdp_status srmdp_mlp_pack(int32_t in, int32_t out, const float *params, void *packed, void *stream)
+{
+    g_error.clear();
+    srmdp_status rc = check_net(in, out);
+    if (rc != SRMDP_OK) return rc;
+    if (!params || !packed) return fail(SRMDP_E_INVALID, "params and packed must be non-NULL");
+    HIP_TRY(launch_mlp_pack(in, out, params, packed, (hipStream_t)stream), "network pack");
+    return SRMDP_OK;
+}
+
+srmdp_status srmdp_mlp_forward(int32_t in, int32_t out, const void *packed, const float *x, int64_t n, float *y,
+                               void *stream)
+{
+    g_error.clear();
+    srmdp_status rc = check_net(in, out);
+    if (rc != SRMDP_OK) return rc;
+    if (n < 0) return fail(SRMDP_E_INVALID, "n < 0");
+    if (n == 0) return SRMDP_OK;
+    if (!packed || !x || !y) return fail(SRMDP_E_INVALID, "packed, x and y must be non-NULL");
+    HIP_TRY(launch_mlp_forward(in, out, packed, x, n, y, (hipStream_t)stream), "network forward");
+    return SRMDP_OK;
+}
+
+size_t srmdp_mlp_backward_workspace(int32_t in, int32_t out, int64_t n)
+{
+    if (check_net(in, out) != SRMDP_OK || n < 0) return 0;
+    return std::max<size_t>(1, mlp_backward_partials(n)) * (size_t)MlpShape{in, out}.count() * sizeof(float);
+}
+
+srmdp_status srmdp_mlp_backward(int32_t in, int32_t out, const void *packed, const float *x, const float *dy,
+                                int64_t n, float *grad, void *workspace, size_t ws_bytes, void *stream)
+{
+    g_error.clear();
+    srmdp_status rc = check_net(in, out);
+    if (rc != SRMDP_OK) return rc;
+    if (n < 0) return fail(SRMDP_E_INVALID, "n < 0");
+    if (!packed || !grad || (n > 0 && (!x || !dy)) || !workspace)
+        return fail(SRMDP_E_INVALID, "packed, x, dy, grad and workspace must be non-NULL");
+    const size_t need = srmdp_mlp_backward_workspace(in, out, n);
+    if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        HIP_TRY(launch_zero_f32(grad, MlpShape{in, out}.count(), st), "zero gradient");
+        return SRMDP_OK;
+    }
+    HIP_TRY(launch_mlp_backward(in, out, packed, x, dy, n, (float *)workspace, grad, st), "network backward");
+    return SRMDP_OK;
+}
+
+srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam_m, float *adam_v, int64_t adam_t0,
+                             const float *x16, const float *z16, int64_t n, const srmdp_mlp_train_config *cfg,
+                             void *packed_out, float *loss, void *stream)
+{
+    g_error.clear();
+    srmdp_status rc = check_net(in, out);
+    if (rc != SRMDP_OK) return rc;
+    if (!params || !adam_m || !adam_v || !x16 || !z16 || !cfg || !packed_out)
+        return fail(SRMDP_E_INVALID, "params, adam_m, adam_v, x16, z16, cfg and packed_out are required");
+    if (n < 64 || n % 64 != 0) return fail(SRMDP_E_INVALID, "n must be a positive multiple of 64");
+    if (adam_t0 < 0) return fail(SRMDP_E_INVALID, "adam_t0 < 0");
+    if (((uintptr_t)x16 | (uintptr_t)z16) % 16 != 0) return fail(SRMDP_E_INVALID, "x16 and z16 must be 16-byte aligned");
+    if (cfg->updates_per_step < 1 || cfg->updates_per_step > 4096)
+        return fail(SRMDP_E_INVALID, "updates_per_step outside 1..4096");
+    if (cfg->batch < 256 || cfg->batch > 65536 || cfg->batch % 256 != 0)
+        return fail(SRMDP_E_INVALID, "batch must be a multiple of 256 up to 65536");
+    if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        return fail(SRMDP_E_INVALID, "Adam needs lr > 0, betas in [0, 1) and eps > 0");
+    MlpTrainArgs t{};
+    t.in = in;
+    t.out = out;
+    t.theta = params;
+    t.adam_m = adam_m;
+    t.adam_v = adam_v;
+    t.adam_t0 = adam_t0;
+    t.x16 = x16;
+    t.z16 = z16;
+    t.S = n;
+    t.updates = cfg->updates_per_step;
+    t.batch = cfg->batch;
+    t.lr = cfg->lr;
+    t.beta1 = cfg->beta1;
+    t.beta2 = cfg->beta2;
+    t.eps = cfg->eps;
+    t.packed_out = (unsigned char *)packed_out;
+    t.loss = loss;
+    HIP_TRY(launch_mlp_train(t, (hipStream_t)stream), "network training");
+    return SRMDP_OK;
 }
 
 srmdp_status srmdp_draw(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,

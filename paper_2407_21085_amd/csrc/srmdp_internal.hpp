@@ -56,6 +56,9 @@ struct StepArgs {
     size_t lds_per_cube;
     uint8_t *face_flags;  // [N*K] near-face marks or nullptr
     R face_eps;           // in cell widths
+    const unsigned char *cv_packed;  // control-variate network, packed (nullptr = none)
+    int cv_stride;                   // network evaluated every cv_stride steps (>= 1)
+    int z_center;                    // subtract y_{i+1}(X_i) from the z response's S'
 };
 
 struct SetupArgs {
@@ -101,6 +104,36 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
 bool dimension_compiled(int d);
-size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M);
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false);
+
+// ------------------------------------------------ learned control variate
+// (srmdp_cv.hip; binary32 sweeps only)
+struct MlpTrainArgs {
+    int in, out;
+    float *theta, *adam_m, *adam_v;  // [P] each
+    int64_t adam_t0;                 // Adam steps taken before this call
+    const float *x16, *z16;          // training pairs [S][16]
+    int64_t S;
+    int updates, batch;
+    float lr, beta1, beta2, eps;
+    unsigned char *packed_out;       // packed weights after the last update
+    float *loss;                     // [updates] or nullptr
+};
+bool cv_dimension_compiled(int d);
+hipError_t launch_step_cv(int d, const StepArgs<float> &a, const LaunchShape &s, int basis, int lkmode,
+                          const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                          hipStream_t st);
+hipError_t launch_cv_pairs(int d, int basis, const StepArgs<float> &a, const void *cellF, const void *table,
+                           int64_t S, float *x16, float *z16, hipStream_t st);
+hipError_t launch_mlp_pack(int in, int out, const float *theta, void *packed, hipStream_t st);
+hipError_t launch_mlp_init(int in, int out, uint64_t seed, int zero_output_layer, float *theta,
+                           hipStream_t st);
+hipError_t launch_mlp_forward(int in, int out, const void *packed, const float *x, int64_t B, float *y,
+                              hipStream_t st);
+size_t mlp_backward_partials(int64_t B);
+hipError_t launch_mlp_backward(int in, int out, const void *packed, const float *x, const float *dy,
+                               int64_t B, float *partial, float *grad, hipStream_t st);
+hipError_t launch_mlp_train(const MlpTrainArgs &t, hipStream_t st);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 
 }  // namespace srmdp

@@ -20,8 +20,10 @@ LP0, LP1 = 0, 1
 FP64, FP32 = 0, 1
 DRV_LINEAR, DRV_LOGISTIC = 0, 1
 G_COS_SUM, G_LOGISTIC = 0, 1
-F_GRAPH, F_CHECK_FINITE = 0x1, 0x2
+F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z = 0x1, 0x2, 0x4
+CV_NONE, CV_FROZEN, CV_ONLINE = 0, 1, 2
 MAX_D = 16
+MLP_HIDDEN = 64
 
 
 class SrmdpError(RuntimeError):
@@ -48,6 +50,14 @@ class _Grid(ctypes.Structure):
     ]
 
 
+class _TrainConfig(ctypes.Structure):
+    _fields_ = [
+        ("updates_per_step", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+    ]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [
         ("M", ctypes.c_int32), ("basis", ctypes.c_int32), ("prec", ctypes.c_int32),
@@ -55,6 +65,8 @@ class _Options(ctypes.Structure):
         ("step_hi", ctypes.c_int32), ("step_lo", ctypes.c_int32),
         ("lanes_per_cube", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
+        ("cv", ctypes.c_int32), ("cv_params", ctypes.c_void_p), ("cv_train", _TrainConfig),
+        ("cv_stride", ctypes.c_int32),
     ]
 
 
@@ -64,12 +76,15 @@ class _Stats(ctypes.Structure):
         ("ms_total", ctypes.c_float), ("ms_steps", ctypes.c_float),
         ("step_launches", ctypes.c_int32), ("lanes_per_cube", ctypes.c_int32),
         ("near_face_paths", ctypes.c_uint64),
+        ("cv_loss_first", ctypes.c_float), ("cv_loss_last", ctypes.c_float),
     ]
 
 
 EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_eval",
-           "srmdp_root", "srmdp_draw", "srmdp_release_graphs", "srmdp_last_error",
-           "srmdp_abi_version")
+           "srmdp_root", "srmdp_draw", "srmdp_cv_pairs", "srmdp_mlp_param_count",
+           "srmdp_mlp_packed_bytes", "srmdp_mlp_init", "srmdp_mlp_pack", "srmdp_mlp_forward",
+           "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train",
+           "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
 
 
 def _load():
@@ -99,6 +114,26 @@ def _load():
                              ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int32,
                              vp, vp]
     L.srmdp_draw.restype = ctypes.c_int
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.srmdp_cv_pairs.argtypes = [P, G, O, vp, i32, i64, vp, vp, vp, sz, vp]
+    L.srmdp_cv_pairs.restype = ctypes.c_int
+    L.srmdp_mlp_param_count.argtypes = [i32, i32]
+    L.srmdp_mlp_param_count.restype = i64
+    L.srmdp_mlp_packed_bytes.argtypes = []
+    L.srmdp_mlp_packed_bytes.restype = sz
+    L.srmdp_mlp_init.argtypes = [i32, i32, ctypes.c_uint64, i32, vp, vp]
+    L.srmdp_mlp_init.restype = ctypes.c_int
+    L.srmdp_mlp_pack.argtypes = [i32, i32, vp, vp, vp]
+    L.srmdp_mlp_pack.restype = ctypes.c_int
+    L.srmdp_mlp_forward.argtypes = [i32, i32, vp, vp, i64, vp, vp]
+    L.srmdp_mlp_forward.restype = ctypes.c_int
+    L.srmdp_mlp_backward_workspace.argtypes = [i32, i32, i64]
+    L.srmdp_mlp_backward_workspace.restype = sz
+    L.srmdp_mlp_backward.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp, sz, vp]
+    L.srmdp_mlp_backward.restype = ctypes.c_int
+    L.srmdp_mlp_train.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp, i64,
+                                  ctypes.POINTER(_TrainConfig), vp, vp, vp]
+    L.srmdp_mlp_train.restype = ctypes.c_int
     L.srmdp_release_graphs.argtypes = []
     L.srmdp_release_graphs.restype = None
     L.srmdp_last_error.argtypes = []
@@ -179,6 +214,21 @@ class Grid:
 
 
 @dataclass
+class TrainConfig:
+    """Online training of the control-variate network (Adam)."""
+    updates_per_step: int = 16
+    batch: int = 512
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self) -> _TrainConfig:
+        return _TrainConfig(self.updates_per_step, self.batch, self.lr, self.beta1, self.beta2,
+                            self.eps)
+
+
+@dataclass
 class Options:
     M: int
     basis: int = LP1
@@ -191,11 +241,17 @@ class Options:
     flags: int = 0
     face_flags: object = None   # device uint8 tensor [N, K] or None
     face_eps: float = 0.0
+    cv: int = CV_NONE
+    cv_params: object = None    # device float32 tensor [mlp_param_count(d+1, q)] or None
+    cv_train: TrainConfig = field(default_factory=TrainConfig)
+    cv_stride: int = 1
 
     def c(self) -> _Options:
         ptr = self.face_flags.data_ptr() if self.face_flags is not None else None
+        cvp = self.cv_params.data_ptr() if self.cv_params is not None else None
         return _Options(self.M, self.basis, self.prec, self.seed, self.instance, self.step_hi,
-                        self.step_lo, self.lanes_per_cube, self.flags, ptr, self.face_eps)
+                        self.step_lo, self.lanes_per_cube, self.flags, ptr, self.face_eps,
+                        self.cv, cvp, self.cv_train.c(), self.cv_stride)
 
 
 def table_elems(problem: Problem, grid: Grid, basis: int) -> int:
@@ -256,7 +312,8 @@ def solve(problem: Problem, grid: Grid, opts: Options, table=None, workspace=Non
         out = {"singular_cubes": int(st.singular_cubes), "path_steps": int(st.path_steps),
                "ms_total": float(st.ms_total), "ms_steps": float(st.ms_steps),
                "step_launches": int(st.step_launches), "lanes_per_cube": int(st.lanes_per_cube),
-               "near_face_paths": int(st.near_face_paths)}
+               "near_face_paths": int(st.near_face_paths),
+               "cv_loss_first": float(st.cv_loss_first), "cv_loss_last": float(st.cv_loss_last)}
     return table, out
 
 
@@ -297,6 +354,83 @@ def draw(problem: Problem, grid: Grid, opts: Options, kind: int, i: int, k0: int
     _check(lib.srmdp_draw(problem.c(), grid.c(), opts.c(), kind, i, k0, nk, m0, nm, count,
                           out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def cv_pairs(problem: Problem, grid: Grid, opts: Options, table, i: int, n: int, workspace=None,
+             stream=None):
+    """Training pairs of the online control variate after step i:
+    (x16 [n, 16], z16 [n, 16]) float32 device tensors."""
+    torch = _torch()
+    if workspace is None:
+        workspace = alloc_workspace(problem, grid, opts, device=table.device)
+    x16 = torch.empty((n, 16), dtype=torch.float32, device=table.device)
+    z16 = torch.empty((n, 16), dtype=torch.float32, device=table.device)
+    _check(lib.srmdp_cv_pairs(problem.c(), grid.c(), opts.c(), table.data_ptr(), i, n,
+                              x16.data_ptr(), z16.data_ptr(), workspace.data_ptr(),
+                              workspace.numel(), _stream_ptr(stream)))
+    return x16, z16
+
+
+def mlp_param_count(n_in: int, n_out: int) -> int:
+    n = int(lib.srmdp_mlp_param_count(n_in, n_out))
+    if n == 0:
+        raise SrmdpError(E_INVALID, f"network shape {n_in} -> {n_out} is not supported")
+    return n
+
+
+def mlp_init(n_in: int, n_out: int, seed: int, zero_output_layer: bool = False, stream=None):
+    """Glorot-uniform parameters (float32 device tensor)."""
+    torch = _torch()
+    p = torch.empty(mlp_param_count(n_in, n_out), dtype=torch.float32, device="cuda")
+    _check(lib.srmdp_mlp_init(n_in, n_out, seed, int(zero_output_layer), p.data_ptr(),
+                              _stream_ptr(stream)))
+    return p
+
+
+def mlp_pack(n_in: int, n_out: int, params, stream=None):
+    torch = _torch()
+    packed = torch.empty(int(lib.srmdp_mlp_packed_bytes()), dtype=torch.uint8, device=params.device)
+    _check(lib.srmdp_mlp_pack(n_in, n_out, params.data_ptr(), packed.data_ptr(), _stream_ptr(stream)))
+    return packed
+
+
+def mlp_forward(n_in: int, n_out: int, packed, x, stream=None):
+    """z_theta(x) for x float32 [n, n_in] on the device."""
+    torch = _torch()
+    x = x.to(dtype=torch.float32).contiguous()
+    y = torch.empty((x.shape[0], n_out), dtype=torch.float32, device=x.device)
+    _check(lib.srmdp_mlp_forward(n_in, n_out, packed.data_ptr(), x.data_ptr(), x.shape[0],
+                                 y.data_ptr(), _stream_ptr(stream)))
+    return y
+
+
+def mlp_backward(n_in: int, n_out: int, packed, x, dy, stream=None):
+    """Gradient of sum_s <dy_s, z_theta(x_s)> with respect to the parameters."""
+    torch = _torch()
+    x = x.to(dtype=torch.float32).contiguous()
+    dy = dy.to(dtype=torch.float32).contiguous()
+    n = x.shape[0]
+    grad = torch.empty(mlp_param_count(n_in, n_out), dtype=torch.float32, device=x.device)
+    ws = torch.empty(int(lib.srmdp_mlp_backward_workspace(n_in, n_out, n)), dtype=torch.uint8,
+                     device=x.device)
+    _check(lib.srmdp_mlp_backward(n_in, n_out, packed.data_ptr(), x.data_ptr(), dy.data_ptr(), n,
+                                  grad.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return grad
+
+
+def mlp_train(n_in: int, n_out: int, params, adam_m, adam_v, adam_t0: int, x16, z16,
+              cfg: TrainConfig, stream=None):
+    """cfg.updates_per_step Adam steps in place on params / adam_m / adam_v.
+    Returns (packed network, per-update losses)."""
+    torch = _torch()
+    packed = torch.empty(int(lib.srmdp_mlp_packed_bytes()), dtype=torch.uint8, device=params.device)
+    loss = torch.empty(cfg.updates_per_step, dtype=torch.float32, device=params.device)
+    c = cfg.c()
+    _check(lib.srmdp_mlp_train(n_in, n_out, params.data_ptr(), adam_m.data_ptr(), adam_v.data_ptr(),
+                               adam_t0, x16.data_ptr(), z16.data_ptr(), x16.shape[0],
+                               ctypes.byref(c), packed.data_ptr(), loss.data_ptr(),
+                               _stream_ptr(stream)))
+    return packed, loss
 
 
 def release_graphs() -> None:

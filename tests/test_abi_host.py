@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 100
+    assert S.srmdp.lib.srmdp_abi_version() == 101
 
 
 def test_table_elems_and_paper_sizes():
@@ -112,3 +112,79 @@ def test_workspace_too_small_is_reported():
     need = S.workspace_bytes(P, G, O)
     rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, need - 1, None, None)
     assert rc == S.srmdp.E_WORKSPACE
+
+
+def test_mlp_parameter_counts():
+    S = _S()
+    # (d+1) -> 64 -> 64 -> q: 4804 parameters at d = q = 4, 5320 at d = q = 8
+    assert S.mlp_param_count(5, 4) == 4804
+    assert S.mlp_param_count(9, 8) == 5320
+    assert S.srmdp.lib.srmdp_mlp_param_count(17, 4) == 0
+    assert S.srmdp.lib.srmdp_mlp_param_count(4, 17) == 0
+    assert S.srmdp.lib.srmdp_mlp_packed_bytes() == 640 + 24 * 1024
+
+
+CV_BAD = [
+    ("cv in binary64", None, dict(cv=1, prec=0), -2),
+    ("cv without network", None, dict(cv=1, prec=1, cv_params=None), -1),
+    ("cv with M not a multiple of 8", None, dict(cv=1, prec=1, M=20), -2),
+    ("cv with 128 lanes", None, dict(cv=1, prec=1, lanes_per_cube=128), -2),
+    ("cv with lanes not dividing M", None, dict(cv=1, prec=1, M=24, lanes_per_cube=16), -2),
+    ("unknown cv", None, dict(cv=5, prec=1), -1),
+    ("online batch", None, dict(cv=2, prec=1, batch=100), -1),
+    ("online updates", None, dict(cv=2, prec=1, updates=0), -1),
+    ("online lr", None, dict(cv=2, prec=1, lr=0.0), -1),
+]
+
+
+class _FakeTensor:
+    """A stand-in device pointer: validation fails before it is dereferenced."""
+
+    def data_ptr(self):
+        return 4096
+
+
+@pytest.mark.parametrize("name,_unused,kw,status", CV_BAD, ids=[b[0] for b in CV_BAD])
+def test_control_variate_options_rejected(name, _unused, kw, status):
+    S = _S()
+    P = S.Problem(d=3, N=10)
+    G = S.Grid([-1.0] * 3, [1.0] * 3, [2] * 3)
+    kw = dict(kw)
+    tc = S.TrainConfig(updates_per_step=kw.pop("updates", 4), batch=kw.pop("batch", 256),
+                       lr=kw.pop("lr", 1e-3))
+    params = kw.pop("cv_params", _FakeTensor())
+    O = S.Options(M=kw.pop("M", 32), cv_params=params, cv_train=tc, **kw)
+    rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
+    assert rc == status, S.srmdp.lib.srmdp_last_error().decode()
+
+
+def test_online_workspace_holds_training_state():
+    S = _S()
+    P = S.Problem(d=4, N=50, driver=S.DRV_LOGISTIC, terminal=S.G_LOGISTIC)
+    G = S.Grid([-3.0] * 4, [3.0] * 4, [8] * 4)
+    plain = S.workspace_bytes(P, G, S.Options(M=32, prec=S.FP32))
+    frozen = S.workspace_bytes(P, G, S.Options(M=32, prec=S.FP32, cv=S.CV_FROZEN,
+                                               cv_params=_FakeTensor()))
+    tc = S.TrainConfig(updates_per_step=8, batch=512)
+    online = S.workspace_bytes(P, G, S.Options(M=32, prec=S.FP32, cv=S.CV_ONLINE,
+                                               cv_params=_FakeTensor(), cv_train=tc))
+    assert frozen - plain >= 640 + 24 * 1024
+    # Adam moments, 8 * 512 pairs of 2 x 16 floats, N * 8 losses
+    assert online - frozen >= 2 * 4804 * 4 + 8 * 512 * 32 * 4 + 50 * 8 * 4
+
+
+def test_mlp_calls_reject_bad_arguments():
+    S = _S()
+    lib = S.srmdp.lib
+    tc = S.TrainConfig(updates_per_step=2, batch=256).c()
+    import ctypes
+    # n not a multiple of 64, shape out of range, misaligned pairs
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 100, ctypes.byref(tc), 16, None, None) == -1
+    assert lib.srmdp_mlp_train(17, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(tc), 16, None, None) == -1
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4100, 4096, 128, ctypes.byref(tc), 16, None, None) == -1
+    bad = S.TrainConfig(updates_per_step=2, batch=300).c()
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(bad), 16, None, None) == -1
+    assert lib.srmdp_mlp_forward(0, 4, 16, 16, 10, 16, None) == -1
+    assert lib.srmdp_mlp_forward(5, 4, 16, 16, -1, 16, None) == -1
+    assert lib.srmdp_mlp_backward(5, 4, 16, 16, 16, 64, 16, 16, 0, None) == -3
+    assert lib.srmdp_mlp_backward_workspace(5, 4, 3000) == 3 * 4804 * 4
