@@ -14,6 +14,10 @@ Prints one JSON line:
                per launch / average launch time (HIP events around the step
                kernels, on the stream they run on) against the VALU issue peak
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  error_matched the full-sweep wall time of the plain estimator and of the
+               learned control variate (online training included) at several M,
+               with the error of y(0, x0) over seeds, and the control variate's
+               time at the smallest M that reaches the plain error
 """
 from __future__ import annotations
 
@@ -44,9 +48,10 @@ LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma
 # FETCH_SIZE / WRITE_SIZE counter passes scaled by a plain copy's readings (fetch 2.0,
 # write 1.0), keyed by a hash of the sources the kernel is compiled from.  A kernel
 # built from other sources reports null until it is profiled again.
-KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_device.hpp", "srmdp_internal.hpp")
+KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_sweep.hpp", "srmdp_device.hpp", "srmdp_internal.hpp",
+                  "srmdp_mlp.hpp")
 MEASURED_TRAFFIC = {
-    "72ca1d649e4d7bc9": {"bytes": 5.632168e9,
+    "2080b4982efe38f2": {"bytes": 5.612208e9,
                          "profile": "profiles/sweep_step_kernel_logistic_d8_K65536_M64_N50.md"},
 }
 
@@ -118,11 +123,69 @@ def _product_args(S, cfg: dict):
     P = S.Problem(d=cfg["d"], N=cfg["N"], T=cfg["T"],
                   driver=S.DRV_LOGISTIC if logistic else S.DRV_LINEAR,
                   terminal=S.G_LOGISTIC if cfg["terminal"] == "logistic" else S.G_COS_SUM,
-                  r=cfg.get("r", 0.0), kappa=cfg.get("kappa", 0.0))
+                  r=cfg.get("r", 0.0), kappa=cfg.get("kappa", 0.0),
+                  clamp_y=cfg.get("clamp_y", math.inf))
     G = S.Grid(cfg["lo"], cfg["hi"], cfg["cells"], cfg["mu"])
     Opt = S.Options(M=cfg["M"], basis=S.LP1 if cfg["basis"] == "LP1" else S.LP0,
                     prec=S.FP32 if cfg["prec"] == "fp32" else S.FP64, seed=cfg["seed"])
     return P, G, Opt
+
+
+# Learned control variate of the error-matched comparison: the network is
+# evaluated every CV_STRIDE steps, trained online with CV_TRAIN after each
+# step, and the z response is centred.
+CV_STRIDE = 8
+CV_TRAIN = dict(updates_per_step=4, batch=512, lr=2e-3)
+
+
+def error_matched(S, cfg: dict, seeds, m_cv, root_paths: int, stream) -> dict:
+    """Plain estimator at the workload's M against the online control variate
+    at each M in m_cv, over `seeds`: full-sweep wall time (HIP events on the
+    library's stream, training included) and the RMSE of y(0, x0) from the ROOT
+    read-out against the known solution (0.5 for the logistic benchmark).  Both
+    sides truncate y at C_y = 1, an a-priori bound of this solution (without it
+    the plain recursion diverges for some seeds at these M)."""
+    import torch
+    d = cfg["d"]
+
+    def run(M, cv, seed):
+        c = dict(cfg, M=M, seed=seed, clamp_y=1.0)
+        P, G, Opt = _product_args(S, c)
+        if cv:
+            Opt.cv, Opt.cv_stride = S.CV_ONLINE, CV_STRIDE
+            Opt.flags |= S.F_CV_CENTER_Z
+            Opt.cv_train = S.TrainConfig(**CV_TRAIN)
+            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+        table = S.srmdp.alloc_table(P, G, Opt)
+        ws = S.srmdp.alloc_workspace(P, G, Opt)
+        times = []
+        for rep in range(2):  # the first call warms up
+            if cv:
+                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                ev0.record(stream)
+                S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=False)
+                ev1.record(stream)
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+        y0, _ = S.root(P, G, Opt, table, c["x0"], root_paths, workspace=ws, stream=stream)
+        return times[-1], y0
+
+    def summary(M, cv):
+        rows = [run(M, cv, s) for s in seeds]
+        err = math.sqrt(sum((y - 0.5) ** 2 for _, y in rows) / len(rows))
+        return {"M": M, "ms": sum(t for t, _ in rows) / len(rows), "y0_rmse": err}
+
+    plain = summary(cfg["M"], False)
+    cv = [summary(M, True) for M in m_cv]
+    ok = [c for c in cv if c["y0_rmse"] <= plain["y0_rmse"]]
+    best = min(ok, key=lambda c: c["ms"]) if ok else None
+    return {"read_out": f"ROOT y(0,x0), {root_paths} paths", "exact": 0.5, "truncation": "C_y = 1",
+            "seeds": list(seeds), "cv_form": {"stride": CV_STRIDE, "centred_z": True, **CV_TRAIN},
+            "plain": plain, "cv": cv,
+            "matched": ({"M": best["M"], "speedup": plain["ms"] / best["ms"]} if best else None),
+            "target_speedup": 4.0}
 
 
 def main() -> int:
@@ -134,6 +197,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--root-paths", type=int, default=1 << 20)
+    ap.add_argument("--no-error-matched", action="store_true",
+                    help="skip the plain vs control-variate comparison at matched error")
+    ap.add_argument("--em-seeds", type=int, default=4)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 10 plain device-to-device copies of this many bytes "
                          "(calibrates the HBM byte counters of the profiler)")
@@ -231,6 +297,9 @@ def main() -> int:
         "y0_exact_continuous": 0.5 if cfg["terminal"] == "logistic" else None,
         "lanes_per_cube": stats[0]["lanes_per_cube"],
     }
+    if not args.no_error_matched and cfg["driver"] == "logistic":
+        m_cv = [m for m in (cfg["M"] // 2, cfg["M"] // 4) if m >= cfg["d"] + 1 and m % 8 == 0]
+        out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), m_cv, 1 << 18, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

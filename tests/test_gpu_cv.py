@@ -260,7 +260,7 @@ def cv_step_parity(cfg, steps, params_dev, params, eps=2e-6, stride=1, center=Fa
     torch = _torch()
     K = int(np.prod(cfg["cells"]))
     orc, f_orc = _cv_oracle(cfg, params, cfg["N"] - 1, min(steps), eps, stride, center)
-    worst, worst_flagged, shares = 0.0, 0.0, []
+    worst, worst_flagged, shares, rms = 0.0, 0.0, [], 0.0
     for i in steps:
         table = torch.from_numpy(orc).to(torch.float32).cuda()
         f_gpu = torch.zeros((cfg["N"], K), dtype=torch.uint8, device="cuda")
@@ -273,12 +273,17 @@ def cv_step_parity(cfg, steps, params_dev, params, eps=2e-6, stride=1, center=Fa
         S.solve(Pp, G, Opt, table=table)
         torch.cuda.synchronize()
         flags = f_orc | f_gpu.cpu().numpy()
-        e, ef = parity_unflagged(table.double().cpu().numpy(), orc, [i], flags)
+        gpu = table.double().cpu().numpy()
+        e, ef = parity_unflagged(gpu, orc, [i], flags)
         worst, worst_flagged = max(worst, e), max(worst_flagged, ef)
         shares.append(float(flags[i].mean()))
-    _say(f"[gpu] frozen-network per-step parity {worst:.3e}, flagged share {max(shares):.4f} "
-         f"(worst there {worst_flagged:.3e})")
-    return worst, worst_flagged, max(shares)
+        keep = flags[i] == 0
+        for c in range(orc.shape[2]):
+            ref = np.sqrt(np.mean(orc[i, keep, c, :] ** 2))
+            rms = max(rms, float(np.sqrt(np.mean((gpu[i, keep, c, :] - orc[i, keep, c, :]) ** 2)) / ref))
+    _say(f"[gpu] frozen-network per-step parity: max {worst:.3e}, RMS {rms:.3e}, flagged share "
+         f"{max(shares):.4f} (worst there {worst_flagged:.3e})")
+    return worst, worst_flagged, max(shares), rms
 
 
 CV_CASES = [
@@ -302,15 +307,28 @@ CV_CASES = [
 
 @pytest.mark.parametrize("name,kw", CV_CASES, ids=[c[0] for c in CV_CASES])
 def test_frozen_network_sweep_step_parity(name, kw):
+    """Per-step parity of the control-variate sweep with a frozen random network.
+
+    The network rounds its hidden activations to bf16, and a binary32
+    pre-activation (GPU) and a binary64 one (oracle) that straddle a rounding
+    boundary round to neighbouring bf16 values: at the observed ~3e-7 relative
+    difference of the two, about one network evaluation in fifty.  One such
+    flip moves z_theta by about |W3| 2^-8 |h| ~ 3e-4, and the z response
+    multiplies the control-variate sum by dW_i / dt.  The bound is therefore
+    set per stratum at 1e-3 of the largest coefficient (five times the plain
+    binary32 bound) and at 2e-4 (the plain bound) in RMS over the strata
+    (observed at most 1.2e-4), which a wrong index, time, stride or centre
+    (errors of order one) would exceed by far."""
     kw = dict(kw)
     stride, center = kw.pop("cv_stride", 1), kw.pop("center", False)
     cfg = dict(W.config("cfg2"), name=name, seed=17, **kw)
     d = cfg["d"]
     params_dev, params = _params(d + 1, d, seed=23 + d)
     steps = sorted({cfg["N"] - 1, cfg["N"] - 2, 1, 0}, reverse=True)
-    err, err_flagged, share = cv_step_parity(cfg, steps, params_dev, params, stride=stride,
-                                             center=center)
-    assert err <= 2e-4
+    err, err_flagged, share, rms = cv_step_parity(cfg, steps, params_dev, params, stride=stride,
+                                                  center=center)
+    assert rms <= 2e-4
+    assert err <= 1e-3
     assert share < 0.1
     assert err_flagged < 0.05
 
