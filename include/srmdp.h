@@ -135,6 +135,8 @@ typedef struct {
 #define SRMDP_F_GRAPH        0x1u  /* capture the N step launches in a cached hipGraph */
 #define SRMDP_F_CHECK_FINITE 0x2u  /* fail with SRMDP_E_NUMERIC on a non-finite coefficient */
 #define SRMDP_F_CV_CENTER_Z  0x4u  /* control variate: centre the z response (see srmdp_cv) */
+#define SRMDP_F_AUTOTUNE     0x8u  /* lanes_per_cube == 0: use the autotuned value (srmdp_tune_lanes;
+                                    * tuned once per shape and cached; not during capture) */
 
 typedef struct {
     int32_t M;              /* simulations per stratum, >= nb (Definition of the clouds) */
@@ -197,6 +199,32 @@ size_t srmdp_workspace_bytes(const srmdp_problem *problem, const srmdp_grid *gri
 srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
                          const srmdp_options *opts, void *table, void *workspace,
                          size_t ws_bytes, srmdp_stats *stats, void *stream);
+
+/* Autotuner of the lanes per stratum: times one backward step (the middle of
+ * step_hi..step_lo, whose table row it overwrites; rows above it are read as
+ * for srmdp_solve) with 8, 16, 32, 64, 128 and 256 lanes (those that fit M and
+ * the LDS budget), stores the fastest in *lanes and, if ms is non-NULL, the
+ * time per launch of each candidate in ms[0..5] (-1 = not tried).  The result
+ * is cached per shape and used by SRMDP_F_AUTOTUNE.  Synchronises `stream`. */
+srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *grid,
+                              const srmdp_options *opts, void *table, void *workspace,
+                              size_t ws_bytes, int32_t *lanes, float *ms, void *stream);
+
+/* Ragged batch: n independent instances (host arrays of n problems, grids and
+ * options; same d, basis, precision and look-up mode; any K, M, N, seeds,
+ * instance tags and driver parameters; full plain sweeps, lanes_per_cube
+ * <= 64).  One launch per global step g = 0..max N - 1 runs backward step
+ * N_b - 1 - g of every instance with N_b > g, over the flattened list of
+ * their stratum groups; with SRMDP_F_GRAPH in opts[0].flags the launches are
+ * replayed from a cached hipGraph.  tables: host array of n device tables
+ * (layout of srmdp_table_elems); each equals what srmdp_solve returns for the
+ * instance with the same lanes.  stats: host [n] or NULL (then the call does
+ * not synchronise). */
+size_t srmdp_workspace_bytes_batch(int32_t n, const srmdp_problem *problems, const srmdp_grid *grids,
+                                   const srmdp_options *opts);
+srmdp_status srmdp_solve_batch(int32_t n, const srmdp_problem *problems, const srmdp_grid *grids,
+                               const srmdp_options *opts, void *const *tables, void *workspace,
+                               size_t ws_bytes, srmdp_stats *stats, void *stream);
 
 /* Evaluation of the fitted, truncated y_i and z_i (eq. (PsiM)'s y^M_i, z^M_i)
  * at n points.  table device (precision prec); x device [n*d] doubles;

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
+#include <numeric>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -115,7 +117,7 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     const int L = o->lanes_per_cube;
     if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64 && L != 128 && L != 256)
         return fail(SRMDP_E_INVALID, "lanes_per_cube must be 0, 8, 16, 32, 64, 128 or 256");
-    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z))
+    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z | SRMDP_F_AUTOTUNE))
         return fail(SRMDP_E_INVALID, "unknown flag bits");
     if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
         return fail(SRMDP_E_INVALID, "SRMDP_F_CV_CENTER_Z needs a control variate");
@@ -575,6 +577,335 @@ srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
     for (int l = 0; l < s.q; ++l) z0[l] = out[1 + l];
     return SRMDP_OK;
 }
+
+// ------------------------------------------------------------- autotuner
+// Lanes per stratum, chosen by timing one backward step (the middle of the
+// requested range, so that paths have the average length) with each
+// candidate; results are cached per shape for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tuned;
+
+std::vector<int64_t> tune_key(const Shape &s, int nb, const srmdp_options *o, int lk)
+{
+    return {s.d, s.q, nb, o->prec, lk, o->M, (int64_t)s.K, s.N, o->cv != SRMDP_CV_NONE ? 1 : 0,
+            o->cv_stride, o->basis};
+}
+
+bool lanes_valid(const srmdp_options *o, int L)
+{
+    if (o->cv != SRMDP_CV_NONE) return L <= 64 && o->M % L == 0;
+    int cap = 8;
+    while (cap < o->M && cap < 256) cap *= 2;
+    return L <= cap;
+}
+
+template <typename R>
+srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o, const Shape &s, int nb,
+                       void *table, unsigned char *ws, hipStream_t st, int *best, float *ms_out)
+{
+    const int lk = lookup_mode(p);
+    const bool cv = o->cv != SRMDP_CV_NONE;
+    const Layout lay = layout(s, nb, sizeof(R) == 4, lk, o);
+    const int hi = o->step_hi < 0 ? s.N - 1 : o->step_hi;
+    const int lo = o->step_lo < 0 ? 0 : o->step_lo;
+    const int it = (hi + lo) / 2;
+    StepArgs<R> a;
+    fill_step_args<R>(a, p, g, s, o);
+    a.i = it;
+    a.tag = ((uint32_t)it & 0xFFFFu) | (o->instance << 16);
+    a.face_flags = nullptr;
+    SetupArgs sa;
+    fill_setup_args(sa, p, g, s);
+    HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
+    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    if (it < s.N - 1)
+        HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, it + 1, s.N - 1, st),
+                "look-up rows");
+    if (cv) {
+        a.cv_packed = ws + lay.cv_packed;
+        HIP_TRY(launch_mlp_pack(s.d + 1, s.q, o->cv_params, ws + lay.cv_packed, st), "network pack");
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    const int cand[6] = {8, 16, 32, 64, 128, 256};
+    float best_ms = 0.f;
+    *best = 0;
+    srmdp_status rc = SRMDP_OK;
+    for (int c = 0; c < 6 && rc == SRMDP_OK; ++c) {
+        if (ms_out) ms_out[c] = -1.f;
+        const int L = cand[c];
+        if (!lanes_valid(o, L)) continue;
+        LaunchShape ls;
+        size_t per_cube;
+        if (!make_shape(s, nb, sizeof(R) == 4, o->M, L, ls, per_cube, cv)) continue;
+        a.lanes = L;
+        a.lds_per_cube = per_cube;
+        auto launch = [&]() -> hipError_t {
+            if constexpr (std::is_same<R, float>::value)
+                if (cv)
+                    return launch_step_cv(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
+                                          table, ws + lay.counters, st);
+            return launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup, table,
+                                  ws + lay.counters, st);
+        };
+        hipError_t e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune launch");
+            break;
+        }
+        ms /= 3.f;
+        if (ms_out) ms_out[c] = ms;
+        if (*best == 0 || ms < best_ms) {
+            *best = L;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SRMDP_OK && *best == 0) rc = fail(SRMDP_E_UNSUPPORTED, "no lanes-per-stratum candidate fits");
+    return rc;
+}
+
+srmdp_status tune_cached(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o, const Shape &s, int nb,
+                         void *table, unsigned char *ws, hipStream_t st, int *best, float *ms_out, bool force)
+{
+    const auto key = tune_key(s, nb, o, lookup_mode(p));
+    if (!force) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *best = it->second;
+            return SRMDP_OK;
+        }
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) return fail(SRMDP_E_INVALID, "the autotuner cannot run during capture");
+    srmdp_status rc = o->prec == SRMDP_FP32 ? tune_impl<float>(p, g, o, s, nb, table, ws, st, best, ms_out)
+                                            : tune_impl<double>(p, g, o, s, nb, table, ws, st, best, ms_out);
+    if (rc == SRMDP_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[key] = *best;
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------- batched sweep
+struct BatchPlan {
+    std::vector<int> order;      // instances sorted by N, descending
+    std::vector<int> lanes;      // per instance
+    std::vector<size_t> ws_off;  // per instance sub-workspace offset
+    std::vector<Shape> shapes;
+    size_t inst_bytes = 0, total = 0;
+    int nb = 0, lk = 0, gmax = 0;
+};
+
+template <typename R>
+size_t batch_inst_size() { return sizeof(BatchInstance<R>); }
+
+srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, const srmdp_options *O, BatchPlan &bp)
+{
+    if (n < 1) return fail(SRMDP_E_INVALID, "a batch needs at least one instance");
+    if (!P || !G || !O) return fail(SRMDP_E_INVALID, "problems, grids and options must be non-NULL");
+    bp.shapes.resize(n);
+    bp.lanes.resize(n);
+    bp.ws_off.resize(n);
+    for (int b = 0; b < n; ++b) {
+        int nb;
+        srmdp_status rc = check_problem(&P[b], &G[b], bp.shapes[b]);
+        if (rc == SRMDP_OK) rc = check_options(&O[b], bp.shapes[b], nb);
+        if (rc != SRMDP_OK) return fail(rc, "instance %d: %s", b, g_error.c_str());
+        const int lk = lookup_mode(&P[b]);
+        if (b == 0) {
+            bp.nb = nb;
+            bp.lk = lk;
+        } else if (P[b].d != P[0].d || O[b].basis != O[0].basis || O[b].prec != O[0].prec || lk != bp.lk) {
+            return fail(SRMDP_E_INVALID, "instance %d: a batch shares d, basis, precision and look-up mode", b);
+        }
+        if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0)
+            return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
+        if (O[b].lanes_per_cube > 64)
+            return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches use at most 64 lanes per stratum", b);
+        bp.gmax = std::max(bp.gmax, P[b].N);
+    }
+    if (!dimension_compiled(P[0].d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", P[0].d);
+    bp.order.resize(n);
+    std::iota(bp.order.begin(), bp.order.end(), 0);
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](int x, int y) { return P[x].N > P[y].N; });
+    const int is_float = O[0].prec == SRMDP_FP32;
+    bp.inst_bytes = align_up((size_t)n * (is_float ? batch_inst_size<float>() : batch_inst_size<double>()), 256);
+    size_t off = bp.inst_bytes;
+    for (int b = 0; b < n; ++b) {
+        bp.ws_off[b] = off;
+        off += align_up(layout(bp.shapes[b], bp.nb, is_float, bp.lk, &O[b]).total, 256);
+    }
+    bp.total = off;
+    return SRMDP_OK;
+}
+
+// Lanes per instance: explicit, tuned (cached per shape) or the heuristic, at
+// most 64.  Tuning runs kernels and synchronises, so it happens before any
+// capture.
+srmdp_status resolve_batch_lanes(int n, const srmdp_problem *P, const srmdp_grid *G, const srmdp_options *O,
+                                 void *const *tables, unsigned char *ws, BatchPlan &bp, hipStream_t st)
+{
+    for (int b = 0; b < n; ++b) {
+        int L = O[b].lanes_per_cube;
+        if (L == 0 && (O[b].flags & SRMDP_F_AUTOTUNE)) {
+            srmdp_options o = O[b];
+            o.lanes_per_cube = 0;
+            srmdp_status rc = tune_cached(&P[b], &G[b], &o, bp.shapes[b], bp.nb, tables[b], ws + bp.ws_off[b], st,
+                                          &L, nullptr, false);
+            if (rc != SRMDP_OK) return rc;
+            if (L > 64) L = 64;
+        }
+        if (L == 0) L = auto_lanes(O[b].M);
+        bp.lanes[b] = L;
+    }
+    return SRMDP_OK;
+}
+
+template <typename R>
+srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, const srmdp_options *O,
+                           void *const *tables, unsigned char *ws, const BatchPlan &bp, hipStream_t st)
+{
+    const int is_float = sizeof(R) == 4;
+    const unsigned threads = 64;
+    std::vector<BatchInstance<R>> inst(n);
+    size_t lds = 0;
+    uint32_t first = 0;
+    std::vector<uint32_t> prefix(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        const int b = bp.order[r];
+        const Shape &s = bp.shapes[b];
+        const int L = bp.lanes[b];
+        const int cpw = (int)threads / L;
+        const size_t per_cube = align_up(cube_lds_bytes(is_float, s.d, bp.nb, O[b].M, false), 16);
+        lds = std::max(lds, (size_t)cpw * per_cube);
+        const Layout lay = layout(s, bp.nb, is_float, bp.lk, &O[b]);
+        unsigned char *w = ws + bp.ws_off[b];
+        BatchInstance<R> &I = inst[r];
+        std::memset(&I, 0, sizeof I);
+        fill_step_args<R>(I.a, &P[b], &G[b], s, &O[b]);
+        I.a.lanes = L;
+        I.a.lds_per_cube = per_cube;
+        I.a.face_flags = nullptr;
+        I.cellF = w + lay.cellF;
+        I.bsig = w + lay.bsig;
+        I.lk = w + lay.lookup;
+        I.table = tables[b];
+        I.counters = w + lay.counters;
+        I.first_item = first;
+        I.items = (uint32_t)((s.K + cpw - 1) / cpw);
+        I.instance = O[b].instance;
+        first += I.items;
+        prefix[r + 1] = first;
+    }
+    if (lds > 64 * 1024) return fail(SRMDP_E_UNSUPPORTED, "a batch instance does not fit the LDS budget");
+    for (int b = 0; b < n; ++b) {
+        const Layout lay = layout(bp.shapes[b], bp.nb, is_float, bp.lk, &O[b]);
+        unsigned char *w = ws + bp.ws_off[b];
+        SetupArgs sa;
+        fill_setup_args(sa, &P[b], &G[b], bp.shapes[b]);
+        HIP_TRY(launch_zero_u64((unsigned long long *)(w + lay.counters), kCounterCount, st), "zero counters");
+        HIP_TRY(launch_setup<R>(sa, w + lay.cellF, w + lay.bsig, st), "setup kernel");
+    }
+    HIP_TRY(launch_upload(ws, inst.data(), sizeof(BatchInstance<R>) * n, st), "instance upload");
+    int active = n;
+    for (int g = 0; g < bp.gmax; ++g) {
+        while (active > 0 && P[bp.order[active - 1]].N <= g) --active;
+        HIP_TRY(launch_batch_step<R>(P[0].d, O[0].basis, bp.lk, ws, active, prefix[active], g, threads, lds, st),
+                "batched step");
+    }
+    return SRMDP_OK;
+}
+
+template <typename R>
+srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, const srmdp_options *O,
+                        void *const *tables, unsigned char *ws, BatchPlan &bp, srmdp_stats *stats, hipStream_t st)
+{
+    srmdp_status rc = resolve_batch_lanes(n, P, G, O, tables, ws, bp, st);
+    if (rc != SRMDP_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
+    }
+    if ((O[0].flags & SRMDP_F_GRAPH) && st != nullptr) {
+        std::vector<unsigned char> key;
+        auto put = [&](const void *v, size_t sz) {
+            key.insert(key.end(), (const unsigned char *)v, (const unsigned char *)v + sz);
+        };
+        const char tagb[] = "batch";
+        put(tagb, sizeof tagb);
+        for (int b = 0; b < n; ++b) {
+            put(&P[b], sizeof P[b]);
+            if (P[b].b) put(P[b].b, sizeof(double) * P[b].d);
+            if (P[b].sigma) put(P[b].sigma, sizeof(double) * P[b].d * P[b].q);
+            put(G[b].lo, sizeof(double) * P[b].d);
+            put(G[b].hi, sizeof(double) * P[b].d);
+            put(G[b].cells, sizeof(int32_t) * P[b].d);
+            put(&G[b].mu, sizeof G[b].mu);
+            put(&O[b], sizeof O[b]);
+            put(&tables[b], sizeof tables[b]);
+            put(&bp.lanes[b], sizeof bp.lanes[b]);
+        }
+        put(&ws, sizeof ws);
+        const std::string k = graph_key(key.data(), key.size(), st);
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        auto it = g_graphs.find(k);
+        if (it == g_graphs.end()) {
+            GraphEntry ent;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            rc = enqueue_batch<R>(n, P, G, O, tables, ws, bp, st);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &graph);
+            if (rc != SRMDP_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+            ent.graph = graph;
+            HIP_TRY(hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            it = g_graphs.emplace(k, ent).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second.exec, st), "hipGraphLaunch");
+    } else {
+        rc = enqueue_batch<R>(n, P, G, O, tables, ws, bp, st);
+        if (rc != SRMDP_OK) return rc;
+    }
+    if (stats) {
+        HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        const int is_float = sizeof(R) == 4;
+        for (int b = 0; b < n; ++b) {
+            const Layout lay = layout(bp.shapes[b], bp.nb, is_float, bp.lk, &O[b]);
+            unsigned long long ctr[kCounterCount] = {0, 0, 0, 0};
+            HIP_TRY(hipMemcpy(ctr, ws + bp.ws_off[b] + lay.counters, sizeof ctr, hipMemcpyDeviceToHost), "counters");
+            std::memset(&stats[b], 0, sizeof stats[b]);
+            stats[b].singular_cubes = ctr[kCounterSingular];
+            stats[b].path_steps = (uint64_t)bp.shapes[b].N * (bp.shapes[b].N + 1) / 2 * bp.shapes[b].K * (uint64_t)O[b].M;
+            stats[b].ms_total = ms;
+            stats[b].ms_steps = -1.f;
+            stats[b].step_launches = bp.gmax;
+            stats[b].lanes_per_cube = bp.lanes[b];
+        }
+    }
+    return SRMDP_OK;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -621,9 +952,64 @@ srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
         return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
     hipStream_t st = (hipStream_t)stream;
-    if (opts->prec == SRMDP_FP32)
-        return solve_impl<float>(problem, grid, opts, s, nb, table, workspace, stats, st);
-    return solve_impl<double>(problem, grid, opts, s, nb, table, workspace, stats, st);
+    srmdp_options o = *opts;
+    if ((o.flags & SRMDP_F_AUTOTUNE) && o.lanes_per_cube == 0) {
+        int L = 0;
+        rc = tune_cached(problem, grid, &o, s, nb, table, (unsigned char *)workspace, st, &L, nullptr, false);
+        if (rc != SRMDP_OK) return rc;
+        o.lanes_per_cube = L;
+    }
+    if (o.prec == SRMDP_FP32) return solve_impl<float>(problem, grid, &o, s, nb, table, workspace, stats, st);
+    return solve_impl<double>(problem, grid, &o, s, nb, table, workspace, stats, st);
+}
+
+srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
+                              void *table, void *workspace, size_t ws_bytes, int32_t *lanes, float *ms,
+                              void *stream)
+{
+    g_error.clear();
+    Shape s;
+    int nb;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    rc = check_options(opts, s, nb);
+    if (rc != SRMDP_OK) return rc;
+    if (!table || !workspace || !lanes) return fail(SRMDP_E_INVALID, "table, workspace and lanes are required");
+    const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
+    if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    int L = 0;
+    rc = tune_cached(problem, grid, opts, s, nb, table, (unsigned char *)workspace, (hipStream_t)stream, &L, ms,
+                     true);
+    if (rc != SRMDP_OK) return rc;
+    *lanes = L;
+    return SRMDP_OK;
+}
+
+size_t srmdp_workspace_bytes_batch(int32_t n, const srmdp_problem *problems, const srmdp_grid *grids,
+                                   const srmdp_options *opts)
+{
+    BatchPlan bp;
+    if (plan_batch(n, problems, grids, opts, bp) != SRMDP_OK) return 0;
+    return bp.total;
+}
+
+srmdp_status srmdp_solve_batch(int32_t n, const srmdp_problem *problems, const srmdp_grid *grids,
+                               const srmdp_options *opts, void *const *tables, void *workspace, size_t ws_bytes,
+                               srmdp_stats *stats, void *stream)
+{
+    g_error.clear();
+    BatchPlan bp;
+    srmdp_status rc = plan_batch(n, problems, grids, opts, bp);
+    if (rc != SRMDP_OK) return rc;
+    if (!tables || !workspace) return fail(SRMDP_E_INVALID, "tables and workspace must be non-NULL");
+    for (int b = 0; b < n; ++b)
+        if (!tables[b]) return fail(SRMDP_E_INVALID, "table %d is NULL", b);
+    if (ws_bytes < bp.total) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, bp.total);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *ws = (unsigned char *)workspace;
+    if (opts[0].prec == SRMDP_FP32) return batch_impl<float>(n, problems, grids, opts, tables, ws, bp, stats, st);
+    return batch_impl<double>(n, problems, grids, opts, tables, ws, bp, stats, st);
 }
 
 srmdp_status srmdp_eval(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis,

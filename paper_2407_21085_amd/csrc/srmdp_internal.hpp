@@ -103,6 +103,30 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
                        uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
+// ------------------------------------------------------ batched sweeps
+// One instance of a batched sweep, as the batched kernel reads it.  Global
+// step g runs backward step i = N - 1 - g of every instance with N > g; the
+// instances are sorted by N (descending), so the active ones are a prefix,
+// and work item w of step g belongs to the last active instance whose
+// first_item <= w.
+template <typename R>
+struct BatchInstance {
+    StepArgs<R> a;
+    const void *cellF, *bsig;
+    void *lk, *table, *counters;
+    uint32_t first_item;  // first work item (stratum group) of the instance
+    uint32_t items;       // ceil(K / strata per workgroup)
+    uint32_t instance;    // instance field of the counter tag
+    uint32_t pad;
+};
+
+template <typename R>
+hipError_t launch_batch_step(int d, int basis, int lkmode, const void *inst, int n_active, uint32_t total_items,
+                             int g, unsigned threads, size_t lds_bytes, hipStream_t st);
+// Copies `bytes` from host memory to the device through kernel arguments (no
+// staging buffer, nothing to keep alive after the call, capturable).
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+
 bool dimension_compiled(int d);
 size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false);
 

@@ -399,18 +399,21 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
     return (b % 8u) * (full / 8u) + b / 8u;
 }
 
+// One group of strata of backward step a.i: the workgroup's cpw = blockDim / L
+// strata k = group * cpw + slot, L = a.lanes lanes each.  Shared by the
+// per-step kernel and the batched (several instances) kernel.
 template <typename R, int D, int NB, int LK, bool CV>
-__global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
-                                                        const CellF<R> *__restrict__ cellF,
-                                                        const R *__restrict__ bsig,
-                                                        R *__restrict__ lk, R *__restrict__ table,
-                                                        unsigned long long *__restrict__ counters)
+__device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
+                                            const CellF<R> *__restrict__ cellF,
+                                            const R *__restrict__ bsig, R *__restrict__ lk,
+                                            R *__restrict__ table,
+                                            unsigned long long *__restrict__ counters,
+                                            unsigned char *smem)
 {
     using Lay = CubeLds<R, D, NB, CV>;
     constexpr int SW = Lay::SW;
     constexpr int REC = (1 + D) * NB;
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
-    extern __shared__ __align__(16) unsigned char smem[];
 
     const int L = a.lanes;
     const int cpw = blockDim.x / L;
@@ -418,7 +421,7 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
     const int t = threadIdx.x % L;
     const int M = a.M;
 
-    const uint32_t k = xcd_block_order(blockIdx.x, gridDim.x) * (uint32_t)cpw + (uint32_t)slot;
+    const uint32_t k = group * (uint32_t)cpw + (uint32_t)slot;
     const bool live = k < a.K;
 
     // With the control variate the workgroup first copies the network's
@@ -637,6 +640,18 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
             lrow[e] = (R)v;
         }
     }
+}
+
+template <typename R, int D, int NB, int LK, bool CV>
+__global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
+                                                        const CellF<R> *__restrict__ cellF,
+                                                        const R *__restrict__ bsig,
+                                                        R *__restrict__ lk, R *__restrict__ table,
+                                                        unsigned long long *__restrict__ counters)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_group<R, D, NB, LK, CV>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table,
+                                  counters, smem);
 }
 
 }  // namespace srmdp

@@ -20,7 +20,7 @@ LP0, LP1 = 0, 1
 FP64, FP32 = 0, 1
 DRV_LINEAR, DRV_LOGISTIC = 0, 1
 G_COS_SUM, G_LOGISTIC = 0, 1
-F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z = 0x1, 0x2, 0x4
+F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z, F_AUTOTUNE = 0x1, 0x2, 0x4, 0x8
 CV_NONE, CV_FROZEN, CV_ONLINE = 0, 1, 2
 MAX_D = 16
 MLP_HIDDEN = 64
@@ -81,7 +81,8 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_eval",
-           "srmdp_root", "srmdp_draw", "srmdp_cv_pairs", "srmdp_mlp_param_count",
+           "srmdp_root", "srmdp_draw", "srmdp_tune_lanes", "srmdp_workspace_bytes_batch",
+           "srmdp_solve_batch", "srmdp_cv_pairs", "srmdp_mlp_param_count",
            "srmdp_mlp_packed_bytes", "srmdp_mlp_init", "srmdp_mlp_pack", "srmdp_mlp_forward",
            "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train",
            "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
@@ -115,6 +116,12 @@ def _load():
                              vp, vp]
     L.srmdp_draw.restype = ctypes.c_int
     i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.srmdp_tune_lanes.argtypes = [P, G, O, vp, vp, sz, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp]
+    L.srmdp_tune_lanes.restype = ctypes.c_int
+    L.srmdp_workspace_bytes_batch.argtypes = [i32, P, G, O]
+    L.srmdp_workspace_bytes_batch.restype = sz
+    L.srmdp_solve_batch.argtypes = [i32, P, G, O, ctypes.POINTER(vp), vp, sz, S, vp]
+    L.srmdp_solve_batch.restype = ctypes.c_int
     L.srmdp_cv_pairs.argtypes = [P, G, O, vp, i32, i64, vp, vp, vp, sz, vp]
     L.srmdp_cv_pairs.restype = ctypes.c_int
     L.srmdp_mlp_param_count.argtypes = [i32, i32]
@@ -431,6 +438,59 @@ def mlp_train(n_in: int, n_out: int, params, adam_m, adam_v, adam_t0: int, x16, 
                                ctypes.byref(c), packed.data_ptr(), loss.data_ptr(),
                                _stream_ptr(stream)))
     return packed, loss
+
+
+def tune_lanes(problem: Problem, grid: Grid, opts: Options, table=None, workspace=None, stream=None):
+    """Autotuned lanes per stratum and the time per launch of each candidate
+    (8, 16, 32, 64, 128, 256; -1 = not tried).  Overwrites one table row."""
+    if table is None:
+        table = alloc_table(problem, grid, opts)
+    if workspace is None:
+        workspace = alloc_workspace(problem, grid, opts, device=table.device)
+    lanes = ctypes.c_int32(0)
+    ms = (ctypes.c_float * 6)()
+    _check(lib.srmdp_tune_lanes(problem.c(), grid.c(), opts.c(), table.data_ptr(), workspace.data_ptr(),
+                                workspace.numel(), ctypes.byref(lanes),
+                                ctypes.cast(ms, ctypes.POINTER(ctypes.c_float)), _stream_ptr(stream)))
+    return int(lanes.value), [float(v) for v in ms]
+
+
+def _arrays(problems, grids, opts):
+    n = len(problems)
+    Pa = (_Problem * n)(*[p.c() for p in problems])
+    Ga = (_Grid * n)(*[g.c() for g in grids])
+    Oa = (_Options * n)(*[o.c() for o in opts])
+    return n, Pa, Ga, Oa
+
+
+def workspace_bytes_batch(problems, grids, opts) -> int:
+    n, Pa, Ga, Oa = _arrays(problems, grids, opts)
+    v = int(lib.srmdp_workspace_bytes_batch(n, Pa, Ga, Oa))
+    if v == 0:
+        raise SrmdpError(E_INVALID, lib.srmdp_last_error().decode())
+    return v
+
+
+def solve_batch(problems, grids, opts, tables=None, workspace=None, stream=None, stats: bool = True):
+    """Ragged batch of instances in one launch per global backward step.
+    Returns (list of tables, list of stats dicts or None)."""
+    torch = _torch()
+    if tables is None:
+        tables = [alloc_table(p, g, o) for p, g, o in zip(problems, grids, opts)]
+    n, Pa, Ga, Oa = _arrays(problems, grids, opts)
+    if workspace is None:
+        workspace = torch.empty(int(lib.srmdp_workspace_bytes_batch(n, Pa, Ga, Oa)) or 1, dtype=torch.uint8,
+                                device="cuda")
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in tables])
+    st = (_Stats * n)()
+    _check(lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, workspace.data_ptr(), workspace.numel(),
+                                 st if stats else None, _stream_ptr(stream)))
+    out = None
+    if stats:
+        out = [{"singular_cubes": int(x.singular_cubes), "path_steps": int(x.path_steps),
+                "ms_total": float(x.ms_total), "step_launches": int(x.step_launches),
+                "lanes_per_cube": int(x.lanes_per_cube)} for x in st]
+    return tables, out
 
 
 def release_graphs() -> None:

@@ -188,3 +188,33 @@ def test_mlp_calls_reject_bad_arguments():
     assert lib.srmdp_mlp_forward(5, 4, 16, 16, -1, 16, None) == -1
     assert lib.srmdp_mlp_backward(5, 4, 16, 16, 16, 64, 16, 16, 0, None) == -3
     assert lib.srmdp_mlp_backward_workspace(5, 4, 3000) == 3 * 4804 * 4
+
+
+def _batch(S, ds=(2, 2), **okw):
+    P = [S.Problem(d=d, N=5 + b) for b, d in enumerate(ds)]
+    G = [S.Grid([-1.0] * d, [1.0] * d, [3] * d) for d in ds]
+    O = [S.Options(M=16, prec=S.FP32, **okw) for _ in ds]
+    return P, G, O
+
+
+def test_batch_workspace_and_rejections():
+    S = _S()
+    lib = S.srmdp.lib
+    P, G, O = _batch(S)
+    total = S.workspace_bytes_batch(P, G, O)
+    single = sum(S.workspace_bytes(p, g, o) for p, g, o in zip(P, G, O))
+    assert total >= single
+    for bad, status in [(_batch(S, ds=(2, 3)), -1),                 # different d
+                        (_batch(S, lanes_per_cube=128), -2),        # more than 64 lanes
+                        (_batch(S, step_hi=2), -2),                 # partial sweeps
+                        (_batch(S, cv=1, cv_params=_FakeTensor()), -2)]:
+        n, Pa, Ga, Oa = S.srmdp._arrays(*bad)
+        import ctypes
+        ptrs = (ctypes.c_void_p * n)(*([4096] * n))
+        rc = lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None)
+        assert rc == status, lib.srmdp_last_error().decode()
+    n, Pa, Ga, Oa = S.srmdp._arrays(P, G, O)
+    import ctypes
+    ptrs = (ctypes.c_void_p * n)(*([4096] * n))
+    assert lib.srmdp_solve_batch(0, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -1
+    assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, total - 1, None, None) == -3
