@@ -14,6 +14,8 @@ Prints one JSON line:
                per launch / average launch time (HIP events around the step
                kernels, on the stream they run on) against the VALU issue peak
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  ragged_batch the 64-instance ragged batch of d = 2 cos problems in one launch
+               per global step, against the same instances solved one by one
   error_matched the full-sweep wall time of the plain estimator and of the
                learned control variate (online training included) at several M,
                with the error of y(0, x0) over seeds, and the control variate's
@@ -188,6 +190,45 @@ def error_matched(S, cfg: dict, seeds, m_cv, root_paths: int, stream) -> dict:
             "target_speedup": 4.0}
 
 
+def ragged_batch(S, stream) -> dict:
+    """The ragged batch workload (64 d = 2 cos instances, K 16^2..64^2,
+    M 64..1024, N 10..50, binary32): one batched sweep (one launch per global
+    step), with heuristic and with autotuned lanes, against the 64 sweeps one
+    after the other; HIP events on the library's stream, after a warm-up."""
+    import torch
+    cfgs = W.ragged_batch()
+    args = [_product_args(S, c) for c in cfgs]
+    P = [a[0] for a in args]
+    G = [a[1] for a in args]
+    O = [a[2] for a in args]
+    tables = [S.srmdp.alloc_table(p, g, o) for p, g, o in args]
+    ws = torch.empty(S.workspace_bytes_batch(P, G, O), dtype=torch.uint8, device="cuda")
+    wss = [S.srmdp.alloc_workspace(p, g, o) for p, g, o in args]
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            fn()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            fn()
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    batch_ms = timed(lambda: S.solve_batch(P, G, O, tables=tables, workspace=ws, stream=stream, stats=False))
+    single_ms = timed(lambda: [S.solve(p, g, o, table=t, workspace=w, stream=stream, stats=False)
+                               for (p, g, o), t, w in zip(args, tables, wss)])
+    for o in O:
+        o.flags |= S.F_AUTOTUNE
+    _, st = S.solve_batch(P, G, O, tables=tables, workspace=ws, stream=stream)  # tunes once per shape
+    tuned_ms = timed(lambda: S.solve_batch(P, G, O, tables=tables, workspace=ws, stream=stream, stats=False))
+    steps = sum(W.path_steps(c) for c in cfgs)
+    return {"instances": len(cfgs), "path_steps": steps, "batch_ms": batch_ms,
+            "batch_ms_autotuned": tuned_ms, "one_by_one_ms": single_ms,
+            "path_steps_per_s": steps / (min(batch_ms, tuned_ms) / 1e3),
+            "autotuned_lanes": sorted({s["lanes_per_cube"] for s in st})}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +241,8 @@ def main() -> int:
     ap.add_argument("--no-error-matched", action="store_true",
                     help="skip the plain vs control-variate comparison at matched error")
     ap.add_argument("--em-seeds", type=int, default=4)
+    ap.add_argument("--no-ragged-batch", action="store_true",
+                    help="skip the 64-instance ragged batch measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run 10 plain device-to-device copies of this many bytes "
                          "(calibrates the HBM byte counters of the profiler)")
@@ -297,6 +340,8 @@ def main() -> int:
         "y0_exact_continuous": 0.5 if cfg["terminal"] == "logistic" else None,
         "lanes_per_cube": stats[0]["lanes_per_cube"],
     }
+    if not args.no_ragged_batch:
+        out["ragged_batch"] = ragged_batch(S, stream)
     if not args.no_error_matched and cfg["driver"] == "logistic":
         m_cv = [m for m in (cfg["M"] // 2, cfg["M"] // 4) if m >= cfg["d"] + 1 and m % 8 == 0]
         out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), m_cv, 1 << 18, stream)

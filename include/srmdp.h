@@ -212,8 +212,8 @@ srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *gr
 
 /* Ragged batch: n independent instances (host arrays of n problems, grids and
  * options; same d, basis, precision and look-up mode; any K, M, N, seeds,
- * instance tags and driver parameters; full plain sweeps, lanes_per_cube
- * <= 64).  One launch per global step g = 0..max N - 1 runs backward step
+ * instance tags and driver parameters; full plain sweeps; lanes_per_cube 0
+ * means one lane per simulation up to 256).  One launch per global step g = 0..max N - 1 runs backward step
  * N_b - 1 - g of every instance with N_b > g, over the flattened list of
  * their stratum groups; with SRMDP_F_GRAPH in opts[0].flags the launches are
  * replayed from a cached hipGraph.  tables: host array of n device tables

@@ -731,8 +731,6 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
         }
         if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0)
             return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
-        if (O[b].lanes_per_cube > 64)
-            return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches use at most 64 lanes per stratum", b);
         bp.gmax = std::max(bp.gmax, P[b].N);
     }
     if (!dimension_compiled(P[0].d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", P[0].d);
@@ -750,9 +748,12 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
     return SRMDP_OK;
 }
 
-// Lanes per instance: explicit, tuned (cached per shape) or the heuristic, at
-// most 64.  Tuning runs kernels and synchronises, so it happens before any
-// capture.
+// Lanes per instance: explicit, tuned (cached per shape) or one lane per
+// simulation up to 256.  A batch runs workgroups of 256 threads, each holding
+// 256 / L strata, so that the LDS of a workgroup, about 256 (M / L) rows, stays
+// similar across instances of very different M (the workgroup's LDS is the
+// largest any instance needs).  Tuning runs kernels and synchronises, so it
+// happens before any capture.
 srmdp_status resolve_batch_lanes(int n, const srmdp_problem *P, const srmdp_grid *G, const srmdp_options *O,
                                  void *const *tables, unsigned char *ws, BatchPlan &bp, hipStream_t st)
 {
@@ -764,9 +765,11 @@ srmdp_status resolve_batch_lanes(int n, const srmdp_problem *P, const srmdp_grid
             srmdp_status rc = tune_cached(&P[b], &G[b], &o, bp.shapes[b], bp.nb, tables[b], ws + bp.ws_off[b], st,
                                           &L, nullptr, false);
             if (rc != SRMDP_OK) return rc;
-            if (L > 64) L = 64;
         }
-        if (L == 0) L = auto_lanes(O[b].M);
+        if (L == 0) {
+            L = 8;
+            while (L < O[b].M && L < 256) L *= 2;
+        }
         bp.lanes[b] = L;
     }
     return SRMDP_OK;
@@ -777,7 +780,7 @@ srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, c
                            void *const *tables, unsigned char *ws, const BatchPlan &bp, hipStream_t st)
 {
     const int is_float = sizeof(R) == 4;
-    const unsigned threads = 64;
+    const unsigned threads = 256;
     std::vector<BatchInstance<R>> inst(n);
     size_t lds = 0;
     uint32_t first = 0;

@@ -380,13 +380,13 @@ template <typename R, int D, int NB, bool CV = false>
 struct CubeLds {
     static constexpr int SW = NB + D + 2 + (CV ? 2 : 0);
     static constexpr int F64 = 2 * NB * NB + 2 * (1 + D) * NB + 2 + NB;
-    static __host__ __device__ size_t bytes(int M)
-    {
-        size_t rows = (size_t)M * SW * sizeof(R);
-        rows = (rows + 15) & ~(size_t)15;
-        return rows + (size_t)F64 * sizeof(double);
-    }
+    static constexpr int NE = NB * (NB + 1) / 2 + D * NB;  // Gram and z right-hand-side entries
 };
+
+// Sums over the samples run in chunks of kChunk in sample order; with more
+// than one chunk the chunk sums (one per lane and entry, in parallel) are
+// added in chunk order.  The order depends on M only, not on the lanes.
+constexpr int kChunk = 64;
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so block b
 // runs on XCD b % 8.  Give each XCD a contiguous range of strata so that
@@ -445,6 +445,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     double *beta = RHS + REC;
     double *flag = beta + REC;
     double *zsum = flag + 2;
+    double *part = zsum + NB;  // [entries][chunks] partial sums when M > kChunk
+    const int nch = (M + kChunk - 1) / kChunk;
 
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The
     //    network needs every lane of a wavefront, so with the control variate
@@ -468,35 +470,63 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     }
     __syncthreads();
 
-    // 2. Gram entries (a <= b) and z right-hand sides, one entry per lane,
-    //    binary64 sums over the M samples in sample order.
+    // 2. Gram entries (a <= b) and z right-hand sides: binary64 sums over the
+    //    M samples, one (entry, chunk) pair per lane, then the chunks in order.
     constexpr int NG = NB * (NB + 1) / 2;
-    constexpr int NE = NG + D * NB;
-    if (live) {
-        for (int e = t; e < NE; e += L) {
-            double acc = 0.0;
-            if (e < NG) {
-                int r = 0, rem = e;
-                while (rem >= NB - r) {
-                    rem -= NB - r;
-                    ++r;
-                }
-                const int c = r + rem;
-                for (int m = 0; m < M; ++m) {
-                    const R *row = rows + (size_t)m * SW;
-                    acc += (double)row[r] * (double)row[c];
-                }
-                G[r * NB + c] = acc;
-                G[c * NB + r] = acc;
-            } else {
-                const int l = (e - NG) / NB, b = (e - NG) % NB;
-                for (int m = 0; m < M; ++m) {
-                    const R *row = rows + (size_t)m * SW;
-                    acc += (double)row[b] * ((double)row[NB + D] * (double)row[NB + l]);
-                }
-                RHS[(1 + l) * NB + b] = acc * a.inv_dt;
+    constexpr int NE = Lay::NE;
+    auto gram_sum = [&](int e, int m0, int m1) {
+        double acc = 0.0;
+        if (e < NG) {
+            int r = 0, rem = e;
+            while (rem >= NB - r) {
+                rem -= NB - r;
+                ++r;
+            }
+            const int c = r + rem;
+            for (int m = m0; m < m1; ++m) {
+                const R *row = rows + (size_t)m * SW;
+                acc += (double)row[r] * (double)row[c];
+            }
+        } else {
+            const int l = (e - NG) / NB, b = (e - NG) % NB;
+            for (int m = m0; m < m1; ++m) {
+                const R *row = rows + (size_t)m * SW;
+                acc += (double)row[b] * ((double)row[NB + D] * (double)row[NB + l]);
             }
         }
+        return acc;
+    };
+    auto gram_store = [&](int e, double acc) {
+        if (e < NG) {
+            int r = 0, rem = e;
+            while (rem >= NB - r) {
+                rem -= NB - r;
+                ++r;
+            }
+            const int c = r + rem;
+            G[r * NB + c] = acc;
+            G[c * NB + r] = acc;
+        } else {
+            const int l = (e - NG) / NB, b = (e - NG) % NB;
+            RHS[(1 + l) * NB + b] = acc * a.inv_dt;
+        }
+    };
+    if (nch == 1) {
+        if (live)
+            for (int e = t; e < NE; e += L) gram_store(e, gram_sum(e, 0, M));
+    } else {
+        if (live)
+            for (int w = t; w < NE * nch; w += L) {
+                const int e = w / nch, c = w % nch;
+                part[w] = gram_sum(e, c * kChunk, min(M, (c + 1) * kChunk));
+            }
+        __syncthreads();
+        if (live)
+            for (int e = t; e < NE; e += L) {
+                double acc = 0.0;
+                for (int c = 0; c < nch; ++c) acc += part[e * nch + c];
+                gram_store(e, acc);
+            }
     }
     __syncthreads();
 
@@ -589,16 +619,31 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     }
     __syncthreads();
 
-    // 6. y right-hand side and solve
-    if (live) {
-        for (int b = t; b < NB; b += L) {
-            double acc = 0.0;
-            for (int m = 0; m < M; ++m) {
-                const R *row = rows + (size_t)m * SW;
-                acc += (double)row[b] * (double)row[NB + D];
-            }
-            RHS[b] = acc;
+    // 6. y right-hand side (chunked as the Gram sums) and solve
+    auto y_sum = [&](int b, int m0, int m1) {
+        double acc = 0.0;
+        for (int m = m0; m < m1; ++m) {
+            const R *row = rows + (size_t)m * SW;
+            acc += (double)row[b] * (double)row[NB + D];
         }
+        return acc;
+    };
+    if (nch == 1) {
+        if (live)
+            for (int b = t; b < NB; b += L) RHS[b] = y_sum(b, 0, M);
+    } else {
+        if (live)
+            for (int w = t; w < NB * nch; w += L) {
+                const int b = w / nch, c = w % nch;
+                part[w] = y_sum(b, c * kChunk, min(M, (c + 1) * kChunk));
+            }
+        __syncthreads();
+        if (live)
+            for (int b = t; b < NB; b += L) {
+                double acc = 0.0;
+                for (int c = 0; c < nch; ++c) acc += part[b * nch + c];
+                RHS[b] = acc;
+            }
     }
     __syncthreads();
     if (live) {

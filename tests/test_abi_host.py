@@ -205,7 +205,6 @@ def test_batch_workspace_and_rejections():
     single = sum(S.workspace_bytes(p, g, o) for p, g, o in zip(P, G, O))
     assert total >= single
     for bad, status in [(_batch(S, ds=(2, 3)), -1),                 # different d
-                        (_batch(S, lanes_per_cube=128), -2),        # more than 64 lanes
                         (_batch(S, step_hi=2), -2),                 # partial sweeps
                         (_batch(S, cv=1, cv_params=_FakeTensor()), -2)]:
         n, Pa, Ga, Oa = S.srmdp._arrays(*bad)
