@@ -181,6 +181,10 @@ def error_matched(S, cfg: dict, seeds, m_cv, root_paths: int, stream) -> dict:
 
     plain = summary(cfg["M"], False)
     cv = [summary(M, True) for M in m_cv]
+    for c in cv:  # the same M without the control variate: the variance ratio at equal M
+        p = summary(c["M"], False)
+        c["plain_same_M"] = p
+        c["mse_ratio_same_M"] = (p["y0_rmse"] / c["y0_rmse"]) ** 2 if c["y0_rmse"] > 0 else None
     ok = [c for c in cv if c["y0_rmse"] <= plain["y0_rmse"]]
     best = min(ok, key=lambda c: c["ms"]) if ok else None
     return {"read_out": f"ROOT y(0,x0), {root_paths} paths", "exact": 0.5, "truncation": "C_y = 1",

@@ -406,3 +406,60 @@ def test_online_network_reduces_the_error_of_the_fits():
     _say(f"[gpu] MSE ratio plain / control variate, [(y, z) at t=0, t=0.5]: {ratio.tolist()}")
     assert np.all(ratio[:, 0] > 1.5)
     assert np.all(ratio[:, 1] > 1.5)
+
+
+def test_frozen_network_sweep_graph_replays():
+    """The control-variate sweep (frozen network, stride 2, centred) captured in a
+    hipGraph: three replays, each equal to the eager sweep."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = dict(W.config("cfg2"), N=6, cells=[4] * 4, M=32)
+    P, G, Opt = product_args(cfg)
+    params = S.mlp_init(5, 4, 7)
+    Opt.cv, Opt.cv_params, Opt.cv_stride = S.CV_FROZEN, params, 2
+    Opt.flags |= S.F_CV_CENTER_Z
+    eager, _ = S.solve(P, G, Opt)
+    Opt.flags |= S.F_GRAPH
+    stream = torch.cuda.Stream()
+    ws = S.srmdp.alloc_workspace(P, G, Opt)
+    table = torch.zeros_like(eager)
+    for rep in range(3):
+        table.zero_()
+        torch.cuda.synchronize()
+        _say(f"[gpu] control-variate graph replay {rep}")
+        with torch.cuda.stream(stream):
+            S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        assert torch.equal(table, eager)
+    S.release_graphs()
+
+
+def test_control_variate_keeps_the_mean_of_the_fits():
+    """Unbiasedness: with a linear driver (f = -r y + kappa sum z) the fitted
+    coefficients are linear in the responses, so their expectation is the same
+    with and without the network's martingale terms and the centring.  Over 16
+    seeds, the mean difference (control variate - plain) of the coefficients,
+    averaged per step and component over strata and basis functions, stays
+    within 4 standard errors of zero, while the control variate moves single
+    runs by far more (it changes the noise)."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = dict(W.config("cfg1"), d=2, N=6, lo=[-2.0] * 2, hi=[2.0] * 2, cells=[6, 6], M=32, prec="fp32",
+               driver="linear", terminal="cos", r=0.2, kappa=0.3)
+    params = S.mlp_init(3, 2, 11)
+    diffs = []
+    for seed in range(1, 17):
+        P, G, Opt = product_args(cfg, seed=seed)
+        plain, _ = S.solve(P, G, Opt)
+        Opt.cv, Opt.cv_params, Opt.cv_stride = S.CV_FROZEN, params, 2
+        Opt.flags |= S.F_CV_CENTER_Z
+        cv, _ = S.solve(P, G, Opt)
+        torch.cuda.synchronize()
+        d = (cv - plain).double().cpu().numpy()
+        diffs.append(d.mean(axis=(1, 3)))  # per (step, component)
+    diffs = np.array(diffs)
+    mean = diffs.mean(axis=0)
+    se = diffs.std(axis=0, ddof=1) / math.sqrt(diffs.shape[0])
+    _say(f"[gpu] mean difference / standard error per (step, component): {np.round(mean / se, 2).tolist()}")
+    assert np.all(np.abs(mean) <= 4.0 * se)
+    assert np.max(np.abs(diffs)) > 10 * np.max(se)
