@@ -136,7 +136,7 @@ def _product_args(S, cfg: dict):
 # Learned control variate of the error-matched comparison: the network is
 # evaluated every CV_STRIDE steps, trained online with CV_TRAIN after each
 # step, and the z response is centred.
-CV_STRIDE = 8
+CV_STRIDE = 16
 CV_TRAIN = dict(updates_per_step=4, batch=512, lr=2e-3)
 
 
