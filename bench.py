@@ -20,6 +20,9 @@ Prints one JSON line:
                learned control variate (online training included) at several M,
                with the error of y(0, x0) over seeds, and the control variate's
                time at the smallest M that reaches the plain error
+  cv_equal_M   the d = 4 logistic workload at M = 32: plain against the online
+               control variate, same draws; errors of the fitted y and z against
+               the closed form and their variance across seeds
 """
 from __future__ import annotations
 
@@ -194,6 +197,98 @@ def error_matched(S, cfg: dict, seeds, m_cv, root_paths: int, stream) -> dict:
             "target_speedup": 4.0}
 
 
+# Forms of the control variate reported at equal M on the d = 4 workload: the
+# error-matched comparison's form, and the network evaluated at every step with
+# four times the training.
+CV_FORMS_EQUAL_M = (
+    {"stride": CV_STRIDE, **CV_TRAIN},
+    {"stride": 1, "updates_per_step": 16, "batch": 512, "lr": 2e-3},
+)
+
+
+def cv_equal_m(S, cfg: dict, seeds, stream, n_points: int = 4096) -> dict:
+    """Plain estimator against the online control variate at the workload's M
+    (same draws, same seeds): full-sweep time, and for the fitted y_i, z_i at
+    t = 0 and t = T/2 on points drawn uniformly from the central region
+    [-1.5, 1.5]^d, the RMS error against the closed form
+    u = 1 / (1 + exp(-(t + sum x))), z_l = u (1 - u), and the variance across
+    seeds (the mean over the points of the per-point sample variance).  The
+    ratios plain / control variate of both are the reported gains."""
+    import numpy as np
+    import torch
+    d = cfg["d"]
+    rng = np.random.default_rng(12345)
+    pts = rng.uniform(-1.5, 1.5, (n_points, d))
+    x = torch.from_numpy(pts).to("cuda")
+    steps = (0, cfg["N"] // 2)
+
+    def exact(i):
+        t = i * cfg["T"] / cfg["N"]
+        u = 1.0 / (1.0 + np.exp(-(t + pts.sum(axis=1))))
+        return u, u * (1.0 - u)
+
+    def run(form, seed):
+        c = dict(cfg, seed=seed, clamp_y=1.0)
+        P, G, Opt = _product_args(S, c)
+        if form is not None:
+            Opt.cv, Opt.cv_stride = S.CV_ONLINE, form["stride"]
+            Opt.flags |= S.F_CV_CENTER_Z
+            Opt.cv_train = S.TrainConfig(**{k: v for k, v in form.items() if k != "stride"})
+            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+        table = S.srmdp.alloc_table(P, G, Opt)
+        ws = S.srmdp.alloc_workspace(P, G, Opt)
+        times, st = [], None
+        for rep in range(2):  # the first call warms up
+            if form is not None:
+                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                ev0.record(stream)
+                _, st = S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=rep == 1)
+                ev1.record(stream)
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+        fits = []
+        for i in steps:
+            y, z = S.evaluate(P, G, Opt.basis, Opt.prec, table, i, x, stream=stream)
+            torch.cuda.synchronize()
+            fits.append((y.cpu().numpy(), z.cpu().numpy()))
+        return times[-1], fits, st
+
+    def summary(form):
+        rows = [run(form, s) for s in seeds]
+        out = {"ms": sum(r[0] for r in rows) / len(rows)}
+        for n, i in enumerate(steps):
+            u, zu = exact(i)
+            ys = np.stack([r[1][n][0] for r in rows])          # [seeds, points]
+            zs = np.stack([r[1][n][1] for r in rows])          # [seeds, points, q]
+            out[f"i{i}"] = {
+                "y_rmse": float(np.sqrt(np.mean((ys - u) ** 2))),
+                "z_rmse": float(np.sqrt(np.mean((zs - zu[None, :, None]) ** 2))),
+                "y_var": float(np.mean(np.var(ys, axis=0, ddof=1))),
+                "z_var": float(np.mean(np.var(zs, axis=0, ddof=1))),
+            }
+        if form is not None:
+            out["form"] = dict(form, centred_z=True)
+            out["train_loss_first_last"] = [rows[-1][2]["cv_loss_first"], rows[-1][2]["cv_loss_last"]]
+        return out
+
+    plain = summary(None)
+    forms = []
+    for form in CV_FORMS_EQUAL_M:
+        c = summary(form)
+        for i in steps:
+            p, v = plain[f"i{i}"], c[f"i{i}"]
+            v["mse_ratio_y"] = (p["y_rmse"] / v["y_rmse"]) ** 2
+            v["mse_ratio_z"] = (p["z_rmse"] / v["z_rmse"]) ** 2
+            v["var_ratio_y"] = p["y_var"] / v["y_var"]
+            v["var_ratio_z"] = p["z_var"] / v["z_var"]
+        forms.append(c)
+    return {"workload": cfg["name"], "M": cfg["M"], "seeds": list(seeds), "truncation": "C_y = 1",
+            "steps": {f"i{i}": i * cfg["T"] / cfg["N"] for i in steps},
+            "points": f"{n_points} uniform on [-1.5, 1.5]^{d}", "plain": plain, "cv": forms}
+
+
 def ragged_batch(S, stream) -> dict:
     """The ragged batch workload (64 d = 2 cos instances, K 16^2..64^2,
     M 64..1024, N 10..50, binary32): one batched sweep (one launch per global
@@ -245,6 +340,8 @@ def main() -> int:
     ap.add_argument("--no-error-matched", action="store_true",
                     help="skip the plain vs control-variate comparison at matched error")
     ap.add_argument("--em-seeds", type=int, default=4)
+    ap.add_argument("--no-cv-equal-m", action="store_true",
+                    help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
     ap.add_argument("--no-ragged-batch", action="store_true",
                     help="skip the 64-instance ragged batch measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -349,6 +446,8 @@ def main() -> int:
     if not args.no_error_matched and cfg["driver"] == "logistic":
         m_cv = [m for m in (cfg["M"] // 2, cfg["M"] // 4) if m >= cfg["d"] + 1 and m % 8 == 0]
         out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), m_cv, 1 << 18, stream)
+    if not args.no_cv_equal_m:
+        out["cv_equal_M"] = cv_equal_m(S, W.config("cfg4"), range(1, args.em_seeds + 1), stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
