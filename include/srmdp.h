@@ -118,8 +118,8 @@ typedef struct {
  * adapted, so still of mean zero), dividing its cost by s.  With
  * SRMDP_F_CV_CENTER_Z the z response S' dW_i / dt also loses
  * y_{i+1}(X_i) dW_i / dt (g(X_i) when i + 1 = N), of conditional mean zero too.
- * Binary32 sweeps only; M must be a multiple of 8 and of the lanes per
- * stratum, which must divide 64.  The ROOT read-out does not use it. */
+ * Binary32 sweeps only, with at most 64 lanes per stratum (any M >= nb).
+ * The ROOT read-out does not use it. */
 typedef enum { SRMDP_CV_NONE = 0, SRMDP_CV_FROZEN = 1, SRMDP_CV_ONLINE = 2 } srmdp_cv;
 
 #define SRMDP_MLP_HIDDEN 64
@@ -301,11 +301,15 @@ srmdp_status srmdp_mlp_backward(int32_t in, int32_t out, const void *packed, con
  * adam_v [P] are the moment estimates (zero before the first step) and adam_t0
  * the number of steps taken before.  params is updated in place; packed_out
  * receives the packed network; loss (device [updates] or NULL) the batch loss
- * before each step.  One workgroup. */
+ * before each step.  Each update is two launches: the batch's gradient over
+ * batch / 256 workgroups (partial sums in the workspace, device,
+ * srmdp_mlp_train_workspace_bytes() bytes), then the Adam step over the
+ * parameters, which sums the partials in workgroup order. */
+size_t srmdp_mlp_train_workspace_bytes(int32_t in, int32_t out, const srmdp_mlp_train_config *cfg);
 srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam_m, float *adam_v,
                              int64_t adam_t0, const float *x16, const float *z16, int64_t n,
                              const srmdp_mlp_train_config *cfg, void *packed_out, float *loss,
-                             void *stream);
+                             void *workspace, size_t ws_bytes, void *stream);
 
 /* Releases cached hipGraph executables. */
 void srmdp_release_graphs(void);

@@ -220,98 +220,107 @@ __global__ void grad_reduce_kernel(const float *__restrict__ partial, int nblock
 struct TrainLds {
     bf16x8 frag[kFrags * 64];
     float bias[kBiasFloats];
-    float theta[kMaxParams];
     GradScratch u;
     float loss[4];
 };
 
-// `updates` Adam steps on the mean squared error of z_theta against the
-// targets, one workgroup: each update takes `batch` consecutive pairs
-// (cyclically) of x16 / z16, forward and backward passes on the matrix cores,
-// gradients summed over the four wavefronts in a fixed order, then the Adam
-// step on the binary32 master weights, each thread rewriting the bf16 slots
-// of the parameters it owns.
-__global__ void __launch_bounds__(256) mlp_train_kernel(MlpTrainArgs A)
+// Gradient of Adam update u, spread over batch / 256 workgroups.  Workgroup b
+// takes the 256 pairs from (u batch + 256 b) mod S of x16 / z16, 64 per
+// wavefront: forward and backward passes on the matrix cores with the packed
+// network of packed_out, the loss gradient 2 (z_theta - z) / batch, the
+// wavefronts' gradients summed in wavefront order.  partial [b][pstride]
+// receives the gradient (P values) and the sum of squared errors (entry P).
+__global__ void __launch_bounds__(256) mlp_train_grad_kernel(MlpTrainArgs A, int u, float *__restrict__ partial,
+                                                            int pstride)
 {
     __shared__ __align__(16) TrainLds L;
+    stage_weights(A.packed_out, reinterpret_cast<unsigned char *>(L.bias), kPackedBiasBytes);
+    stage_weights(A.packed_out + kPackedBiasBytes, reinterpret_cast<unsigned char *>(L.frag),
+                  kPackedBytes - kPackedBiasBytes);
+    __syncthreads();
     const MlpShape s{A.in, A.out};
-    const int P = s.count();
     const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, wave = tid >> 6;
-    for (int p = tid; p < P; p += 256) L.theta[p] = A.theta[p];
-    __syncthreads();
-    pack_weights(s, L.theta, reinterpret_cast<__bf16 *>(L.frag), L.bias, tid, 256);
-    __syncthreads();
-    __bf16 *frag16 = reinterpret_cast<__bf16 *>(L.frag);
     const MlpWeights w{L.frag, L.bias};
     const float gscale = 2.0f / (float)A.batch;
-    const int groups = A.batch / 256;
-    for (int u = 0; u < A.updates; ++u) {
-        MlpGrad acc;
-        acc.clear();
-        float lsum = 0.0f;
-        for (int g = 0; g < groups; ++g) {
-            const int64_t base = ((int64_t)u * A.batch + (int64_t)(4 * g + wave) * 64) % A.S;
-            const float4 *xs = reinterpret_cast<const float4 *>(A.x16 + (base + lane) * 16);
-            float in16[16];
+    MlpGrad acc;
+    acc.clear();
+    float lsum = 0.0f;
+    const int64_t base = ((int64_t)u * A.batch + (int64_t)(4 * blockIdx.x + wave) * 64) % A.S;
+    const float4 *xs = reinterpret_cast<const float4 *>(A.x16 + (base + lane) * 16);
+    float in16[16];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float4 q = xs[v];
-                in16[4 * v] = q.x;
-                in16[4 * v + 1] = q.y;
-                in16[4 * v + 2] = q.z;
-                in16[4 * v + 3] = q.w;
-            }
-            TileInput op[2];
-            input_operands(in16, op[0], op[1]);
+    for (int v = 0; v < 4; ++v) {
+        const float4 q = xs[v];
+        in16[4 * v] = q.x;
+        in16[4 * v + 1] = q.y;
+        in16[4 * v + 2] = q.z;
+        in16[4 * v + 3] = q.w;
+    }
+    TileInput op[2];
+    input_operands(in16, op[0], op[1]);
 #pragma unroll 1
-            for (int nt = 0; nt < 2; ++nt) {
-                MlpTile keep;
-                const f32x16 yv = mlp_tile_forward<true>(w, lane, op[nt], &keep);
-                const int64_t sm = base + 32 * nt + (lane & 31);
-                const float4 za = *reinterpret_cast<const float4 *>(A.z16 + sm * 16 + 4 * h);
-                const float4 zb = *reinterpret_cast<const float4 *>(A.z16 + sm * 16 + 8 + 4 * h);
-                const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
-                float gr[8];
+    for (int nt = 0; nt < 2; ++nt) {
+        MlpTile keep;
+        const f32x16 yv = mlp_tile_forward<true>(w, lane, op[nt], &keep);
+        const int64_t sm = base + 32 * nt + (lane & 31);
+        const float4 za = *reinterpret_cast<const float4 *>(A.z16 + sm * 16 + 4 * h);
+        const float4 zb = *reinterpret_cast<const float4 *>(A.z16 + sm * 16 + 8 + 4 * h);
+        const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+        float gr[8];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const float diff = c_row(r, h) < s.out ? yv[r] - zz[r] : 0.0f;
-                    lsum += diff * diff;
-                    gr[r] = gscale * diff;
-                }
-                mlp_tile_backward(w, lane, keep, op[nt], gr, L.u.xp[wave][0], L.u.xp[wave][1], acc);
-            }
+        for (int r = 0; r < 8; ++r) {
+            const float diff = c_row(r, h) < s.out ? yv[r] - zz[r] : 0.0f;
+            lsum += diff * diff;
+            gr[r] = gscale * diff;
         }
+        mlp_tile_backward(w, lane, keep, op[nt], gr, L.u.xp[wave][0], L.u.xp[wave][1], acc);
+    }
 #pragma unroll
-        for (int m = 1; m < 64; m <<= 1) lsum += __shfl_xor(lsum, m, 64);
-        if (lane == 0) L.loss[wave] = lsum;
-        __syncthreads();  // every wavefront is done with the transpose buffers
-        mlp_grad_flush(s, lane, acc, L.u.part[wave], false);
-        __syncthreads();
+    for (int m = 1; m < 64; m <<= 1) lsum += __shfl_xor(lsum, m, 64);
+    if (lane == 0) L.loss[wave] = lsum;
+    __syncthreads();  // every wavefront is done with the transpose buffers
+    mlp_grad_flush(s, lane, acc, L.u.part[wave], false);
+    __syncthreads();
+    const int P = s.count();
+    float *out = partial + (size_t)blockIdx.x * pstride;
+    for (int p = tid; p < P; p += 256)
+        out[p] = ((L.u.part[0][p] + L.u.part[1][p]) + L.u.part[2][p]) + L.u.part[3][p];
+    if (tid == 0) out[P] = ((L.loss[0] + L.loss[1]) + L.loss[2]) + L.loss[3];
+}
+
+// Adam step of update u: the gradient of each parameter is the sum of the
+// nblk workgroup partials in workgroup order; theta (binary32 master weights)
+// and the moments are updated in place, and the parameter's bf16 slots (or
+// its bias entry) are rewritten in the packed network.  Every other byte of
+// packed_out keeps what the packing of theta put there.
+__global__ void __launch_bounds__(256) mlp_adam_kernel(MlpTrainArgs A, int u, const float *__restrict__ partial,
+                                                      int nblk, int pstride)
+{
+    const MlpShape s{A.in, A.out};
+    const int P = s.count();
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < P) {
+        float gp = partial[p];
+        for (int b = 1; b < nblk; ++b) gp += partial[(size_t)b * pstride + p];
         const float t = (float)(A.adam_t0 + u + 1);
         const float bc1 = 1.0f - powf(A.beta1, t), bc2 = 1.0f - powf(A.beta2, t);
-#pragma unroll 4
-        for (int p = tid; p < P; p += 256) {
-            const float gp = ((L.u.part[0][p] + L.u.part[1][p]) + L.u.part[2][p]) + L.u.part[3][p];
-            const float m = A.beta1 * A.adam_m[p] + (1.0f - A.beta1) * gp;
-            const float v = A.beta2 * A.adam_v[p] + (1.0f - A.beta2) * gp * gp;
-            A.adam_m[p] = m;
-            A.adam_v[p] = v;
-            const float th = L.theta[p] - A.lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
-            L.theta[p] = th;
-            int slot[2], bslot;
-            const int n = param_slots(s, p, slot, &bslot);
-            for (int e = 0; e < n; ++e) frag16[slot[e]] = (__bf16)th;
-            if (bslot >= 0) L.bias[bslot] = th;
-        }
-        if (tid == 0 && A.loss) A.loss[u] = (L.loss[0] + L.loss[1] + L.loss[2] + L.loss[3]) / (float)A.batch;
-        __syncthreads();
+        const float m = A.beta1 * A.adam_m[p] + (1.0f - A.beta1) * gp;
+        const float v = A.beta2 * A.adam_v[p] + (1.0f - A.beta2) * gp * gp;
+        A.adam_m[p] = m;
+        A.adam_v[p] = v;
+        const float th = A.theta[p] - A.lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
+        A.theta[p] = th;
+        int slot[2], bslot;
+        const int n = param_slots(s, p, slot, &bslot);
+        __bf16 *frag16 = reinterpret_cast<__bf16 *>(A.packed_out + kPackedBiasBytes);
+        for (int e = 0; e < n; ++e) frag16[slot[e]] = (__bf16)th;
+        if (bslot >= 0) reinterpret_cast<float *>(A.packed_out)[bslot] = th;
     }
-    for (int p = tid; p < P; p += 256) A.theta[p] = L.theta[p];
-    float *pb = reinterpret_cast<float *>(A.packed_out);
-    for (int i = tid; i < kBiasFloats; i += 256) pb[i] = L.bias[i];
-    const uint4 *src = reinterpret_cast<const uint4 *>(L.frag);
-    uint4 *dst = reinterpret_cast<uint4 *>(A.packed_out + kPackedBiasBytes);
-    for (int v = tid; v < kFrags * 64; v += 256) dst[v] = src[v];
+    if (p == 0 && A.loss) {
+        float l = 0.0f;
+        for (int b = 0; b < nblk; ++b) l += partial[(size_t)b * pstride + P];
+        A.loss[u] = l / (float)A.batch;
+    }
 }
 
 // The training pairs of step i: pair s draws a stratum k and a simulation m
@@ -400,9 +409,22 @@ hipError_t launch_mlp_backward(int in, int out, const void *packed, const float 
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(const MlpTrainArgs &t, hipStream_t st)
+int mlp_train_partial_stride(int in, int out) { return (MlpShape{in, out}.count() + 1 + 63) & ~63; }
+
+size_t mlp_train_partial_bytes(int in, int out, int batch)
 {
-    hipLaunchKernelGGL(mlp_train_kernel, dim3(1), dim3(256), 0, st, t);
+    return (size_t)(batch / 256) * mlp_train_partial_stride(in, out) * sizeof(float);
+}
+
+hipError_t launch_mlp_train(const MlpTrainArgs &t, float *partial, hipStream_t st)
+{
+    const int nblk = t.batch / 256, pstride = mlp_train_partial_stride(t.in, t.out);
+    const int P = MlpShape{t.in, t.out}.count();
+    for (int u = 0; u < t.updates; ++u) {
+        hipLaunchKernelGGL(mlp_train_grad_kernel, dim3(nblk), dim3(256), 0, st, t, u, partial, pstride);
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((P + 255) / 256), dim3(256), 0, st, t, u,
+                           (const float *)partial, nblk, pstride);
+    }
     return hipGetLastError();
 }
 

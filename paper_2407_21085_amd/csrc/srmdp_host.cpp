@@ -132,11 +132,8 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
             return fail(SRMDP_E_UNSUPPORTED, "the control variate takes d + 1 <= %d inputs", kMlpMaxIn);
         if (o->prec != SRMDP_FP32)
             return fail(SRMDP_E_UNSUPPORTED, "the control variate runs in binary32 sweeps only");
-        if (o->M % 8 != 0)
-            return fail(SRMDP_E_UNSUPPORTED, "the control variate needs M a multiple of 8 (M = %d)", o->M);
-        if (L != 0 && (L > 64 || o->M % L != 0))
-            return fail(SRMDP_E_UNSUPPORTED,
-                        "the control variate needs lanes_per_cube <= 64 dividing M (%d, M = %d)", L, o->M);
+        if (L > 64)
+            return fail(SRMDP_E_UNSUPPORTED, "the control variate needs lanes_per_cube <= 64 (%d)", L);
         if (o->cv == SRMDP_CV_ONLINE) {
             const srmdp_mlp_train_config &c = o->cv_train;
             if (c.updates_per_step < 1 || c.updates_per_step > 4096)
@@ -163,7 +160,7 @@ constexpr int kRootBlocks = 512;
 
 struct Layout {
     size_t counters, cellF, bsig, lookup, root_partial, root_out;
-    size_t cv_packed, cv_m, cv_v, cv_x, cv_z, cv_loss;  // control variate (0 = absent)
+    size_t cv_packed, cv_m, cv_v, cv_x, cv_z, cv_loss, cv_part;  // control variate (0 = absent)
     int64_t cv_pairs;                                    // training pairs per step
     size_t total;
 };
@@ -201,6 +198,8 @@ Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options 
             off = align_up(off + (size_t)L.cv_pairs * 16 * sizeof(float), 256);
             L.cv_loss = off;
             off = align_up(off + (size_t)s.N * o->cv_train.updates_per_step * sizeof(float), 256);
+            L.cv_part = off;
+            off = align_up(off + mlp_train_partial_bytes(s.d + 1, s.q, o->cv_train.batch), 256);
         }
     }
     L.total = off;
@@ -284,20 +283,16 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
 // Lanes per stratum: enough to give every lane one path up to a wavefront.
 // With the control variate every lane of a wavefront must run the same number
 // of paths: the largest power of two up to 64 that divides M.
-int auto_lanes(int M, bool cv = false)
+int auto_lanes(int M)
 {
     int L = 8;
-    if (cv) {
-        while (L < 64 && M % (2 * L) == 0) L *= 2;
-        return L;
-    }
     while (L < M && L < 64) L *= 2;
     return L;
 }
 
 int lanes_for(const srmdp_options *o)
 {
-    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M, o->cv != SRMDP_CV_NONE);
+    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
 }
 
 // One wavefront per workgroup when a stratum fits in one (several strata share
@@ -416,7 +411,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
                     t.eps = o->cv_train.eps;
                     t.packed_out = ws + lay.cv_packed;
                     t.loss = (float *)(ws + lay.cv_loss) + (size_t)(hi - i) * U;
-                    HIP_TRY(launch_mlp_train(t, st), "network training");
+                    HIP_TRY(launch_mlp_train(t, (float *)(ws + lay.cv_part), st), "network training");
                 }
                 launched = true;
             }
@@ -593,10 +588,9 @@ std::vector<int64_t> tune_key(const Shape &s, int nb, const srmdp_options *o, in
 
 bool lanes_valid(const srmdp_options *o, int L)
 {
-    if (o->cv != SRMDP_CV_NONE) return L <= 64 && o->M % L == 0;
     int cap = 8;
     while (cap < o->M && cap < 256) cap *= 2;
-    return L <= cap;
+    return L <= cap && (o->cv == SRMDP_CV_NONE || L <= 64);
 }
 
 template <typename R>
@@ -915,7 +909,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 101; }
+int32_t srmdp_abi_version(void) { return 102; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 
@@ -1183,15 +1177,22 @@ srmdp_status srmdp_mlp_backward(int32_t in, int32_t out, const void *packed, con
     return SRMDP_OK;
 }
 
+size_t srmdp_mlp_train_workspace_bytes(int32_t in, int32_t out, const srmdp_mlp_train_config *cfg)
+{
+    if (check_net(in, out) != SRMDP_OK || !cfg || cfg->batch < 256 || cfg->batch > 65536 || cfg->batch % 256 != 0)
+        return 0;
+    return mlp_train_partial_bytes(in, out, cfg->batch);
+}
+
 srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam_m, float *adam_v, int64_t adam_t0,
                              const float *x16, const float *z16, int64_t n, const srmdp_mlp_train_config *cfg,
-                             void *packed_out, float *loss, void *stream)
+                             void *packed_out, float *loss, void *workspace, size_t ws_bytes, void *stream)
 {
     g_error.clear();
     srmdp_status rc = check_net(in, out);
     if (rc != SRMDP_OK) return rc;
-    if (!params || !adam_m || !adam_v || !x16 || !z16 || !cfg || !packed_out)
-        return fail(SRMDP_E_INVALID, "params, adam_m, adam_v, x16, z16, cfg and packed_out are required");
+    if (!params || !adam_m || !adam_v || !x16 || !z16 || !cfg || !packed_out || !workspace)
+        return fail(SRMDP_E_INVALID, "params, adam_m, adam_v, x16, z16, cfg, packed_out and workspace are required");
     if (n < 64 || n % 64 != 0) return fail(SRMDP_E_INVALID, "n must be a positive multiple of 64");
     if (adam_t0 < 0) return fail(SRMDP_E_INVALID, "adam_t0 < 0");
     if (((uintptr_t)x16 | (uintptr_t)z16) % 16 != 0) return fail(SRMDP_E_INVALID, "x16 and z16 must be 16-byte aligned");
@@ -1202,6 +1203,9 @@ srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
         return fail(SRMDP_E_INVALID, "Adam needs lr > 0, betas in [0, 1) and eps > 0");
+    if (ws_bytes < mlp_train_partial_bytes(in, out, cfg->batch))
+        return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes,
+                    mlp_train_partial_bytes(in, out, cfg->batch));
     MlpTrainArgs t{};
     t.in = in;
     t.out = out;
@@ -1220,7 +1224,9 @@ srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam
     t.eps = cfg->eps;
     t.packed_out = (unsigned char *)packed_out;
     t.loss = loss;
-    HIP_TRY(launch_mlp_train(t, (hipStream_t)stream), "network training");
+    const hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_mlp_pack(in, out, params, packed_out, st), "network pack");
+    HIP_TRY(launch_mlp_train(t, (float *)workspace, st), "network training");
     return SRMDP_OK;
 }
 

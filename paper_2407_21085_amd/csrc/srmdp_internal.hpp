@@ -140,7 +140,7 @@ struct MlpTrainArgs {
     int64_t S;
     int updates, batch;
     float lr, beta1, beta2, eps;
-    unsigned char *packed_out;       // packed weights after the last update
+    unsigned char *packed_out;       // the packing of theta on entry, kept equal to it after each update
     float *loss;                     // [updates] or nullptr
 };
 bool cv_dimension_compiled(int d);
@@ -157,7 +157,10 @@ hipError_t launch_mlp_forward(int in, int out, const void *packed, const float *
 size_t mlp_backward_partials(int64_t B);
 hipError_t launch_mlp_backward(int in, int out, const void *packed, const float *x, const float *dy,
                                int64_t B, float *partial, float *grad, hipStream_t st);
-hipError_t launch_mlp_train(const MlpTrainArgs &t, hipStream_t st);
+// Bytes of the per-workgroup gradient partials of one update at this batch.
+size_t mlp_train_partial_bytes(int in, int out, int batch);
+// t.updates Adam updates, two launches each; partial: mlp_train_partial_bytes.
+hipError_t launch_mlp_train(const MlpTrainArgs &t, float *partial, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 
 }  // namespace srmdp

@@ -444,7 +444,8 @@ bool dimension_compiled(int d)
 size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv)
 {
     const size_t rsz = prec_is_float ? 4 : 8;
-    size_t rows = (size_t)M * (nb + d + 2 + (cv ? 2 : 0)) * rsz;
+    // with the control variate, one spare row for the lanes past the last simulation
+    size_t rows = (size_t)(cv ? M + 1 : M) * (nb + d + 2 + (cv ? 2 : 0)) * rsz;
     rows = (rows + 15) & ~(size_t)15;
     const int nch = (M + kChunk - 1) / kChunk;
     const size_t part = nch > 1 ? (size_t)(nb * (nb + 1) / 2 + d * nb) * nch : 0;  // chunk sums

@@ -438,7 +438,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     }
     unsigned char *base = smem + (CV ? kPackedFwdBytes : 0) + (size_t)slot * a.lds_per_cube;
     R *rows = reinterpret_cast<R *>(base);
-    double *f64 = reinterpret_cast<double *>(base + (((size_t)M * SW * sizeof(R) + 15) & ~(size_t)15));
+    double *f64 = reinterpret_cast<double *>(base + (((size_t)(CV ? M + 1 : M) * SW * sizeof(R) + 15) & ~(size_t)15));
     double *G = f64;
     double *H = G + NB * NB;
     double *RHS = H + NB * NB;
@@ -450,11 +450,15 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
 
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The
     //    network needs every lane of a wavefront, so with the control variate
-    //    the slots past the last stratum simulate stratum K-1 and discard it.
+    //    the slots past the last stratum simulate stratum K-1 and discard it,
+    //    and every lane makes ceil(M / L) trips: the lanes past simulation M-1
+    //    simulate one more (index >= M, a stream of its own) into the spare
+    //    row M, which nothing reads.
     if (live || CV) {
         const uint32_t ks = live ? k : a.K - 1;
-        for (int m = t; m < M; m += L) {
-            R *row = rows + (size_t)m * SW;
+        const int mend = CV ? (M + L - 1) / L * L : M;
+        for (int m = t; m < mend; m += L) {
+            R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
             R Sp, y1, cvi, centre;
             simulate_path<R, D, NB, LK, CV>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp, y1,
                                             &cv, &cvi, &centre);

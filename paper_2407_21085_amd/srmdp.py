@@ -84,7 +84,8 @@ EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_e
            "srmdp_root", "srmdp_draw", "srmdp_tune_lanes", "srmdp_workspace_bytes_batch",
            "srmdp_solve_batch", "srmdp_cv_pairs", "srmdp_mlp_param_count",
            "srmdp_mlp_packed_bytes", "srmdp_mlp_init", "srmdp_mlp_pack", "srmdp_mlp_forward",
-           "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train",
+           "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train_workspace_bytes",
+           "srmdp_mlp_train",
            "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
 
 
@@ -138,8 +139,10 @@ def _load():
     L.srmdp_mlp_backward_workspace.restype = sz
     L.srmdp_mlp_backward.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp, sz, vp]
     L.srmdp_mlp_backward.restype = ctypes.c_int
+    L.srmdp_mlp_train_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(_TrainConfig)]
+    L.srmdp_mlp_train_workspace_bytes.restype = sz
     L.srmdp_mlp_train.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp, i64,
-                                  ctypes.POINTER(_TrainConfig), vp, vp, vp]
+                                  ctypes.POINTER(_TrainConfig), vp, vp, vp, sz, vp]
     L.srmdp_mlp_train.restype = ctypes.c_int
     L.srmdp_release_graphs.argtypes = []
     L.srmdp_release_graphs.restype = None
@@ -433,9 +436,11 @@ def mlp_train(n_in: int, n_out: int, params, adam_m, adam_v, adam_t0: int, x16, 
     packed = torch.empty(int(lib.srmdp_mlp_packed_bytes()), dtype=torch.uint8, device=params.device)
     loss = torch.empty(cfg.updates_per_step, dtype=torch.float32, device=params.device)
     c = cfg.c()
+    nws = int(lib.srmdp_mlp_train_workspace_bytes(n_in, n_out, ctypes.byref(c)))
+    ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=params.device)
     _check(lib.srmdp_mlp_train(n_in, n_out, params.data_ptr(), adam_m.data_ptr(), adam_v.data_ptr(),
                                adam_t0, x16.data_ptr(), z16.data_ptr(), x16.shape[0],
-                               ctypes.byref(c), packed.data_ptr(), loss.data_ptr(),
+                               ctypes.byref(c), packed.data_ptr(), loss.data_ptr(), ws.data_ptr(), nws,
                                _stream_ptr(stream)))
     return packed, loss
 

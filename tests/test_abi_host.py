@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 101
+    assert S.srmdp.lib.srmdp_abi_version() == 102
 
 
 def test_table_elems_and_paper_sizes():
@@ -127,9 +127,7 @@ def test_mlp_parameter_counts():
 CV_BAD = [
     ("cv in binary64", None, dict(cv=1, prec=0), -2),
     ("cv without network", None, dict(cv=1, prec=1, cv_params=None), -1),
-    ("cv with M not a multiple of 8", None, dict(cv=1, prec=1, M=20), -2),
     ("cv with 128 lanes", None, dict(cv=1, prec=1, lanes_per_cube=128), -2),
-    ("cv with lanes not dividing M", None, dict(cv=1, prec=1, M=24, lanes_per_cube=16), -2),
     ("unknown cv", None, dict(cv=5, prec=1), -1),
     ("online batch", None, dict(cv=2, prec=1, batch=100), -1),
     ("online updates", None, dict(cv=2, prec=1, updates=0), -1),
@@ -169,8 +167,8 @@ def test_online_workspace_holds_training_state():
     online = S.workspace_bytes(P, G, S.Options(M=32, prec=S.FP32, cv=S.CV_ONLINE,
                                                cv_params=_FakeTensor(), cv_train=tc))
     assert frozen - plain >= 640 + 24 * 1024
-    # Adam moments, 8 * 512 pairs of 2 x 16 floats, N * 8 losses
-    assert online - frozen >= 2 * 4804 * 4 + 8 * 512 * 32 * 4 + 50 * 8 * 4
+    # Adam moments, 8 * 512 pairs of 2 x 16 floats, N * 8 losses, 2 gradient partials
+    assert online - frozen >= 2 * 4804 * 4 + 8 * 512 * 32 * 4 + 50 * 8 * 4 + 2 * 4864 * 4
 
 
 def test_mlp_calls_reject_bad_arguments():
@@ -179,11 +177,19 @@ def test_mlp_calls_reject_bad_arguments():
     tc = S.TrainConfig(updates_per_step=2, batch=256).c()
     import ctypes
     # n not a multiple of 64, shape out of range, misaligned pairs
-    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 100, ctypes.byref(tc), 16, None, None) == -1
-    assert lib.srmdp_mlp_train(17, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(tc), 16, None, None) == -1
-    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4100, 4096, 128, ctypes.byref(tc), 16, None, None) == -1
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 100, ctypes.byref(tc), 16, None, 16, 1 << 20, None) == -1
+    assert lib.srmdp_mlp_train(17, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(tc), 16, None, 16, 1 << 20, None) == -1
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4100, 4096, 128, ctypes.byref(tc), 16, None, 16, 1 << 20, None) == -1
     bad = S.TrainConfig(updates_per_step=2, batch=300).c()
-    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(bad), 16, None, None) == -1
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(bad), 16, None, 16, 1 << 20, None) == -1
+    # workspace missing or too small: batch 512 needs 2 partials of (4804 + 1) floats, rounded up to 4864
+    tc2 = S.TrainConfig(updates_per_step=2, batch=512).c()
+    assert lib.srmdp_mlp_train_workspace_bytes(5, 4, ctypes.byref(tc2)) == 2 * 4864 * 4
+    assert lib.srmdp_mlp_train_workspace_bytes(5, 4, ctypes.byref(bad)) == 0
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(tc2), 16, None, None, 0,
+                               None) == -1
+    assert lib.srmdp_mlp_train(5, 4, 16, 16, 16, 0, 4096, 4096, 128, ctypes.byref(tc2), 16, None, 16,
+                               2 * 4864 * 4 - 1, None) == -3
     assert lib.srmdp_mlp_forward(0, 4, 16, 16, 10, 16, None) == -1
     assert lib.srmdp_mlp_forward(5, 4, 16, 16, -1, 16, None) == -1
     assert lib.srmdp_mlp_backward(5, 4, 16, 16, 16, 64, 16, 16, 0, None) == -3

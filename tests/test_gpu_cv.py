@@ -140,29 +140,31 @@ def _pairs(n, n_in, n_out, seed, target):
     return x16, z16
 
 
-def test_mlp_train_step_gradient_and_adam():
+@pytest.mark.parametrize("batch", [256, 1024])
+def test_mlp_train_step_gradient_and_adam(batch):
     """One Adam step from zero moments: m = (1 - beta1) g, v = (1 - beta2) g^2 with
     g the gradient of the batch loss mean_s sum_o (z_theta - z)^2, which the
     oracle computes from its forward pass (dy = 2 (y - z) / batch) and its
-    backward pass.  The parameter step is then lr m_hat / (sqrt(v_hat) + eps)."""
+    backward pass.  The parameter step is then lr m_hat / (sqrt(v_hat) + eps).
+    A batch of 1024 spreads the gradient over four workgroups."""
     import paper_2407_21085_amd as S
     torch = _torch()
     n_in, n_out = 5, 4
     p_dev, p = _params(n_in, n_out, seed=3)
-    x16, z16 = _pairs(1024, n_in, n_out, 4, lambda x: 0.3 * np.tanh(x[:, :n_out]))
-    cfg = S.TrainConfig(updates_per_step=1, batch=256, lr=1e-3)
+    x16, z16 = _pairs(2048, n_in, n_out, 4, lambda x: 0.3 * np.tanh(x[:, :n_out]))
+    cfg = S.TrainConfig(updates_per_step=1, batch=batch, lr=1e-3)
     m = torch.zeros_like(p_dev)
     v = torch.zeros_like(p_dev)
     p0 = p_dev.clone()
-    _say("[gpu] mlp train: one Adam step")
+    _say(f"[gpu] mlp train: one Adam step, batch {batch}")
     packed, loss = S.mlp_train(n_in, n_out, p_dev, m, v, 0, torch.from_numpy(x16).cuda(),
                                torch.from_numpy(z16).cuda(), cfg)
     torch.cuda.synchronize()
     g_gpu = m.cpu().numpy().astype(np.float64) / (1 - cfg.beta1)
-    xb = x16[:256, :n_in].astype(np.float64)
-    zb = z16[:256, :n_out].astype(np.float64)
+    xb = x16[:batch, :n_in].astype(np.float64)
+    zb = z16[:batch, :n_out].astype(np.float64)
     y = O.mlp_forward(n_in, H, n_out, p, xb, bf=NET_BF)
-    dy = 2.0 * (y - zb) / 256
+    dy = 2.0 * (y - zb) / batch
     g_ref = O.mlp_backward(n_in, H, n_out, p, xb, dy, bf=O.BF_ALL)
     for name, a, b in _groups(n_in, n_out):
         err = _norm_rel(g_gpu[a:b], g_ref[a:b])
@@ -176,6 +178,34 @@ def test_mlp_train_step_gradient_and_adam():
     np.testing.assert_allclose(p0.cpu().numpy() - p_dev.cpu().numpy(), step, rtol=1e-3, atol=1e-9)
     # the returned packed network is the packing of the updated parameters
     np.testing.assert_array_equal(packed.cpu().numpy(), S.mlp_pack(n_in, n_out, p_dev).cpu().numpy())
+
+
+def test_mlp_train_updates_chain_in_place():
+    """Three updates in one call equal three calls of one update each (Adam step
+    counts 0, 1, 2 and the pairs each update takes), bit for bit: each update
+    reads the packed network the previous one rewrote, which must equal the
+    packing of the updated parameters."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    n_in, n_out, batch = 9, 8, 512
+    x16, z16 = _pairs(4096, n_in, n_out, 21, lambda x: 0.2 * np.sin(x[:, :n_out]))
+    xd, zd = torch.from_numpy(x16).cuda(), torch.from_numpy(z16).cuda()
+    p_a, _ = _params(n_in, n_out, seed=22)
+    p_b = p_a.clone()
+    m_a, v_a = torch.zeros_like(p_a), torch.zeros_like(p_a)
+    m_b, v_b = torch.zeros_like(p_a), torch.zeros_like(p_a)
+    _say("[gpu] mlp train: three updates in one call and in three")
+    packed_a, loss_a = S.mlp_train(n_in, n_out, p_a, m_a, v_a, 0, xd, zd,
+                                   S.TrainConfig(updates_per_step=3, batch=batch, lr=2e-3))
+    losses = []
+    for u in range(3):
+        packed_b, lb = S.mlp_train(n_in, n_out, p_b, m_b, v_b, u, xd[u * batch:], zd[u * batch:],
+                                   S.TrainConfig(updates_per_step=1, batch=batch, lr=2e-3))
+        losses.append(lb)
+    torch.cuda.synchronize()
+    assert torch.equal(p_a, p_b) and torch.equal(m_a, m_b) and torch.equal(v_a, v_b)
+    assert torch.equal(packed_a, packed_b)
+    assert torch.equal(loss_a, torch.cat(losses))
 
 
 def test_mlp_training_fits_a_smooth_target():
@@ -292,6 +322,9 @@ CV_CASES = [
     # 8 lanes per stratum (eight strata per wavefront), K = 3^4 = 81 (ragged last workgroup)
     ("d4 lp1 8 lanes", dict(N=5, cells=[3] * 4, M=24, lanes=8)),
     ("d4 lp0", dict(N=5, cells=[4] * 4, M=16, basis="LP0")),
+    # M not a multiple of the lanes: the lanes past simulation M-1 make a last trip and discard it
+    ("d4 lp1 M=20 32 lanes", dict(N=5, cells=[3] * 4, M=20)),
+    ("d4 lp1 M=40 16 lanes", dict(N=5, cells=[4] * 4, M=40, lanes=16)),
     ("d8 lp1", dict(d=8, N=4, lo=[-3.0] * 8, hi=[3.0] * 8, cells=[2] * 8, M=64)),
     ("d2 cos linear kappa", dict(d=2, N=6, lo=[-2.0] * 2, hi=[2.0] * 2, cells=[6, 5], M=40,
                                  driver="linear", terminal="cos", r=0.2, kappa=0.3)),
