@@ -147,7 +147,8 @@ typedef struct {
     int32_t step_hi;        /* first backward step to run (-1 = N-1); rows > step_hi of the
                              * table must hold a previous run's coefficients (resume) */
     int32_t step_lo;        /* last backward step to run (-1 = 0) */
-    int32_t lanes_per_cube; /* 0 = automatic; else 8, 16, 32, 64, 128 or 256 */
+    int32_t lanes_per_cube; /* 0 = automatic (next power of two >= M, at most 256; 64 with
+                             * the control variate); else 8, 16, 32, 64, 128 or 256 */
     uint32_t flags;         /* SRMDP_F_* */
     uint8_t *face_flags;    /* device [N*K] or NULL.  When set, entry i*K + k of every step
                              * run becomes 1 if a simulation of stratum k at step i looked

@@ -283,16 +283,22 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
 // Lanes per stratum: enough to give every lane one path up to a wavefront.
 // With the control variate every lane of a wavefront must run the same number
 // of paths: the largest power of two up to 64 that divides M.
-int auto_lanes(int M)
+// Default lanes per stratum: the next power of two >= M (one simulation per
+// lane), at most 256 (64 with the control variate, whose strata must fit in a
+// wavefront).  Larger M then spreads over more wavefronts of one workgroup
+// instead of more trips of one wavefront: at d = 8, M = 512 takes a third of
+// the time it takes with 64 lanes.
+int auto_lanes(int M, bool cv)
 {
+    const int cap = cv ? 64 : 256;
     int L = 8;
-    while (L < M && L < 64) L *= 2;
+    while (L < M && L < cap) L *= 2;
     return L;
 }
 
 int lanes_for(const srmdp_options *o)
 {
-    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
+    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M, o->cv != SRMDP_CV_NONE);
 }
 
 // One wavefront per workgroup when a stratum fits in one (several strata share
