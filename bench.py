@@ -141,7 +141,7 @@ def _product_args(S, cfg: dict):
 # evaluated every CV_STRIDE steps, trained online with CV_TRAIN after each
 # step, and the z response is centred.
 CV_STRIDE = 8
-CV_TRAIN = dict(updates_per_step=4, batch=8192, lr=2e-3)
+CV_TRAIN = dict(updates_per_step=1, batch=16384, lr=1.6e-2)
 
 
 def _interp_at_error(plain, err, value):
@@ -187,13 +187,13 @@ def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_pat
             Opt.cv, Opt.cv_stride = S.CV_ONLINE, CV_STRIDE
             Opt.flags |= S.F_CV_CENTER_Z
             Opt.cv_train = S.TrainConfig(**CV_TRAIN)
-            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True, stream=stream)
         table = S.srmdp.alloc_table(P, G, Opt)
         ws = S.srmdp.alloc_workspace(P, G, Opt)
         ms = 0.0
         for rep in range(2 if warm else 1):  # the first call of a shape warms up
             if cv:
-                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True, stream=stream)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             with torch.cuda.stream(stream):
                 ev0.record(stream)
@@ -268,7 +268,7 @@ def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_pat
 # four times the training.
 CV_FORMS_EQUAL_M = (
     {"stride": CV_STRIDE, **CV_TRAIN},
-    {"stride": 1, "updates_per_step": 16, "batch": 8192, "lr": 2e-3},
+    {"stride": 1, "updates_per_step": 4, "batch": 16384, "lr": 1.6e-2},
 )
 
 
@@ -286,6 +286,7 @@ def cv_equal_m(S, cfg: dict, seeds, stream, n_points: int = 4096) -> dict:
     rng = np.random.default_rng(12345)
     pts = rng.uniform(-1.5, 1.5, (n_points, d))
     x = torch.from_numpy(pts).to("cuda")
+    torch.cuda.synchronize()  # x is used on `stream`
     steps = (0, cfg["N"] // 2)
 
     def exact(i):
@@ -300,13 +301,13 @@ def cv_equal_m(S, cfg: dict, seeds, stream, n_points: int = 4096) -> dict:
             Opt.cv, Opt.cv_stride = S.CV_ONLINE, form["stride"]
             Opt.flags |= S.F_CV_CENTER_Z
             Opt.cv_train = S.TrainConfig(**{k: v for k, v in form.items() if k != "stride"})
-            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+            Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True, stream=stream)
         table = S.srmdp.alloc_table(P, G, Opt)
         ws = S.srmdp.alloc_workspace(P, G, Opt)
         times, st = [], None
         for rep in range(2):  # the first call warms up
             if form is not None:
-                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True)
+                Opt.cv_params = S.mlp_init(d + 1, d, 1000 + seed, zero_output_layer=True, stream=stream)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             with torch.cuda.stream(stream):
                 ev0.record(stream)
@@ -405,7 +406,7 @@ def main() -> int:
     ap.add_argument("--root-paths", type=int, default=1 << 20)
     ap.add_argument("--no-error-matched", action="store_true",
                     help="skip the plain vs control-variate comparison at matched error")
-    ap.add_argument("--em-seeds", type=int, default=16)
+    ap.add_argument("--em-seeds", type=int, default=32)
     ap.add_argument("--no-cv-equal-m", action="store_true",
                     help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
     ap.add_argument("--no-ragged-batch", action="store_true",

@@ -467,6 +467,37 @@ def test_frozen_network_sweep_graph_replays():
     S.release_graphs()
 
 
+@pytest.mark.parametrize("mode", ["plain", "online"])
+def test_sweep_reads_nothing_it_did_not_write(mode):
+    """A sweep's result does not depend on what its table and workspace held
+    before: a workspace and table filled with 0xFF bytes (NaN patterns) and
+    zero-filled ones give the same table, bit for bit, with the online control
+    variate (network, Adam state, training pairs and gradient partials all in
+    the workspace) and without it."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = dict(W.config("cfg2"), N=6, cells=[4] * 4, M=40)
+    tables = []
+    for fill in (0x00, 0xFF):
+        P, G, Opt = product_args(cfg)
+        if mode == "online":
+            Opt.cv, Opt.cv_stride = S.CV_ONLINE, 2
+            Opt.flags |= S.F_CV_CENTER_Z
+            Opt.cv_train = S.TrainConfig(updates_per_step=2, batch=512, lr=1e-2)
+            Opt.cv_params = S.mlp_init(5, 4, 9, zero_output_layer=True)
+        ws = S.srmdp.alloc_workspace(P, G, Opt)
+        table = S.srmdp.alloc_table(P, G, Opt)
+        ws.fill_(fill)
+        table.view(torch.uint8).fill_(fill)
+        torch.cuda.synchronize()
+        _say(f"[gpu] {mode} sweep on a workspace filled with {fill:#04x}")
+        S.solve(P, G, Opt, table=table, workspace=ws)
+        torch.cuda.synchronize()
+        tables.append(table)
+    assert bool(torch.isfinite(tables[1]).all())
+    assert torch.equal(tables[0], tables[1])
+
+
 def test_control_variate_keeps_the_mean_of_the_fits():
     """Unbiasedness: with a linear driver (f = -r y + kappa sum z) the fitted
     coefficients are linear in the responses, so their expectation is the same
