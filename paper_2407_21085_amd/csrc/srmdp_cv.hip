@@ -300,8 +300,17 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(MlpTrainArgs A, int u, co
     const int P = s.count();
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p < P) {
-        float gp = partial[p];
-        for (int b = 1; b < nblk; ++b) gp += partial[(size_t)b * pstride + p];
+        // in workgroup order; the loads go out eight at a time
+        float gp = 0.0f;
+        int b = 0;
+        for (; b + 8 <= nblk; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = partial[(size_t)(b + e) * pstride + p];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gp += v[e];
+        }
+        for (; b < nblk; ++b) gp += partial[(size_t)b * pstride + p];
         const float t = (float)(A.adam_t0 + u + 1);
         const float bc1 = 1.0f - powf(A.beta1, t), bc2 = 1.0f - powf(A.beta2, t);
         const float m = A.beta1 * A.adam_m[p] + (1.0f - A.beta1) * gp;
