@@ -118,8 +118,8 @@ typedef struct {
  * adapted, so still of mean zero), dividing its cost by s.  With
  * SRMDP_F_CV_CENTER_Z the z response S' dW_i / dt also loses
  * y_{i+1}(X_i) dW_i / dt (g(X_i) when i + 1 = N), of conditional mean zero too.
- * Binary32 sweeps only, with at most 64 lanes per stratum (any M >= nb).
- * The ROOT read-out does not use it. */
+ * Binary32 sweeps only (any M >= nb, any lanes per stratum).  The ROOT
+ * read-out does not use it. */
 typedef enum { SRMDP_CV_NONE = 0, SRMDP_CV_FROZEN = 1, SRMDP_CV_ONLINE = 2 } srmdp_cv;
 
 #define SRMDP_MLP_HIDDEN 64
@@ -147,8 +147,8 @@ typedef struct {
     int32_t step_hi;        /* first backward step to run (-1 = N-1); rows > step_hi of the
                              * table must hold a previous run's coefficients (resume) */
     int32_t step_lo;        /* last backward step to run (-1 = 0) */
-    int32_t lanes_per_cube; /* 0 = automatic (next power of two >= M, at most 256; 64 with
-                             * the control variate); else 8, 16, 32, 64, 128 or 256 */
+    int32_t lanes_per_cube; /* 0 = automatic (next power of two >= M, at most 256);
+                             * else 8, 16, 32, 64, 128 or 256 */
     uint32_t flags;         /* SRMDP_F_* */
     uint8_t *face_flags;    /* device [N*K] or NULL.  When set, entry i*K + k of every step
                              * run becomes 1 if a simulation of stratum k at step i looked

@@ -132,8 +132,6 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
             return fail(SRMDP_E_UNSUPPORTED, "the control variate takes d + 1 <= %d inputs", kMlpMaxIn);
         if (o->prec != SRMDP_FP32)
             return fail(SRMDP_E_UNSUPPORTED, "the control variate runs in binary32 sweeps only");
-        if (L > 64)
-            return fail(SRMDP_E_UNSUPPORTED, "the control variate needs lanes_per_cube <= 64 (%d)", L);
         if (o->cv == SRMDP_CV_ONLINE) {
             const srmdp_mlp_train_config &c = o->cv_train;
             if (c.updates_per_step < 1 || c.updates_per_step > 4096)
@@ -284,21 +282,19 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
 // With the control variate every lane of a wavefront must run the same number
 // of paths: the largest power of two up to 64 that divides M.
 // Default lanes per stratum: the next power of two >= M (one simulation per
-// lane), at most 256 (64 with the control variate, whose strata must fit in a
-// wavefront).  Larger M then spreads over more wavefronts of one workgroup
-// instead of more trips of one wavefront: at d = 8, M = 512 takes a third of
-// the time it takes with 64 lanes.
-int auto_lanes(int M, bool cv)
+// lane), at most 256.  Larger M then spreads over more wavefronts of one
+// workgroup instead of more trips of one wavefront: at d = 8, M = 512 takes a
+// third of the time it takes with 64 lanes.
+int auto_lanes(int M)
 {
-    const int cap = cv ? 64 : 256;
     int L = 8;
-    while (L < M && L < cap) L *= 2;
+    while (L < M && L < 256) L *= 2;
     return L;
 }
 
 int lanes_for(const srmdp_options *o)
 {
-    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M, o->cv != SRMDP_CV_NONE);
+    return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
 }
 
 // One wavefront per workgroup when a stratum fits in one (several strata share
@@ -596,7 +592,7 @@ bool lanes_valid(const srmdp_options *o, int L)
 {
     int cap = 8;
     while (cap < o->M && cap < 256) cap *= 2;
-    return L <= cap && (o->cv == SRMDP_CV_NONE || L <= 64);
+    return L <= cap;
 }
 
 template <typename R>

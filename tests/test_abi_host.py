@@ -127,7 +127,6 @@ def test_mlp_parameter_counts():
 CV_BAD = [
     ("cv in binary64", None, dict(cv=1, prec=0), -2),
     ("cv without network", None, dict(cv=1, prec=1, cv_params=None), -1),
-    ("cv with 128 lanes", None, dict(cv=1, prec=1, lanes_per_cube=128), -2),
     ("unknown cv", None, dict(cv=5, prec=1), -1),
     ("online batch", None, dict(cv=2, prec=1, batch=100), -1),
     ("online updates", None, dict(cv=2, prec=1, updates=0), -1),

@@ -325,6 +325,10 @@ CV_CASES = [
     # M not a multiple of the lanes: the lanes past simulation M-1 make a last trip and discard it
     ("d4 lp1 M=20 32 lanes", dict(N=5, cells=[3] * 4, M=20)),
     ("d4 lp1 M=40 16 lanes", dict(N=5, cells=[4] * 4, M=40, lanes=16)),
+    # strata over two and four wavefronts
+    ("d4 lp1 M=100 128 lanes", dict(N=4, cells=[3] * 4, M=100)),
+    ("d8 lp1 M=160 256 lanes stride 2 centred", dict(d=8, N=3, lo=[-3.0] * 8, hi=[3.0] * 8, cells=[2] * 8,
+                                                     M=160, cv_stride=2, center=True)),
     ("d8 lp1", dict(d=8, N=4, lo=[-3.0] * 8, hi=[3.0] * 8, cells=[2] * 8, M=64)),
     ("d2 cos linear kappa", dict(d=2, N=6, lo=[-2.0] * 2, hi=[2.0] * 2, cells=[6, 5], M=40,
                                  driver="linear", terminal="cos", r=0.2, kappa=0.3)),
