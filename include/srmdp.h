@@ -137,6 +137,9 @@ typedef struct {
 #define SRMDP_F_CV_CENTER_Z  0x4u  /* control variate: centre the z response (see srmdp_cv) */
 #define SRMDP_F_AUTOTUNE     0x8u  /* lanes_per_cube == 0: use the autotuned value (srmdp_tune_lanes;
                                     * tuned once per shape and cached; not during capture) */
+#define SRMDP_F_GLOBAL_ROWS  0x10u /* keep every stratum's cloud in global memory (see
+                                    * global_rows_strata); automatic, without the control
+                                    * variate, when a cloud does not fit in 64 KB of LDS */
 
 typedef struct {
     int32_t M;              /* simulations per stratum, >= nb (Definition of the clouds) */
@@ -162,6 +165,10 @@ typedef struct {
                              * read and overwritten by ONLINE; NULL when cv is NONE */
     srmdp_mlp_train_config cv_train;  /* ONLINE only */
     int32_t cv_stride;      /* network evaluated every cv_stride steps; <= 1 = every step */
+    int32_t global_rows_strata; /* clouds in global memory: strata per launch (rounded up to a
+                                 * multiple of 8); 0 = as many as 2 GiB of rows hold.  The
+                                 * workspace then holds that many clouds (M rows of
+                                 * nb + d + 2 values, plus binary64 chunk sums, each) */
 } srmdp_options;
 
 typedef struct {

@@ -117,8 +117,12 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     const int L = o->lanes_per_cube;
     if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64 && L != 128 && L != 256)
         return fail(SRMDP_E_INVALID, "lanes_per_cube must be 0, 8, 16, 32, 64, 128 or 256");
-    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z | SRMDP_F_AUTOTUNE))
+    if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z | SRMDP_F_AUTOTUNE |
+                               SRMDP_F_GLOBAL_ROWS))
         return fail(SRMDP_E_INVALID, "unknown flag bits");
+    if (o->global_rows_strata < 0) return fail(SRMDP_E_INVALID, "global_rows_strata < 0");
+    if ((o->flags & SRMDP_F_GLOBAL_ROWS) && o->cv != SRMDP_CV_NONE)
+        return fail(SRMDP_E_UNSUPPORTED, "global cloud rows run without the control variate");
     if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
         return fail(SRMDP_E_INVALID, "SRMDP_F_CV_CENTER_Z needs a control variate");
     if (o->cv_stride > 65535) return fail(SRMDP_E_INVALID, "cv_stride above 65535");
@@ -156,9 +160,14 @@ int lookup_mode(const srmdp_problem *p)
 // ------------------------------------------------------------- workspace
 constexpr int kRootBlocks = 512;
 
+bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube,
+                bool cv = false, const srmdp_options *o = nullptr);
+int lanes_for(const srmdp_options *o);
+
 struct Layout {
     size_t counters, cellF, bsig, lookup, root_partial, root_out;
     size_t cv_packed, cv_m, cv_v, cv_x, cv_z, cv_loss, cv_part;  // control variate (0 = absent)
+    size_t grows;                                                 // global cloud rows (0 = absent)
     int64_t cv_pairs;                                    // training pairs per step
     size_t total;
 };
@@ -198,6 +207,14 @@ Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options 
             off = align_up(off + (size_t)s.N * o->cv_train.updates_per_step * sizeof(float), 256);
             L.cv_part = off;
             off = align_up(off + mlp_train_partial_bytes(s.d + 1, s.q, o->cv_train.batch), 256);
+        }
+    }
+    if (o && o->cv == SRMDP_CV_NONE && o->M >= 1) {
+        LaunchShape ls;
+        size_t per_cube;
+        if (make_shape(s, nb, is_float, o->M, lanes_for(o), ls, per_cube, false, o) && ls.grows) {
+            L.grows = off;
+            off = align_up(off + (size_t)ls.kc * ls.grow_bytes, 256);
         }
     }
     L.total = off;
@@ -297,6 +314,17 @@ int lanes_for(const srmdp_options *o)
     return o->lanes_per_cube ? o->lanes_per_cube : auto_lanes(o->M);
 }
 
+constexpr size_t kGlobalRowsBudget = (size_t)2 << 30;  // bytes of global cloud rows per launch
+
+// Strata per global-rows launch: what the budget holds (or the caller's
+// choice), a multiple of 8 so that every lanes setting divides it.
+uint32_t grows_strata(const Shape &s, size_t grow_bytes, const srmdp_options *o)
+{
+    uint64_t kc = (o && o->global_rows_strata > 0) ? (uint64_t)o->global_rows_strata : kGlobalRowsBudget / grow_bytes;
+    kc = std::max<uint64_t>(8, (kc + 7) / 8 * 8);
+    return (uint32_t)std::min<uint64_t>(kc, ((uint64_t)s.K + 7) / 8 * 8);
+}
+
 // One wavefront per workgroup when a stratum fits in one (several strata share
 // it when M is small): the regression's barriers are then wave-local, and the
 // wavefronts of a CU drift apart, so one wave's latency-bound regression
@@ -304,9 +332,15 @@ int lanes_for(const srmdp_options *o)
 // the same barrier.
 // With the control variate a workgroup of up to four wavefronts shares one LDS
 // copy of the network's forward weights.
-bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube,
-                bool cv = false)
+// Without it, a stratum whose cloud does not fit in a workgroup's 64 KB of LDS
+// (or any stratum, with SRMDP_F_GLOBAL_ROWS) keeps its cloud rows and chunk
+// sums in global memory, and each step runs in launches of ls.kc strata.
+bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube, bool cv,
+                const srmdp_options *o)
 {
+    ls.grows = false;
+    ls.kc = 0;
+    ls.grow_bytes = 0;
     per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, cv), 16);
     if (cv) {
         const size_t cap = 64 * 1024 - kPackedFwdBytes;
@@ -318,14 +352,52 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
         ls.lds_bytes = kPackedFwdBytes + (size_t)cpw * per_cube;
         return true;
     }
-    int cpw = std::max(1, 64 / L);
     const size_t lds_cap = 64 * 1024;
+    const bool force = o && (o->flags & SRMDP_F_GLOBAL_ROWS);
+    if (force || per_cube > lds_cap) {
+        ls.grows = true;
+        per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
+        ls.grow_bytes = cube_global_bytes(is_float, s.d, nb, M);
+        ls.kc = grows_strata(s, ls.grow_bytes, o);
+    }
+    int cpw = std::max(1, 64 / L);
     while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;
     if ((size_t)cpw * per_cube > lds_cap) return false;
     ls.threads = (unsigned)(cpw * L);
     ls.blocks = (unsigned)((s.K + cpw - 1) / cpw);
     ls.lds_bytes = (size_t)cpw * per_cube;
     return true;
+}
+
+// One backward step without the control variate: one launch, or with global
+// rows one launch per ls.kc strata.
+template <typename R>
+hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &ls, int basis, int lk,
+                             unsigned char *ws, size_t off_cellF, size_t off_bsig, size_t off_lookup,
+                             size_t off_counters, size_t off_grows, void *table, hipStream_t st)
+{
+    if (!ls.grows)
+        return launch_step<R>(s.d, a, ls, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
+                              ws + off_counters, st);
+    const uint32_t cpw = ls.threads / (uint32_t)a.lanes;
+    for (uint32_t k0 = 0; k0 < s.K; k0 += ls.kc) {
+        a.k0 = k0;
+        a.k_end = std::min<uint32_t>(s.K, k0 + ls.kc);
+        a.grows = ws + off_grows;
+        a.grow_bytes = ls.grow_bytes;
+        LaunchShape sub = ls;
+        sub.blocks = (a.k_end - k0 + cpw - 1) / cpw;
+        const hipError_t e = launch_step_gr<R>(s.d, a, sub, basis, lk, ws + off_cellF, ws + off_bsig,
+                                               ws + off_lookup, table, ws + off_counters, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Backward-step launches per step.
+uint32_t launches_per_step(const Shape &s, const LaunchShape &ls)
+{
+    return ls.grows ? (uint32_t)((s.K + ls.kc - 1) / ls.kc) : 1u;
 }
 
 // ------------------------------------------------------------- graph cache
@@ -354,7 +426,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
     const bool cv = o->cv != SRMDP_CV_NONE;
     LaunchShape ls;
     size_t per_cube;
-    if (!make_shape(s, nb, is_float, o->M, L, ls, per_cube, cv))
+    if (!make_shape(s, nb, is_float, o->M, L, ls, per_cube, cv, o))
         return fail(SRMDP_E_UNSUPPORTED, "M = %d does not fit the per-workgroup LDS budget", o->M);
     StepArgs<R> a;
     fill_step_args<R>(a, p, g, s, o);
@@ -419,8 +491,8 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
             }
         }
         if (!launched)
-            HIP_TRY(launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
-                                   table, ws + lay.counters, st),
+            HIP_TRY(launch_plain_step<R>(s, a, ls, o->basis, lk, ws, lay.cellF, lay.bsig, lay.lookup, lay.counters,
+                                         lay.grows, table, st),
                     "sweep step");
         if (a.face_flags)
             HIP_TRY(launch_face_flags<R>(s.d, o->basis, a, ws + lay.cellF, ws + lay.bsig,
@@ -511,7 +583,14 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
                 HIP_TRY(hipEventElapsedTime(&ms, s0, s1), "hipEventElapsedTime");
                 stats->ms_steps = ms;
             }
-            stats->step_launches = hi - lo + 1;
+            uint32_t per_step = 1;
+            if (o->cv == SRMDP_CV_NONE) {
+                LaunchShape ls;
+                size_t per_cube;
+                if (make_shape(s, nb, sizeof(R) == 4, o->M, lanes_for(o), ls, per_cube, false, o))
+                    per_step = launches_per_step(s, ls);
+            }
+            stats->step_launches = (hi - lo + 1) * (int32_t)per_step;
             stats->near_face_paths = ctr[kCounterNearFace];
             stats->lanes_per_cube = lanes_for(o);
             if (o->cv == SRMDP_CV_ONLINE) {
@@ -634,7 +713,7 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
         if (!lanes_valid(o, L)) continue;
         LaunchShape ls;
         size_t per_cube;
-        if (!make_shape(s, nb, sizeof(R) == 4, o->M, L, ls, per_cube, cv)) continue;
+        if (!make_shape(s, nb, sizeof(R) == 4, o->M, L, ls, per_cube, cv, o)) continue;
         a.lanes = L;
         a.lds_per_cube = per_cube;
         auto launch = [&]() -> hipError_t {
@@ -642,8 +721,8 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
                 if (cv)
                     return launch_step_cv(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
                                           table, ws + lay.counters, st);
-            return launch_step<R>(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup, table,
-                                  ws + lay.counters, st);
+            return launch_plain_step<R>(s, a, ls, o->basis, lk, ws, lay.cellF, lay.bsig, lay.lookup, lay.counters,
+                                        lay.grows, table, st);
         };
         hipError_t e = launch();
         if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -911,7 +990,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 102; }
+int32_t srmdp_abi_version(void) { return 103; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 

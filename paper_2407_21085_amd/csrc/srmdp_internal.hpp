@@ -59,6 +59,12 @@ struct StepArgs {
     const unsigned char *cv_packed;  // control-variate network, packed (nullptr = none)
     int cv_stride;                   // network evaluated every cv_stride steps (>= 1)
     int z_center;                    // subtract y_{i+1}(X_i) from the z response's S'
+    // Global-rows launches (clouds too large for LDS): this launch runs strata
+    // k0 .. k_end-1, each keeping its regression inputs and chunk sums in
+    // grow_bytes of global memory from grows (slot = stratum - k0).
+    uint32_t k0, k_end;
+    unsigned char *grows;
+    size_t grow_bytes;
 };
 
 struct SetupArgs {
@@ -77,6 +83,9 @@ struct RootPoint {
 struct LaunchShape {
     unsigned blocks, threads;  // groups of strata, threads per workgroup
     size_t lds_bytes;
+    bool grows;                // clouds in global memory, launches of `kc` strata
+    uint32_t kc;
+    size_t grow_bytes;         // global bytes per stratum
 };
 
 template <typename R>
@@ -128,7 +137,14 @@ hipError_t launch_batch_step(int d, int basis, int lkmode, const void *inst, int
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 bool dimension_compiled(int d);
-size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false);
+// LDS bytes of one stratum's regression; with grows the cloud rows and chunk
+// sums are in global memory (cube_global_bytes per stratum) instead.
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false, bool grows = false);
+size_t cube_global_bytes(int prec_is_float, int d, int nb, int M);
+template <typename R>
+hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                          const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                          hipStream_t st);
 
 // ------------------------------------------------ learned control variate
 // (srmdp_cv.hip; binary32 sweeps only)

@@ -441,15 +441,31 @@ bool dimension_compiled(int d)
     }
 }
 
-size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv)
+// Cloud rows of a stratum (16-byte aligned) and its chunk sums.
+static size_t cube_row_bytes(int prec_is_float, int d, int nb, int M, bool cv)
 {
     const size_t rsz = prec_is_float ? 4 : 8;
     // with the control variate, one spare row for the lanes past the last simulation
-    size_t rows = (size_t)(cv ? M + 1 : M) * (nb + d + 2 + (cv ? 2 : 0)) * rsz;
-    rows = (rows + 15) & ~(size_t)15;
+    const size_t rows = (size_t)(cv ? M + 1 : M) * (nb + d + 2 + (cv ? 2 : 0)) * rsz;
+    return (rows + 15) & ~(size_t)15;
+}
+static size_t cube_part_bytes(int d, int nb, int M)
+{
     const int nch = (M + kChunk - 1) / kChunk;
-    const size_t part = nch > 1 ? (size_t)(nb * (nb + 1) / 2 + d * nb) * nch : 0;  // chunk sums
-    return rows + (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb + part) * sizeof(double);
+    return nch > 1 ? (size_t)(nb * (nb + 1) / 2 + d * nb) * nch * sizeof(double) : 0;
+}
+
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv, bool grows)
+{
+    const size_t small = (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
+    if (grows) return small;
+    return cube_row_bytes(prec_is_float, d, nb, M, cv) + small + cube_part_bytes(d, nb, M);
+}
+
+size_t cube_global_bytes(int prec_is_float, int d, int nb, int M)
+{
+    const size_t b = cube_row_bytes(prec_is_float, d, nb, M, false) + cube_part_bytes(d, nb, M);
+    return (b + 255) & ~(size_t)255;
 }
 
 #define SRMDP_INSTANTIATE(R)                                                                        \

@@ -402,7 +402,10 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // One group of strata of backward step a.i: the workgroup's cpw = blockDim / L
 // strata k = group * cpw + slot, L = a.lanes lanes each.  Shared by the
 // per-step kernel and the batched (several instances) kernel.
-template <typename R, int D, int NB, int LK, bool CV>
+// With GR (global rows) the cloud rows and the chunk sums of a stratum live in
+// a.grow_bytes of global memory (clouds too large for LDS), and the launch
+// covers strata a.k0 .. a.k_end-1; LDS keeps the small binary64 arrays only.
+template <typename R, int D, int NB, int LK, bool CV, bool GR = false>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
                                             const R *__restrict__ bsig, R *__restrict__ lk,
@@ -421,8 +424,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     const int t = threadIdx.x % L;
     const int M = a.M;
 
-    const uint32_t k = group * (uint32_t)cpw + (uint32_t)slot;
-    const bool live = k < a.K;
+    const uint32_t k = (GR ? a.k0 : 0u) + group * (uint32_t)cpw + (uint32_t)slot;
+    const bool live = k < (GR ? a.k_end : a.K);
 
     // With the control variate the workgroup first copies the network's
     // forward weights to LDS; the strata follow them.
@@ -437,15 +440,26 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         __syncthreads();
     }
     unsigned char *base = smem + (CV ? kPackedFwdBytes : 0) + (size_t)slot * a.lds_per_cube;
-    R *rows = reinterpret_cast<R *>(base);
-    double *f64 = reinterpret_cast<double *>(base + (((size_t)(CV ? M + 1 : M) * SW * sizeof(R) + 15) & ~(size_t)15));
+    const size_t row_bytes = ((size_t)(CV ? M + 1 : M) * SW * sizeof(R) + 15) & ~(size_t)15;
+    R *rows;
+    double *f64;
+    unsigned char *gbase = nullptr;
+    if constexpr (GR) {
+        gbase = a.grows + (size_t)(group * (uint32_t)cpw + (uint32_t)slot) * a.grow_bytes;
+        rows = reinterpret_cast<R *>(gbase);
+        f64 = reinterpret_cast<double *>(base);
+    } else {
+        rows = reinterpret_cast<R *>(base);
+        f64 = reinterpret_cast<double *>(base + row_bytes);
+    }
     double *G = f64;
     double *H = G + NB * NB;
     double *RHS = H + NB * NB;
     double *beta = RHS + REC;
     double *flag = beta + REC;
     double *zsum = flag + 2;
-    double *part = zsum + NB;  // [entries][chunks] partial sums when M > kChunk
+    // [entries][chunks] partial sums when M > kChunk
+    double *part = GR ? reinterpret_cast<double *>(gbase + row_bytes) : zsum + NB;
     const int nch = (M + kChunk - 1) / kChunk;
 
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The

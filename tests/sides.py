@@ -33,5 +33,5 @@ def product_args(cfg, **kw):
     Opt = S.Options(M=c["M"], basis=_BASIS[c["basis"]], prec=S.FP32 if c["prec"] == "fp32" else S.FP64,
                     seed=c["seed"], instance=c.get("instance", 0), step_hi=c.get("step_hi", -1),
                     step_lo=c.get("step_lo", -1), lanes_per_cube=c.get("lanes", 0),
-                    flags=c.get("flags", 0))
+                    flags=c.get("flags", 0), global_rows_strata=c.get("global_rows_strata", 0))
     return P, G, Opt

@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 102
+    assert S.srmdp.lib.srmdp_abi_version() == 103
 
 
 def test_table_elems_and_paper_sizes():
@@ -131,6 +131,7 @@ CV_BAD = [
     ("online batch", None, dict(cv=2, prec=1, batch=100), -1),
     ("online updates", None, dict(cv=2, prec=1, updates=0), -1),
     ("online lr", None, dict(cv=2, prec=1, lr=0.0), -1),
+    ("cv with global cloud rows", None, dict(cv=1, prec=1, flags=0x10), -2),
 ]
 
 
@@ -153,6 +154,28 @@ def test_control_variate_options_rejected(name, _unused, kw, status):
     O = S.Options(M=kw.pop("M", 32), cv_params=params, cv_train=tc, **kw)
     rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
     assert rc == status, S.srmdp.lib.srmdp_last_error().decode()
+
+
+def test_global_rows_workspace_and_rejections():
+    """Clouds in global memory: the workspace grows by the strata per launch
+    times the bytes of one cloud (M rows of nb + d + 2 binary64 values, 16-byte
+    aligned, plus chunk sums, the total 256-byte aligned), automatically when a
+    cloud exceeds 64 KB of LDS; a negative strata count is rejected."""
+    S = _S()
+    P = S.Problem(d=1, N=10)
+    G = S.Grid([-4.0], [4.0], [32])
+    base = S.workspace_bytes(P, G, S.Options(M=40))
+    forced = S.workspace_bytes(P, G, S.Options(M=40, flags=S.F_GLOBAL_ROWS, global_rows_strata=8))
+    assert forced - base == 8 * 1792                        # 40 * 5 * 8 = 1600 -> 1792
+    default = S.workspace_bytes(P, G, S.Options(M=40, flags=S.F_GLOBAL_ROWS))
+    assert default - base == 32 * 1792                      # every stratum in one launch
+    # M = 12000: 480000 bytes of rows, 188 chunks of 5 sums (7520 bytes): automatic
+    big = S.workspace_bytes(P, G, S.Options(M=12000))
+    small_lds = S.workspace_bytes(P, G, S.Options(M=12000, global_rows_strata=8))
+    assert big - small_lds == 24 * 487680
+    rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), S.Options(M=40, global_rows_strata=-1).c(), 16, 16, 1 << 40,
+                                 None, None)
+    assert rc == -1
 
 
 def test_online_workspace_holds_training_state():
