@@ -24,6 +24,9 @@ Prints one JSON line:
   cv_equal_M   the d = 4 logistic workload at M = 32: plain against the online
                control variate, same draws; errors of the fitted y and z against
                the closed form and their variance across seeds
+  paper_tables the paper's own workloads (rows of its Tables LP0d4 .. LP1d6_1):
+               sweep time and the error indicators of eq. (mse), beside the
+               values and GPU seconds the paper prints
 """
 from __future__ import annotations
 
@@ -369,6 +372,69 @@ def cv_equal_m(S, cfg: dict, seeds, stream, n_points: int = 4096) -> dict:
             "points": f"{n_points} uniform on [-1.5, 1.5]^{d}", "plain": plain, "cv": forms}
 
 
+# Rows of the paper's Tables LP0d4, LP0d6_0, LP0d6_1, LP1d4 and LP1d6_1
+# (Section 4: logistic BSDE, X = W, [-6.5, 6.5]^q in #C^q cubes, mu = 1,
+# T = 1, binary32): (table, d, basis, N, #C, M, the printed indicators
+# (MSE_Y,max, MSE_Y,av, MSE_Z,av) of eq. (mse), the printed GPU seconds on a
+# GTX TITAN Black).
+PAPER_ROWS = (
+    ("LP0d4", 4, "LP0", 20, 17, 400, (-4.337988, -4.698645, -2.302092), 12.39),
+    ("LP0d4", 4, "LP0", 50, 28, 2500, (-4.472564, -4.988069, -3.225411), 3070.92),
+    ("LP0d6_0", 6, "LP0", 50, 7, 2500, (-3.235130, -3.539011, -2.557686), 874.25),
+    ("LP0d6_1", 6, "LP0", 20, 8, 400, (-3.505867, -3.664396, -1.795697), 52.20),
+    ("LP1d4", 4, "LP1", 20, 7, 2000, (-4.541253, -5.022405, -2.281332), 7.83),
+    ("LP1d4", 4, "LP1", 50, 10, 12500, (-4.574551, -5.143310, -3.228237), 847.83),
+    ("LP1d6_1", 6, "LP1", 20, 4, 2800, (-4.075928, -4.231639, -1.791519), 20.50),
+    ("LP1d6_1", 6, "LP1", 50, 6, 17500, (-3.809734, -4.529827, -2.689432), 15283.18),
+)
+
+
+def paper_tables(S, stream, rows=PAPER_ROWS, points: int = 1000) -> list:
+    """The paper's own workloads at their sizes: one binary32 sweep each
+    (HIP events on the library's stream; a warm-up sweep first for the small
+    ones), and the error indicators of eq. (mse) from 10^3 test points per
+    time step drawn from the unrestricted nu (product logistic, mu = 1),
+    against y_i = w / (1 + w), z_i = w / (1 + w)^2 with w = exp(t_i + sum x)."""
+    import numpy as np
+    import torch
+    out = []
+    for name, d, basis, N, C, M, printed, paper_s in rows:
+        cfg = dict(name=f"{name} N={N}", d=d, N=N, T=1.0, lo=[-6.5] * d, hi=[6.5] * d, cells=[C] * d, mu=1.0,
+                   M=M, basis=basis, prec="fp32", driver="logistic", terminal="logistic", seed=1)
+        P, G, Opt = _product_args(S, cfg)
+        table = S.srmdp.alloc_table(P, G, Opt)
+        ws = S.srmdp.alloc_workspace(P, G, Opt)
+        steps = W.path_steps(cfg)
+        reps = 2 if steps < 2e10 else 1
+        for _ in range(reps):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                ev0.record(stream)
+                _, st = S.solve(P, G, Opt, table=table, workspace=ws, stream=stream)
+                ev1.record(stream)
+            torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        rng = np.random.default_rng(2024)
+        ey, ez = [], []
+        for i in range(N):
+            u = rng.random((points, d))
+            x = np.log(u / (1.0 - u))
+            y, z = S.evaluate(P, G, Opt.basis, Opt.prec, table, i, torch.from_numpy(x).cuda(), stream=stream)
+            torch.cuda.synchronize()
+            w = np.exp(i / N + x.sum(axis=1))
+            ey.append(float(np.mean((y.cpu().numpy() - w / (1 + w)) ** 2)))
+            ez.append(float(np.mean(((z.cpu().numpy() - (w / (1 + w) ** 2)[:, None]) ** 2).sum(axis=1))))
+        mse = (math.log(max(ey)), math.log(sum(ey) / N), math.log(sum(ez) / N))
+        out.append({"table": name, "d": d, "basis": basis, "N": N, "cells": C, "K": C ** d, "M": M,
+                    "path_steps": steps, "sweep_s": ms / 1e3, "path_steps_per_s": steps / (ms / 1e3),
+                    "launches": st["step_launches"], "lanes_per_cube": st["lanes_per_cube"],
+                    "mse": [round(v, 4) for v in mse], "paper_mse": list(printed),
+                    "paper_gpu_s": paper_s, "paper_gpu": "GTX TITAN Black (context, not the target)"})
+        del table, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def ragged_batch(S, stream) -> dict:
     """The ragged batch workload (64 d = 2 cos instances, K 16^2..64^2,
     M 64..1024, N 10..50, binary32): one batched sweep (one launch per global
@@ -422,6 +488,8 @@ def main() -> int:
     ap.add_argument("--em-seeds", type=int, default=32)
     ap.add_argument("--no-cv-equal-m", action="store_true",
                     help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
+    ap.add_argument("--no-paper-tables", action="store_true",
+                    help="skip the paper's own workloads (Tables LP0d4 .. LP1d6_1)")
     ap.add_argument("--no-ragged-batch", action="store_true",
                     help="skip the 64-instance ragged batch measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -523,6 +591,8 @@ def main() -> int:
     }
     if not args.no_ragged_batch:
         out["ragged_batch"] = ragged_batch(S, stream)
+    if not args.no_paper_tables:
+        out["paper_tables"] = paper_tables(S, stream)
     if not args.no_error_matched and cfg["driver"] == "logistic":
         M = cfg["M"]
         out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), [M, 2 * M, 4 * M, 8 * M],

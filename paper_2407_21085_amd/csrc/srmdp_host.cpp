@@ -341,6 +341,7 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
     ls.grows = false;
     ls.kc = 0;
     ls.grow_bytes = 0;
+    ls.stage_chunks = 0;
     per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, cv), 16);
     if (cv) {
         const size_t cap = 64 * 1024 - kPackedFwdBytes;
@@ -359,6 +360,7 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
         per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
         ls.grow_bytes = cube_global_bytes(is_float, s.d, nb, M);
         ls.kc = grows_strata(s, ls.grow_bytes, o);
+        ls.stage_chunks = cube_stage_chunks(is_float, s.d, nb, M);
     }
     int cpw = std::max(1, 64 / L);
     while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;
@@ -385,6 +387,7 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
         a.k_end = std::min<uint32_t>(s.K, k0 + ls.kc);
         a.grows = ws + off_grows;
         a.grow_bytes = ls.grow_bytes;
+        a.stage_chunks = ls.stage_chunks;
         LaunchShape sub = ls;
         sub.blocks = (a.k_end - k0 + cpw - 1) / cpw;
         const hipError_t e = launch_step_gr<R>(s.d, a, sub, basis, lk, ws + off_cellF, ws + off_bsig,

@@ -65,6 +65,7 @@ struct StepArgs {
     uint32_t k0, k_end;
     unsigned char *grows;
     size_t grow_bytes;
+    int stage_chunks;  // chunks of rows per LDS window of the sums
 };
 
 struct SetupArgs {
@@ -86,6 +87,7 @@ struct LaunchShape {
     bool grows;                // clouds in global memory, launches of `kc` strata
     uint32_t kc;
     size_t grow_bytes;         // global bytes per stratum
+    int stage_chunks;          // chunks per LDS window of the sums
 };
 
 template <typename R>
@@ -141,6 +143,8 @@ bool dimension_compiled(int d);
 // sums are in global memory (cube_global_bytes per stratum) instead.
 size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false, bool grows = false);
 size_t cube_global_bytes(int prec_is_float, int d, int nb, int M);
+// Chunks of rows in the LDS window through which the sums read a global cloud.
+int cube_stage_chunks(int prec_is_float, int d, int nb, int M);
 template <typename R>
 hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,

@@ -458,8 +458,20 @@ static size_t cube_part_bytes(int d, int nb, int M)
 size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv, bool grows)
 {
     const size_t small = (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
-    if (grows) return small;
+    if (grows) {  // binary64 arrays, then the window of rows
+        const size_t rsz = prec_is_float ? 4 : 8;
+        return ((small + 15) & ~(size_t)15) +
+               (size_t)cube_stage_chunks(prec_is_float, d, nb, M) * kChunk * (nb + d + 2) * rsz;
+    }
     return cube_row_bytes(prec_is_float, d, nb, M, cv) + small + cube_part_bytes(d, nb, M);
+}
+
+int cube_stage_chunks(int prec_is_float, int d, int nb, int M)
+{
+    const size_t rsz = prec_is_float ? 4 : 8;
+    const int fit = (int)(kStageBytes / ((size_t)kChunk * (nb + d + 2) * rsz));
+    const int nch = (M + kChunk - 1) / kChunk;
+    return fit < 1 ? 1 : (fit < nch ? fit : nch);
 }
 
 size_t cube_global_bytes(int prec_is_float, int d, int nb, int M)

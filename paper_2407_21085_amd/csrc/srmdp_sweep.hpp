@@ -387,6 +387,9 @@ struct CubeLds {
 // than one chunk the chunk sums (one per lane and entry, in parallel) are
 // added in chunk order.  The order depends on M only, not on the lanes.
 constexpr int kChunk = 64;
+// With the cloud in global memory, the sums read it through an LDS window of
+// a.stage_chunks chunks (about kStageBytes), copied in with coalesced loads.
+constexpr int kStageBytes = 32 * 1024;
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so block b
 // runs on XCD b % 8.  Give each XCD a contiguous range of strata so that
@@ -461,6 +464,9 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     // [entries][chunks] partial sums when M > kChunk
     double *part = GR ? reinterpret_cast<double *>(gbase + row_bytes) : zsum + NB;
     const int nch = (M + kChunk - 1) / kChunk;
+    // GR: LDS window of kStageChunks chunks of rows, after the binary64 arrays
+    R *stage = GR ? reinterpret_cast<R *>(base + ((sizeof(double) * (size_t)Lay::F64 + 15) & ~(size_t)15))
+                  : nullptr;
 
     // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The
     //    network needs every lane of a wavefront, so with the control variate
@@ -492,7 +498,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     //    M samples, one (entry, chunk) pair per lane, then the chunks in order.
     constexpr int NG = NB * (NB + 1) / 2;
     constexpr int NE = Lay::NE;
-    auto gram_sum = [&](int e, int m0, int m1) {
+    auto gram_sum = [&](const R *rb, int e, int m0, int m1) {
         double acc = 0.0;
         if (e < NG) {
             int r = 0, rem = e;
@@ -502,17 +508,22 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             }
             const int c = r + rem;
             for (int m = m0; m < m1; ++m) {
-                const R *row = rows + (size_t)m * SW;
+                const R *row = rb + (size_t)m * SW;
                 acc += (double)row[r] * (double)row[c];
             }
         } else {
             const int l = (e - NG) / NB, b = (e - NG) % NB;
             for (int m = m0; m < m1; ++m) {
-                const R *row = rows + (size_t)m * SW;
+                const R *row = rb + (size_t)m * SW;
                 acc += (double)row[b] * ((double)row[NB + D] * (double)row[NB + l]);
             }
         }
         return acc;
+    };
+    // GR: copy rows m0..m1-1 of the cloud into the LDS window (whole workgroup)
+    auto stage_rows = [&](int m0, int m1) {
+        if (live)
+            for (int e = t; e < (m1 - m0) * SW; e += L) stage[e] = rows[(size_t)m0 * SW + e];
     };
     auto gram_store = [&](int e, double acc) {
         if (e < NG) {
@@ -529,14 +540,40 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             RHS[(1 + l) * NB + b] = acc * a.inv_dt;
         }
     };
-    if (nch == 1) {
+    if constexpr (GR) {
+        for (int c0 = 0; c0 < nch; c0 += a.stage_chunks) {
+            const int c1 = min(nch, c0 + a.stage_chunks), m0 = c0 * kChunk, m1 = min(M, c1 * kChunk);
+            stage_rows(m0, m1);
+            __syncthreads();
+            if (live) {
+                if (nch == 1) {
+                    for (int e = t; e < NE; e += L) gram_store(e, gram_sum(stage, e, 0, M));
+                } else {
+                    const int ncs = c1 - c0;
+                    for (int w = t; w < NE * ncs; w += L) {
+                        const int e = w / ncs, c = c0 + w % ncs;
+                        part[e * nch + c] = gram_sum(stage, e, c * kChunk - m0, min(M, (c + 1) * kChunk) - m0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (nch > 1) {
+            if (live)
+                for (int e = t; e < NE; e += L) {
+                    double acc = 0.0;
+                    for (int c = 0; c < nch; ++c) acc += part[e * nch + c];
+                    gram_store(e, acc);
+                }
+        }
+    } else if (nch == 1) {
         if (live)
-            for (int e = t; e < NE; e += L) gram_store(e, gram_sum(e, 0, M));
+            for (int e = t; e < NE; e += L) gram_store(e, gram_sum(rows, e, 0, M));
     } else {
         if (live)
             for (int w = t; w < NE * nch; w += L) {
                 const int e = w / nch, c = w % nch;
-                part[w] = gram_sum(e, c * kChunk, min(M, (c + 1) * kChunk));
+                part[w] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
             }
         __syncthreads();
         if (live)
@@ -638,22 +675,48 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     __syncthreads();
 
     // 6. y right-hand side (chunked as the Gram sums) and solve
-    auto y_sum = [&](int b, int m0, int m1) {
+    auto y_sum = [&](const R *rb, int b, int m0, int m1) {
         double acc = 0.0;
         for (int m = m0; m < m1; ++m) {
-            const R *row = rows + (size_t)m * SW;
+            const R *row = rb + (size_t)m * SW;
             acc += (double)row[b] * (double)row[NB + D];
         }
         return acc;
     };
-    if (nch == 1) {
+    if constexpr (GR) {
+        for (int c0 = 0; c0 < nch; c0 += a.stage_chunks) {
+            const int c1 = min(nch, c0 + a.stage_chunks), m0 = c0 * kChunk, m1 = min(M, c1 * kChunk);
+            stage_rows(m0, m1);
+            __syncthreads();
+            if (live) {
+                if (nch == 1) {
+                    for (int b = t; b < NB; b += L) RHS[b] = y_sum(stage, b, 0, M);
+                } else {
+                    const int ncs = c1 - c0;
+                    for (int w = t; w < NB * ncs; w += L) {
+                        const int b = w / ncs, c = c0 + w % ncs;
+                        part[b * nch + c] = y_sum(stage, b, c * kChunk - m0, min(M, (c + 1) * kChunk) - m0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (nch > 1) {
+            if (live)
+                for (int b = t; b < NB; b += L) {
+                    double acc = 0.0;
+                    for (int c = 0; c < nch; ++c) acc += part[b * nch + c];
+                    RHS[b] = acc;
+                }
+        }
+    } else if (nch == 1) {
         if (live)
-            for (int b = t; b < NB; b += L) RHS[b] = y_sum(b, 0, M);
+            for (int b = t; b < NB; b += L) RHS[b] = y_sum(rows, b, 0, M);
     } else {
         if (live)
             for (int w = t; w < NB * nch; w += L) {
                 const int b = w / nch, c = w % nch;
-                part[w] = y_sum(b, c * kChunk, min(M, (c + 1) * kChunk));
+                part[w] = y_sum(rows, b, c * kChunk, min(M, (c + 1) * kChunk));
             }
         __syncthreads();
         if (live)
