@@ -354,7 +354,7 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
         return true;
     }
     const size_t lds_cap = 64 * 1024;
-    const bool force = o && (o->flags & SRMDP_F_GLOBAL_ROWS);
+    const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d);
     if (force || per_cube > lds_cap) {
         ls.grows = true;
         per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
@@ -395,6 +395,19 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// The sweep kernels compiled for the shape: every compiled dimension has the
+// global-rows kernel in binary32 with look-up modes Y and YZ; the LDS kernel
+// (both precisions, every mode) exists for the dimensions of the main file.
+srmdp_status sweep_supported(const Shape &s, const srmdp_options *o, int lk)
+{
+    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    if (!lds_dimension_compiled(s.d) &&
+        (o->prec != SRMDP_FP32 || (lk != kLookupY && lk != kLookupYZ) || o->cv != SRMDP_CV_NONE))
+        return fail(SRMDP_E_UNSUPPORTED,
+                    "d = %d runs binary32 sweeps without z truncation or control variate only", s.d);
+    return SRMDP_OK;
 }
 
 // Backward-step launches per step.
@@ -811,7 +824,8 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
             return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
         bp.gmax = std::max(bp.gmax, P[b].N);
     }
-    if (!dimension_compiled(P[0].d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", P[0].d);
+    if (!lds_dimension_compiled(P[0].d))
+        return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled for batches", P[0].d);
     bp.order.resize(n);
     std::iota(bp.order.begin(), bp.order.end(), 0);
     std::stable_sort(bp.order.begin(), bp.order.end(), [&](int x, int y) { return P[x].N > P[y].N; });
@@ -1031,7 +1045,8 @@ srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
     const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
     if (ws_bytes < need)
         return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    rc = sweep_supported(s, opts, lookup_mode(problem));
+    if (rc != SRMDP_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     srmdp_options o = *opts;
     if ((o.flags & SRMDP_F_AUTOTUNE) && o.lanes_per_cube == 0) {
@@ -1058,7 +1073,8 @@ srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *gr
     if (!table || !workspace || !lanes) return fail(SRMDP_E_INVALID, "table, workspace and lanes are required");
     const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
     if (ws_bytes < need) return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-    if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
+    rc = sweep_supported(s, opts, lookup_mode(problem));
+    if (rc != SRMDP_OK) return rc;
     int L = 0;
     rc = tune_cached(problem, grid, opts, s, nb, table, (unsigned char *)workspace, (hipStream_t)stream, &L, ms,
                      true);

@@ -114,6 +114,31 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
                        uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
+// The dimensions of the high-dimension file (d = 11..16, the paper's Tables
+// LP0d11 .. LP1d15_19): binary32 sweeps with the cloud in global memory and
+// look-up modes Y and YZ, and every kernel around the sweep.
+bool hd_dimension_compiled(int d);
+template <typename R>
+hipError_t launch_step_gr_hd(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                             const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                             hipStream_t st);
+template <typename R>
+hipError_t launch_face_flags_hd(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                                void *counters, hipStream_t st);
+template <typename R>
+hipError_t launch_lookup_rows_hd(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K,
+                                 int i_lo, int i_hi, hipStream_t st);
+template <typename R>
+hipError_t launch_root_hd(int d, int basis, int lkmode, const StepArgs<R> &a, const void *bsig,
+                          const void *lk, const RootPoint &x0, int M_root, int nblocks, double *partial,
+                          double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_eval_hd(int d, int basis, const StepArgs<R> &a, const void *table, const double *x,
+                          int64_t n, double *y, double *z, hipStream_t st);
+template <typename R>
+hipError_t launch_draw_hd(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
+                          uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
+
 // ------------------------------------------------------ batched sweeps
 // One instance of a batched sweep, as the batched kernel reads it.  Global
 // step g runs backward step i = N - 1 - g of every instance with N > g; the
@@ -138,6 +163,8 @@ hipError_t launch_batch_step(int d, int basis, int lkmode, const void *inst, int
 // staging buffer, nothing to keep alive after the call, capturable).
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
 
+// Dimensions with the LDS sweep kernel, and every dimension compiled at all.
+bool lds_dimension_compiled(int d);
 bool dimension_compiled(int d);
 // LDS bytes of one stratum's regression; with grows the cloud rows and chunk
 // sums are in global memory (cube_global_bytes per stratum) instead.

@@ -55,7 +55,7 @@ hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int
     case DD: return dispatch_gr_d<R, DD>(a, s, basis, lkmode, cellF, bsig, lk, table, counters, st);
         SRMDP_GR_FOR_EACH_D(X)
 #undef X
-    default: return hipErrorInvalidValue;
+    default: return launch_step_gr_hd<R>(d, a, s, basis, lkmode, cellF, bsig, lk, table, counters, st);
     }
 }
 

@@ -178,6 +178,25 @@ def test_global_rows_workspace_and_rejections():
     assert rc == -1
 
 
+def test_high_dimensions_run_binary32_sweeps_only():
+    """d = 11..16 have the global-rows sweep in binary32 with look-up modes Y
+    and YZ only: binary64, z truncation (mode Full) and the control variate are
+    refused before anything is enqueued; d = 9 is not compiled."""
+    S = _S()
+    G = S.Grid([-1.0] * 11, [1.0] * 11, [2] * 11)
+    for P, O, status in [
+        (S.Problem(d=11, N=3), S.Options(M=40, prec=S.FP64), -2),
+        (S.Problem(d=11, N=3, clamp_z=0.5), S.Options(M=40, prec=S.FP32), -2),
+        (S.Problem(d=11, N=3), S.Options(M=40, prec=S.FP32, cv=1, cv_params=_FakeTensor()), -2),
+    ]:
+        rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
+        assert rc == status, S.srmdp.lib.srmdp_last_error().decode()
+    G9 = S.Grid([-1.0] * 9, [1.0] * 9, [2] * 9)
+    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=9, N=3).c(), G9.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16,
+                                 1 << 40, None, None)
+    assert rc == -2
+
+
 def test_online_workspace_holds_training_state():
     S = _S()
     P = S.Problem(d=4, N=50, driver=S.DRV_LOGISTIC, terminal=S.G_LOGISTIC)
