@@ -24,7 +24,7 @@ Prints one JSON line:
   cv_equal_M   the d = 4 logistic workload at M = 32: plain against the online
                control variate, same draws; errors of the fitted y and z against
                the closed form and their variance across seeds
-  paper_tables the paper's own workloads (rows of its Tables LP0d4 .. LP1d6_1):
+  paper_tables the paper's own workloads (rows of its Tables LP0d4 .. LP1d15_19):
                sweep time and the error indicators of eq. (mse), beside the
                values and GPU seconds the paper prints
 """
@@ -372,7 +372,8 @@ def cv_equal_m(S, cfg: dict, seeds, stream, n_points: int = 4096) -> dict:
             "points": f"{n_points} uniform on [-1.5, 1.5]^{d}", "plain": plain, "cv": forms}
 
 
-# Rows of the paper's Tables LP0d4, LP0d6_0, LP0d6_1, LP1d4 and LP1d6_1
+# Rows of the paper's Tables LP0d4, LP0d6_0, LP0d6_1, LP1d4, LP1d6_1, LP0d11
+# and LP1d11 .. LP1d15_19 up to d = 16
 # (Section 4: logistic BSDE, X = W, [-6.5, 6.5]^q in #C^q cubes, mu = 1,
 # T = 1, binary32): (table, d, basis, N, #C, M, the printed indicators
 # (MSE_Y,max, MSE_Y,av, MSE_Z,av) of eq. (mse), the printed GPU seconds on a
@@ -386,6 +387,14 @@ PAPER_ROWS = (
     ("LP1d4", 4, "LP1", 50, 10, 12500, (-4.574551, -5.143310, -3.228237), 847.83),
     ("LP1d6_1", 6, "LP1", 20, 4, 2800, (-4.075928, -4.231639, -1.791519), 20.50),
     ("LP1d6_1", 6, "LP1", 50, 6, 17500, (-3.809734, -4.529827, -2.689432), 15283.18),
+    ("LP0d11", 11, "LP0", 10, 3, 100, (-2.144843, -2.267742, -0.469759), 6.29),
+    ("LP0d11", 11, "LP0", 20, 4, 400, (-2.484169, -2.633602, -1.070096), 2108.64),
+    ("LP1d11", 11, "LP1", 5, 3, 4000, (-3.269004, -3.403994, -1.975300), 290.56),
+    ("LP1d12", 12, "LP1", 5, 3, 4000, (-3.214096, -3.272644, -1.821935), 1196.28),
+    ("LP1d13", 13, "LP1", 5, 2, 4000, (-3.022855, -3.158471, -1.649632), 16.58),
+    ("LP1d14", 14, "LP1", 5, 2, 4000, (-3.029663, -3.105833, -1.558935), 50.62),
+    ("LP1d15_19", 15, "LP1", 5, 2, 5000, (-2.981181, -3.106590, -1.574532), 139.60),
+    ("LP1d15_19", 16, "LP1", 5, 2, 6000, (-2.795353, -2.959375, -1.588716), 429.53),
 )
 
 
@@ -489,7 +498,7 @@ def main() -> int:
     ap.add_argument("--no-cv-equal-m", action="store_true",
                     help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
     ap.add_argument("--no-paper-tables", action="store_true",
-                    help="skip the paper's own workloads (Tables LP0d4 .. LP1d6_1)")
+                    help="skip the paper's own workloads (Tables LP0d4 .. LP1d15_19)")
     ap.add_argument("--no-ragged-batch", action="store_true",
                     help="skip the 64-instance ragged batch measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
