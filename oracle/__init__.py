@@ -76,6 +76,7 @@ class _Problem(ctypes.Structure):
         ("cv_bf16", ctypes.c_int32),
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
         ("cv_stride", ctypes.c_int32), ("z_center", ctypes.c_int32),
+        ("b_lin", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -148,6 +149,7 @@ class Problem:
     clamp_y: float = math.inf
     clamp_z: float = math.inf
     b: Optional[Sequence[float]] = None
+    b_lin: Optional[Sequence[float]] = None   # drift b_l + b_lin_l x_l
     sigma: Optional[Sequence[float]] = None
     seed: int = 1
     inst: int = 0
@@ -191,7 +193,7 @@ class Problem:
 
         lo, hi = arr(self.lo), arr(self.hi)
         cells = arr(self.cells, np.int32)
-        b, sig = arr(self.b), arr(self.sigma)
+        b, sig, blin = arr(self.b), arr(self.sigma), arr(self.b_lin)
         cvp = arr(self.cv_params)
         s = _Problem()
         s.d, s.q, s.T, s.N = self.d, self.q, self.T, self.N
@@ -213,6 +215,7 @@ class Problem:
         s.face_eps = self.face_eps
         s.cv_stride = self.cv_stride
         s.z_center = self.z_center
+        s.b_lin = _dp(blin) if blin is not None else None
         self._keep = keep
         return s
 

@@ -7,7 +7,9 @@
  *
  * Readings of the paper taken here (the paper is silent or garbled on them):
  *  - Euler dynamics (Section 2, Algorithm "Euler dynamics") is read with the
- *    time index of the current step j, X_{j+1} = X_j + b dt + sigma dW_j.
+ *    time index of the current step j, X_{j+1} = X_j + b(X_j) dt + sigma dW_j,
+ *    with the drift b(x)_l = b_l + b_lin_l x_l (constant b, or the
+ *    Ornstein-Uhlenbeck drift) and a constant sigma.
  *  - The z-response of Algorithm SRMDP, eq. (PsiM), uses the tail
  *    g(X_N) + sum_{j=i+1}^{N-1} f_j dt of the same path started at X_i,
  *    multiplied by dW_i / dt, as in the MDP identity eq. (MDP:intro).
@@ -565,7 +567,7 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
         for (int l = 0; l < q; ++l)
             dW[l] = sdt * stream_normal(s, d, (int64_t)(j - i) * q + l);
         for (int l = 0; l < d; ++l) {
-            double drift = P->b ? P->b[l] : 0.0;
+            double drift = (P->b ? P->b[l] : 0.0) + (P->b_lin ? P->b_lin[l] * x[l] : 0.0);
             double diff = 0.0;
             if (P->sigma)
                 for (int c = 0; c < q; ++c) diff += P->sigma[l * q + c] * dW[c];

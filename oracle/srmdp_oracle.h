@@ -59,6 +59,9 @@ typedef struct {
      * (g(X_i) when i + 1 = N) from the z response */
     int32_t cv_stride;
     int32_t z_center;
+    /* [d] diagonal linear part of the drift, b(t, x)_l = b_l + b_lin_l x_l
+     * (Ornstein-Uhlenbeck dynamics), or NULL (zero) */
+    const double *b_lin;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */

@@ -109,6 +109,67 @@ def test_pure_expectation_fits_match_projection_of_closed_form(d, cells, N, M):
     assert worst < 5.0, worst
 
 
+def _ou_cos_exact(P):
+    """Discrete closed form with the Ornstein-Uhlenbeck drift b_l + b_lin_l x_l
+    (sigma = I, f = 0, g = cos(sum x)).  The Euler chain per dimension is
+    X_{j+1} = rho X_j + b dt + dW_j with rho = 1 + b_lin dt, so from X_i = x
+    after n = N - i steps the sum of the coordinates is Gaussian with mean
+    sum_l m_l, m_l = rho_l^n x_l + b_l dt (1 + rho_l + ... + rho_l^(n-1)), and
+    variance sum_l v_l, v_l = dt (1 + rho_l^2 + ... + rho_l^(2(n-1))):
+    y_i = cos(sum m) exp(-sum v / 2) and, by Gaussian integration by parts in
+    dW_i, z_{i,l} = -rho_l^(n-1) sin(sum m) exp(-sum v / 2)."""
+    b = np.asarray(P.b, dtype=float)
+    rho = 1.0 + np.asarray(P.b_lin, dtype=float) * P.dt
+
+    def geo(r, n):
+        return np.array([float(n) if abs(x - 1.0) < 1e-15 else (x ** n - 1.0) / (x - 1.0) for x in r])
+
+    def parts(i, X):
+        n = P.N - i
+        m = (rho ** n) * X + b * P.dt * geo(rho, n)
+        return m.sum(axis=1), P.dt * geo(rho ** 2, n).sum()
+
+    def y(i):
+        def f(X):
+            sm, sv = parts(i, X)
+            return np.cos(sm) * np.exp(-sv / 2)
+        return f
+
+    def z(i, l):
+        def f(X):
+            sm, sv = parts(i, X)
+            return -rho[l] ** (P.N - i - 1) * np.sin(sm) * np.exp(-sv / 2)
+        return f
+    return y, z
+
+
+@pytest.mark.parametrize("d,cells,N,M,b,b_lin", [
+    (1, [16], 4, 20000, [0.3], [-0.8]),
+    (2, [4, 4], 3, 12000, [0.2, -0.1], [-0.5, 0.4]),
+])
+def test_ornstein_uhlenbeck_fits_match_projection_of_closed_form(d, cells, N, M, b, b_lin):
+    """The Ornstein-Uhlenbeck drift (mean reversion, and a repelling one in
+    dimension 2) with f = 0: every coefficient within 5 standard errors of the
+    projection of the discrete closed form on the local basis, as for the
+    Brownian case above."""
+    P = O.Problem(d=d, N=N, lo=[-2.0] * d, hi=[2.0] * d, cells=cells, M=M, seed=3, b=b, b_lin=b_lin)
+    tab, sing = O.solve(P)
+    assert sing == 0
+    yex, zex = _ou_cos_exact(P)
+    worst = 0.0
+    for i in range(N):
+        for k in range(P.K):
+            a, bb = _cube_bounds(P, k)
+            Xi, dW, Sp, y1, cvi = O.cloud(P, tab, i, k)
+            c, h = 0.5 * (a + bb), bb - a
+            A = np.hstack([np.ones((M, 1)), 2 * (Xi - c) / h])
+            worst = max(worst, np.max(np.abs(tab[i, k, 0] - _nu_proj(yex(i), a, bb)) / _sandwich_se(A, Sp)))
+            for l in range(P.q):
+                se_z = _sandwich_se(A, Sp * dW[:, l] / P.dt)
+                worst = max(worst, np.max(np.abs(tab[i, k, 1 + l] - _nu_proj(zex(i, l), a, bb)) / se_z))
+    assert worst < 5.0, worst
+
+
 def test_coupled_driver_matches_discrete_closed_form():
     """r = 2, kappa = 1 (strong coupling through y_{j+1} and z_j): inside the
     domain, away from the boundary cells whose extrapolation biases the paths

@@ -67,6 +67,10 @@ MUTANTS = [
      "return sz * (y - (2.0 + P->q) / (2.0 * P->q));",
      "return sz * (y + (2.0 + P->q) / (2.0 * P->q));",
      CF.test_logistic_root_readout_near_continuous_solution),
+    ("Ornstein-Uhlenbeck drift with the wrong sign",
+     "(P->b_lin ? P->b_lin[l] * x[l] : 0.0)",
+     "(P->b_lin ? -P->b_lin[l] * x[l] : 0.0)",
+     lambda: CF.test_ornstein_uhlenbeck_fits_match_projection_of_closed_form(1, [16], 4, 20000, [0.3], [-0.8])),
     ("Philox key bump skipped",
      "k0 += weyl0;",
      "k0 += 0u;",
