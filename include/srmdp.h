@@ -85,6 +85,9 @@ typedef struct {
     double r, kappa;       /* LINEAR driver parameters */
     double clamp_y, clamp_z; /* truncation levels C_y, C_z of eq. (TL), applied when a
                               * fitted function is evaluated; INFINITY = off */
+    const double *b_lin;   /* host [d]: diagonal linear drift, so that the drift is
+                            * b_l + b_lin_l x_l (Ornstein-Uhlenbeck dynamics, through the
+                            * Euler scheme of Section 2); NULL = 0 */
 } srmdp_problem;
 
 /* Stratification (assumption (A_Strat) with equal-size cells, assumption

@@ -182,7 +182,7 @@ Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options 
     L.cellF = off;
     off = align_up(off + (size_t)s.d * s.cmax * 4 * rsz, 256);
     L.bsig = off;
-    off = align_up(off + (size_t)(s.d + s.d * s.q) * rsz, 256);
+    off = align_up(off + (size_t)(2 * s.d + s.d * s.q) * rsz, 256);
     L.root_partial = off;
     off = align_up(off + (size_t)kRootBlocks * (s.d + 2) * sizeof(double), 256);
     L.root_out = off;
@@ -264,6 +264,11 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
         for (int l = 0; l < s.d; ++l)
             if (p->b[l] != 0.0) drift = true;
     a.has_drift = drift ? 1 : 0;
+    bool lin = false;
+    if (p->b_lin)
+        for (int l = 0; l < s.d; ++l)
+            if (p->b_lin[l] != 0.0) lin = true;
+    a.has_lin_drift = lin ? 1 : 0;
     if (o) {
         a.M = o->M;
         a.key0 = (uint32_t)(o->seed & 0xFFFFFFFFull);
@@ -286,6 +291,7 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
         sa.hi[l] = g->hi[l];
         sa.cells[l] = g->cells[l];
         sa.b[l] = p->b ? p->b[l] : 0.0;
+        sa.b_lin[l] = p->b_lin ? p->b_lin[l] : 0.0;
     }
     for (int t = 0; t < s.d * s.q; ++t)
         sa.sigma[t] = p->sigma ? p->sigma[t] : ((t / s.q) == (t % s.q) ? 1.0 : 0.0);
@@ -546,6 +552,7 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         put(p, sizeof *p);
         if (p->b) put(p->b, sizeof(double) * s.d);
         if (p->sigma) put(p->sigma, sizeof(double) * s.d * s.q);
+        if (p->b_lin) put(p->b_lin, sizeof(double) * s.d);
         put(g->lo, sizeof(double) * s.d);
         put(g->hi, sizeof(double) * s.d);
         put(g->cells, sizeof(int32_t) * s.d);
@@ -945,6 +952,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
             put(&P[b], sizeof P[b]);
             if (P[b].b) put(P[b].b, sizeof(double) * P[b].d);
             if (P[b].sigma) put(P[b].sigma, sizeof(double) * P[b].d * P[b].q);
+            if (P[b].b_lin) put(P[b].b_lin, sizeof(double) * P[b].d);
             put(G[b].lo, sizeof(double) * P[b].d);
             put(G[b].hi, sizeof(double) * P[b].d);
             put(G[b].cells, sizeof(int32_t) * P[b].d);
@@ -1007,7 +1015,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 103; }
+int32_t srmdp_abi_version(void) { return 104; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 

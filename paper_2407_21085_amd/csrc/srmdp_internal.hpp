@@ -50,7 +50,7 @@ struct StepArgs {
     double dt_d, inv_dt;
     int driver, terminal;
     R r, kappa, c_logistic, clamp_y, clamp_z;
-    int identity_sigma, has_drift;
+    int identity_sigma, has_drift, has_lin_drift;
     int lanes;
     int check_finite;
     size_t lds_per_cube;
@@ -73,6 +73,7 @@ struct SetupArgs {
     int cells[kMaxDim];
     double b[kMaxDim];
     double sigma[kMaxDim * kMaxDim];
+    double b_lin[kMaxDim];
     int d, q, cmax;
     double mu;
 };

@@ -148,8 +148,10 @@ __device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__res
     eval_record<R, D, NB, LK>(a, rec, xi, y, zsum);
 }
 
-// X_{j+1} = X_j + b dt + sigma dW_j (Algorithm "Euler dynamics", read with the
-// time index of the current step; exact for the constant coefficients here).
+// X_{j+1} = X_j + b(X_j) dt + sigma dW_j (Algorithm "Euler dynamics", read with
+// the time index of the current step), with b(x)_l = b_l + b_lin_l x_l: exact
+// for constant b, the Euler scheme of the Ornstein-Uhlenbeck drift otherwise.
+// bsig holds b [D], sigma [D][D] and b_lin [D].
 template <typename R, int D>
 __device__ __forceinline__ void euler_step(const StepArgs<R> &a, const R *__restrict__ bsig,
                                            const R *x, const R *dW, R *xn)
@@ -169,6 +171,10 @@ __device__ __forceinline__ void euler_step(const StepArgs<R> &a, const R *__rest
     if (a.has_drift) {
 #pragma unroll
         for (int l = 0; l < D; ++l) xn[l] += bsig[l] * a.dt;
+    }
+    if (a.has_lin_drift) {
+#pragma unroll
+        for (int l = 0; l < D; ++l) xn[l] += bsig[D + D * D + l] * x[l] * a.dt;
     }
 }
 

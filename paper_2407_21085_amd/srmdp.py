@@ -40,6 +40,7 @@ class _Problem(ctypes.Structure):
         ("driver", ctypes.c_int32), ("terminal", ctypes.c_int32),
         ("r", ctypes.c_double), ("kappa", ctypes.c_double),
         ("clamp_y", ctypes.c_double), ("clamp_z", ctypes.c_double),
+        ("b_lin", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -167,7 +168,7 @@ def _darr(v: Sequence[float]):
 
 @dataclass
 class Problem:
-    """Problem data of eq. (fbsde)-(eds) with constant coefficients."""
+    """Problem data of eq. (fbsde)-(eds): constant diffusion, drift b + diag(b_lin) x."""
     d: int
     N: int
     T: float = 1.0
@@ -180,6 +181,7 @@ class Problem:
     clamp_z: float = math.inf
     b: Optional[Sequence[float]] = None
     sigma: Optional[Sequence[float]] = None
+    b_lin: Optional[Sequence[float]] = None   # drift b_l + b_lin_l x_l (Ornstein-Uhlenbeck)
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Problem:
@@ -195,6 +197,10 @@ class Problem:
             a = _darr(self.sigma)
             self._keep.append(a)
             s.sigma = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        if self.b_lin is not None:
+            a = _darr(self.b_lin)
+            self._keep.append(a)
+            s.b_lin = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
         return s
 
 

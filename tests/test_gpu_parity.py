@@ -230,6 +230,17 @@ CASES = [
                               basis="LP1", prec="fp32", driver="linear", r=0.2, terminal="cos")),
     ("lp1 d=8 fp32", dict(d=8, N=4, lo=[-3.0] * 8, hi=[3.0] * 8, cells=[2] * 8, M=64, basis="LP1",
                           prec="fp32", driver="logistic", terminal="logistic")),
+    # Ornstein-Uhlenbeck drift b + diag(b_lin) x (mean-reverting and repelling components)
+    ("lp1 d=2 ornstein-uhlenbeck fp64", dict(d=2, N=6, lo=[-2.0] * 2, hi=[2.0] * 2, cells=[4, 3], M=50,
+                                            basis="LP1", prec="fp64", driver="linear", r=0.2, kappa=0.3,
+                                            terminal="cos", b=[0.1, -0.2], b_lin=[-0.7, 0.3])),
+    ("lp1 d=4 ornstein-uhlenbeck sigma fp64", dict(d=4, N=4, lo=[-2.0] * 4, hi=[2.0] * 4, cells=[2] * 4, M=40,
+                                                  basis="LP1", prec="fp64", driver="logistic",
+                                                  terminal="logistic", b_lin=[-0.5, -1.0, 0.2, 0.0],
+                                                  sigma=list((0.9 * np.eye(4) + 0.05).ravel()))),
+    ("lp0 d=3 ornstein-uhlenbeck fp32", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 2, 2], M=64,
+                                            basis="LP0", prec="fp32", driver="linear", r=0.1,
+                                            terminal="cos", b=[0.0, 0.2, 0.0], b_lin=[-1.0, -0.4, 0.5])),
 ]
 
 
