@@ -115,9 +115,9 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
                        uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
-// The dimensions of the high-dimension file (d = 11..16, the paper's Tables
-// LP0d11 .. LP1d15_19): binary32 sweeps with the cloud in global memory and
-// look-up modes Y and YZ, and every kernel around the sweep.
+// The dimensions of the high-dimension file (d = 7, 9, 10 and 11..16, the
+// paper's Tables LP0d11 .. LP1d15_19): binary32 sweeps with the cloud in global
+// memory and look-up modes Y and YZ, and every kernel around the sweep.
 bool hd_dimension_compiled(int d);
 template <typename R>
 hipError_t launch_step_gr_hd(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
@@ -138,6 +138,27 @@ hipError_t launch_eval_hd(int d, int basis, const StepArgs<R> &a, const void *ta
                           int64_t n, double *y, double *z, hipStream_t st);
 template <typename R>
 hipError_t launch_draw_hd(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
+                          uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
+// The same for the second high-dimension file.
+template <typename R>
+hipError_t launch_step_gr_hd2(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                             const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                             hipStream_t st);
+template <typename R>
+hipError_t launch_face_flags_hd2(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                                void *counters, hipStream_t st);
+template <typename R>
+hipError_t launch_lookup_rows_hd2(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K,
+                                 int i_lo, int i_hi, hipStream_t st);
+template <typename R>
+hipError_t launch_root_hd2(int d, int basis, int lkmode, const StepArgs<R> &a, const void *bsig,
+                          const void *lk, const RootPoint &x0, int M_root, int nblocks, double *partial,
+                          double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_eval_hd2(int d, int basis, const StepArgs<R> &a, const void *table, const double *x,
+                          int64_t n, double *y, double *z, hipStream_t st);
+template <typename R>
+hipError_t launch_draw_hd2(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
                           uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 
 // ------------------------------------------------------ batched sweeps

@@ -1,175 +1,23 @@
-// The sweep for d = 11..16 (the paper's Tables LP0d11 and LP1d11 .. LP1d15_19):
-// binary32 only, clouds in global memory (at these dimensions and the paper's
-// M the LP1 clouds are hundreds of KB per stratum), look-up modes Y and YZ,
-// and every kernel around the sweep in both precisions.
-#include <type_traits>
-
-#include "srmdp_aux.hpp"
+// The sweep for the dimensions without the LDS kernel, d = 7, 9, 10, 11 and 12
+// (the paper's Tables LP0d11, LP1d11 and LP1d12); d = 13..16 are in
+// srmdp_kernels_hd2.hip.  Binary32 only, clouds in global memory (at these
+// dimensions and the paper's M the LP1 clouds are hundreds of KB per stratum),
+// look-up modes Y and YZ, and every kernel around the sweep in both precisions.
+#define HD_DIMS(X) X(7) X(9) X(10) X(11) X(12)
+#define HD_FN(name) name
+#define HD_NEXT(name) name##2
+#define HD_KERNEL sweep_step_hd_kernel
+#define HD_IMPL launch_hd_impl
+#include "srmdp_hd_body.hpp"
 
 namespace srmdp {
-
-#define SRMDP_HD_FOR_EACH_D(X) X(11) X(12) X(13) X(14) X(15) X(16)
 
 bool hd_dimension_compiled(int d)
 {
     switch (d) {
-#define X(DD) case DD: return true;
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
+    case 7: case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: return true;
     default: return false;
     }
 }
-
-template <typename R, int D, int NB, int LK>
-__global__ void __launch_bounds__(256) sweep_step_hd_kernel(const StepArgs<R> a,
-                                                           const CellF<R> *__restrict__ cellF,
-                                                           const R *__restrict__ bsig, R *__restrict__ lk,
-                                                           R *__restrict__ table,
-                                                           unsigned long long *__restrict__ counters)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    sweep_group<R, D, NB, LK, false, true>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table,
-                                           counters, smem);
-}
-
-template <int D, int NB, int LK>
-static hipError_t launch_hd_impl(const StepArgs<float> &a, const LaunchShape &s, const void *cellF, const void *bsig,
-                                 void *lk, void *table, void *counters, hipStream_t st)
-{
-    hipLaunchKernelGGL((sweep_step_hd_kernel<float, D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st,
-                       a, (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
-                       (unsigned long long *)counters);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t launch_step_gr_hd(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
-                             const void *cellF, const void *bsig, void *lk, void *table, void *counters,
-                             hipStream_t st)
-{
-    if constexpr (!std::is_same<R, float>::value) {
-        return hipErrorInvalidValue;
-    } else {
-        if (lkmode != kLookupY && lkmode != kLookupYZ) return hipErrorInvalidValue;
-        switch (d) {
-#define X(DD)                                                                                                \
-    case DD:                                                                                                 \
-        if (basis == 0)                                                                                      \
-            return lkmode == kLookupY ? launch_hd_impl<DD, 1, kLookupY>(a, s, cellF, bsig, lk, table, counters, st) \
-                                      : launch_hd_impl<DD, 1, kLookupYZ>(a, s, cellF, bsig, lk, table, counters, st); \
-        return lkmode == kLookupY ? launch_hd_impl<DD, DD + 1, kLookupY>(a, s, cellF, bsig, lk, table, counters, st) \
-                                  : launch_hd_impl<DD, DD + 1, kLookupYZ>(a, s, cellF, bsig, lk, table, counters, st);
-            SRMDP_HD_FOR_EACH_D(X)
-#undef X
-        default: return hipErrorInvalidValue;
-        }
-    }
-}
-
-template <typename R>
-hipError_t launch_face_flags_hd(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
-                                void *counters, hipStream_t st)
-{
-    switch (d) {
-#define X(DD)                                                                              \
-    case DD:                                                                               \
-        if (basis == 0) return launch_face_flags_impl<R, DD, 1>(a, cellF, bsig, counters, st); \
-        return launch_face_flags_impl<R, DD, DD + 1>(a, cellF, bsig, counters, st);
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t launch_lookup_rows_hd(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K, int i_lo,
-                                 int i_hi, hipStream_t st)
-{
-    switch (d) {
-#define X(DD)                                                                                                    \
-    case DD:                                                                                                     \
-        if (basis == 0) {                                                                                        \
-            if (lkmode == kLookupY) return launch_lookup_rows_impl<R, DD, 1, kLookupY>(table, lk, K, i_lo, i_hi, st);   \
-            if (lkmode == kLookupYZ) return launch_lookup_rows_impl<R, DD, 1, kLookupYZ>(table, lk, K, i_lo, i_hi, st); \
-            return launch_lookup_rows_impl<R, DD, 1, kLookupFull>(table, lk, K, i_lo, i_hi, st);               \
-        }                                                                                                        \
-        if (lkmode == kLookupY) return launch_lookup_rows_impl<R, DD, DD + 1, kLookupY>(table, lk, K, i_lo, i_hi, st);   \
-        if (lkmode == kLookupYZ) return launch_lookup_rows_impl<R, DD, DD + 1, kLookupYZ>(table, lk, K, i_lo, i_hi, st); \
-        return launch_lookup_rows_impl<R, DD, DD + 1, kLookupFull>(table, lk, K, i_lo, i_hi, st);
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t launch_root_hd(int d, int basis, int lkmode, const StepArgs<R> &a, const void *bsig, const void *lk,
-                          const RootPoint &x0, int M_root, int nblocks, double *partial, double *out, hipStream_t st)
-{
-    switch (d) {
-#define X(DD)                                                                                                   \
-    case DD:                                                                                                    \
-        if (basis == 0) {                                                                                       \
-            if (lkmode == kLookupY)                                                                             \
-                return launch_root_impl<R, DD, 1, kLookupY>(a, bsig, lk, x0, M_root, nblocks, partial, out, st); \
-            if (lkmode == kLookupYZ)                                                                            \
-                return launch_root_impl<R, DD, 1, kLookupYZ>(a, bsig, lk, x0, M_root, nblocks, partial, out, st); \
-            return launch_root_impl<R, DD, 1, kLookupFull>(a, bsig, lk, x0, M_root, nblocks, partial, out, st); \
-        }                                                                                                       \
-        if (lkmode == kLookupY)                                                                                 \
-            return launch_root_impl<R, DD, DD + 1, kLookupY>(a, bsig, lk, x0, M_root, nblocks, partial, out, st); \
-        if (lkmode == kLookupYZ)                                                                                \
-            return launch_root_impl<R, DD, DD + 1, kLookupYZ>(a, bsig, lk, x0, M_root, nblocks, partial, out, st); \
-        return launch_root_impl<R, DD, DD + 1, kLookupFull>(a, bsig, lk, x0, M_root, nblocks, partial, out, st);
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t launch_eval_hd(int d, int basis, const StepArgs<R> &a, const void *table, const double *x, int64_t n,
-                          double *y, double *z, hipStream_t st)
-{
-    switch (d) {
-#define X(DD)                                                                                    \
-    case DD:                                                                                     \
-        if (basis == 0) return launch_eval_impl<R, DD, 1>(a, table, x, n, y, z, st);             \
-        return launch_eval_impl<R, DD, DD + 1>(a, table, x, n, y, z, st);
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t launch_draw_hd(int d, const StepArgs<R> &a, const SetupArgs &sa, int kind, uint32_t k0, uint32_t nk,
-                          uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st)
-{
-    switch (d) {
-#define X(DD) \
-    case DD: return launch_draw_impl<R, DD>(a, sa, kind, k0, nk, m0, nm, count, out, st);
-        SRMDP_HD_FOR_EACH_D(X)
-#undef X
-    default: return hipErrorInvalidValue;
-    }
-}
-
-#define SRMDP_HD_INSTANTIATE(R)                                                                                     \
-    template hipError_t launch_step_gr_hd<R>(int, const StepArgs<R> &, const LaunchShape &, int, int, const void *, \
-                                             const void *, void *, void *, void *, hipStream_t);                    \
-    template hipError_t launch_face_flags_hd<R>(int, int, const StepArgs<R> &, const void *, const void *, void *, \
-                                                hipStream_t);                                                      \
-    template hipError_t launch_lookup_rows_hd<R>(int, int, int, const void *, void *, uint32_t, int, int,          \
-                                                 hipStream_t);                                                     \
-    template hipError_t launch_root_hd<R>(int, int, int, const StepArgs<R> &, const void *, const void *,          \
-                                          const RootPoint &, int, int, double *, double *, hipStream_t);           \
-    template hipError_t launch_eval_hd<R>(int, int, const StepArgs<R> &, const void *, const double *, int64_t,    \
-                                          double *, double *, hipStream_t);                                        \
-    template hipError_t launch_draw_hd<R>(int, const StepArgs<R> &, const SetupArgs &, int, uint32_t, uint32_t,    \
-                                          uint32_t, uint32_t, int, double *, hipStream_t);
-
-SRMDP_HD_INSTANTIATE(float)
-SRMDP_HD_INSTANTIATE(double)
 
 }  // namespace srmdp

@@ -179,9 +179,10 @@ def test_global_rows_workspace_and_rejections():
 
 
 def test_high_dimensions_run_binary32_sweeps_only():
-    """d = 11..16 have the global-rows sweep in binary32 with look-up modes Y
-    and YZ only: binary64, z truncation (mode Full) and the control variate are
-    refused before anything is enqueued; d = 9 is not compiled."""
+    """d = 7, 9, 10 and 11..16 have the global-rows sweep in binary32 with
+    look-up modes Y and YZ only: binary64, z truncation (mode Full) and the
+    control variate are refused before anything is enqueued; d = 17 is outside
+    the ABI."""
     S = _S()
     G = S.Grid([-1.0] * 11, [1.0] * 11, [2] * 11)
     for P, O, status in [
@@ -191,10 +192,10 @@ def test_high_dimensions_run_binary32_sweeps_only():
     ]:
         rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
         assert rc == status, S.srmdp.lib.srmdp_last_error().decode()
-    G9 = S.Grid([-1.0] * 9, [1.0] * 9, [2] * 9)
-    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=9, N=3).c(), G9.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16,
+    G17 = S.Grid([-1.0] * 17, [1.0] * 17, [2] * 17)
+    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=17, N=3).c(), G17.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16,
                                  1 << 40, None, None)
-    assert rc == -2
+    assert rc == -1
 
 
 def test_online_workspace_holds_training_state():

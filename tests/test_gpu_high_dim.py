@@ -1,6 +1,7 @@
-"""The high dimensions d = 11..16 (the paper's Tables LP0d11 and LP1d11 ..
-LP1d15_19): binary32 sweeps with the clouds in global memory, per step against
-the FP64 oracle from the same rows (GPU tests, through the C ABI)."""
+"""The dimensions without the LDS kernel, d = 7, 9, 10 and 11..16 (the paper's
+Tables LP0d11 and LP1d11 .. LP1d15_19): binary32 sweeps with the clouds in
+global memory, per step against the FP64 oracle from the same rows (GPU tests,
+through the C ABI)."""
 import sys
 
 import numpy as np
@@ -23,6 +24,9 @@ def _logistic(d, cells, M, N, basis="LP1"):
 
 
 @pytest.mark.parametrize("d,cells,M,basis", [
+    (7, [2] * 7, 40, "LP1"),
+    (9, [2] * 5 + [1] * 4, 40, "LP1"),
+    (10, [3] * 3 + [1] * 7, 32, "LP0"),
     (11, [2] * 6 + [1] * 5, 48, "LP1"),
     (13, [2] * 5 + [1] * 8, 40, "LP1"),
     (16, [2] * 8 + [1] * 8, 64, "LP1"),
