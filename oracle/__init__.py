@@ -27,6 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "libsrmdp_oracle.so")
 LP0, LP1 = 0, 1
 DRV_LINEAR, DRV_LOGISTIC = 0, 1
 G_COS_SUM, G_LOGISTIC = 0, 1
+GRID_EQUAL_SIZE, GRID_EQUAL_PROB = 0, 1
 
 
 def compile_source(src: str, out: str) -> str:
@@ -77,6 +78,7 @@ class _Problem(ctypes.Structure):
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
         ("cv_stride", ctypes.c_int32), ("z_center", ctypes.c_int32),
         ("b_lin", ctypes.POINTER(ctypes.c_double)),
+        ("grid_kind", ctypes.c_int32),
     ]
 
 
@@ -134,8 +136,8 @@ class Problem:
     """Problem data, stratification and simulation settings of one sweep."""
     d: int
     N: int
-    lo: Sequence[float]
-    hi: Sequence[float]
+    lo: Optional[Sequence[float]]   # ignored (may be None) for GRID_EQUAL_PROB
+    hi: Optional[Sequence[float]]
     cells: Sequence[int]
     M: int
     T: float = 1.0
@@ -160,6 +162,7 @@ class Problem:
     face_eps: float = 1e-5
     cv_stride: int = 1
     z_center: int = 0
+    grid_kind: int = GRID_EQUAL_SIZE
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -201,7 +204,8 @@ class Problem:
         s.sigma = _dp(sig) if sig is not None else None
         s.driver, s.terminal, s.r, s.kappa = self.driver, self.terminal, self.r, self.kappa
         s.clamp_y, s.clamp_z = self.clamp_y, self.clamp_z
-        s.lo, s.hi = _dp(lo), _dp(hi)
+        s.lo = _dp(lo) if lo is not None else None
+        s.hi = _dp(hi) if hi is not None else None
         s.cells = cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         s.mu, s.M, s.basis = self.mu, self.M, self.basis
         s.seed, s.inst = self.seed, self.inst
@@ -216,6 +220,7 @@ class Problem:
         s.cv_stride = self.cv_stride
         s.z_center = self.z_center
         s.b_lin = _dp(blin) if blin is not None else None
+        s.grid_kind = self.grid_kind
         self._keep = keep
         return s
 

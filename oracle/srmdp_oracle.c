@@ -150,35 +150,56 @@ static double stream_normal(path_stream *s, int d, int64_t n)
 typedef struct {
     int d;
     int64_t K;
+    int kind;  /* ORC_GRID_* */
+    double mu;
     double lo[64], hi[64], h[64];
     int32_t cells[64];
     int64_t stride[64];
 } grid_t;
 
+static double logistic_cdf(double mu, double x) { return 1.0 / (1.0 + exp(-mu * x)); }
+
+/* Logistic quantile F^{-1}(p) = log(p / (1 - p)) / mu. */
+static double logistic_quantile(double mu, double p) { return log(p / (1.0 - p)) / mu; }
+
 static int grid_init(const orc_problem *P, grid_t *G)
 {
     if (P->d < 1 || P->d > 64) return -1;
+    if (P->grid_kind != ORC_GRID_EQUAL_SIZE && P->grid_kind != ORC_GRID_EQUAL_PROB) return -1;
     G->d = P->d;
     G->K = 1;
+    G->kind = P->grid_kind;
+    G->mu = P->mu;
     for (int l = 0; l < P->d; ++l) {
-        if (!(P->lo[l] < P->hi[l]) || P->cells[l] < 1) return -1;
-        G->lo[l] = P->lo[l];
-        G->hi[l] = P->hi[l];
+        if (P->cells[l] < 1) return -1;
+        if (G->kind == ORC_GRID_EQUAL_SIZE) {
+            if (!(P->lo[l] < P->hi[l])) return -1;
+            G->lo[l] = P->lo[l];
+            G->hi[l] = P->hi[l];
+            G->h[l] = (P->hi[l] - P->lo[l]) / (double)P->cells[l];
+        }
         G->cells[l] = P->cells[l];
-        G->h[l] = (P->hi[l] - P->lo[l]) / (double)P->cells[l];
         G->stride[l] = G->K; /* dimension 0 varies fastest */
         G->K *= P->cells[l];
     }
     return 0;
 }
 
-/* Cell of x along dimension l: floor((x - lo) * (C / (hi - lo))), clamped to
- * the boundary cells (points outside the domain belong to the nearest
+/* Position of x along dimension l in cell widths: (x - lo) C / (hi - lo) for
+ * equal-size cells; C F(x) for equal-probability cells, whose c-th cell is
+ * the set where c <= C F(x) < c + 1. */
+static double cell_coord(const grid_t *G, int l, double x)
+{
+    if (G->kind == ORC_GRID_EQUAL_PROB) return (double)G->cells[l] * logistic_cdf(G->mu, x);
+    return (x - G->lo[l]) * ((double)G->cells[l] / (G->hi[l] - G->lo[l]));
+}
+
+/* Cell of x along dimension l: floor of its coordinate, clamped to the
+ * boundary cells (points outside an equal-size domain belong to the nearest
  * boundary cell for evaluation). */
 static int64_t cell_of(const grid_t *G, int l, double x)
 {
-    double scale = (double)G->cells[l] / (G->hi[l] - G->lo[l]);
-    double c = floor((x - G->lo[l]) * scale);
+    double c = floor(cell_coord(G, l, x));
     if (c < 0.0) c = 0.0;
     if (c > (double)(G->cells[l] - 1)) c = (double)(G->cells[l] - 1);
     return (int64_t)c;
@@ -195,8 +216,7 @@ static int64_t cube_of(const grid_t *G, const double *x)
 static int near_interior_face(const grid_t *G, const double *x, double eps)
 {
     for (int l = 0; l < G->d; ++l) {
-        double scale = (double)G->cells[l] / (G->hi[l] - G->lo[l]);
-        double t = (x[l] - G->lo[l]) * scale;
+        double t = cell_coord(G, l, x[l]);
         double c = (double)cell_of(G, l, x[l]);
         double frac = t - c;
         if (frac < eps && c > 0.0 && t >= 0.0) return 1;
@@ -211,7 +231,10 @@ static int64_t cube_cell(const grid_t *G, int64_t k, int l)
 }
 
 /* Basis of the local spaces of assumption (A_Strat): LP0 = {1}, LP1 =
- * {1, xi_1..xi_d} with xi the cube-centred and scaled coordinate. */
+ * {1, xi_1..xi_d} with xi an affine coordinate of the cube.  Equal-size
+ * cells: xi = 2 (x - centre) / h, in [-1, 1) inside the cube.  Equal-
+ * probability cells, unbounded at the ends: xi = mu (x - m) with m the
+ * cell's nu-median F^{-1}((c + 1/2) / C).  Only the span enters the fit. */
 static int basis_size(const orc_problem *P) { return P->basis == ORC_LP1 ? P->d + 1 : 1; }
 
 static void basis_eval(const orc_problem *P, const grid_t *G, int64_t k, const double *x,
@@ -220,9 +243,14 @@ static void basis_eval(const orc_problem *P, const grid_t *G, int64_t k, const d
     phi[0] = 1.0;
     if (P->basis != ORC_LP1) return;
     for (int l = 0; l < G->d; ++l) {
-        double lower = G->lo[l] + (double)cube_cell(G, k, l) * G->h[l];
-        double centre = lower + 0.5 * G->h[l];
-        phi[1 + l] = 2.0 * (x[l] - centre) / G->h[l];
+        double c = (double)cube_cell(G, k, l);
+        if (G->kind == ORC_GRID_EQUAL_PROB) {
+            double m = logistic_quantile(G->mu, (c + 0.5) / (double)G->cells[l]);
+            phi[1 + l] = G->mu * (x[l] - m);
+        } else {
+            double centre = G->lo[l] + (c + 0.5) * G->h[l];
+            phi[1 + l] = 2.0 * (x[l] - centre) / G->h[l];
+        }
     }
 }
 
@@ -460,12 +488,9 @@ static int64_t rec_size(const orc_problem *P) { return (int64_t)(1 + P->q) * bas
 /* ---------------------------------------------------- sampling (nu_k) -- */
 
 /* Algorithm "stratify": inverse CDF of the logistic law restricted to
- * [x-, x+), F(x) = 1 / (1 + exp(-mu x)). */
-static double logistic_cdf(double mu, double x) { return 1.0 / (1.0 + exp(-mu * x)); }
-
-static double stratify_one(double mu, double xm, double xp, double U)
+ * [x-, x+), F(x) = 1 / (1 + exp(-mu x)), given Fm = F(x-) and Fp = F(x+). */
+static double stratify_one(double mu, double Fm, double Fp, double U)
 {
-    double Fm = logistic_cdf(mu, xm), Fp = logistic_cdf(mu, xp);
     return -(1.0 / mu) * log(1.0 / (Fm + U * (Fp - Fm)) - 1.0);
 }
 
@@ -473,9 +498,17 @@ static void start_point(const orc_problem *P, const grid_t *G, path_stream *s, i
                         double *x)
 {
     for (int l = 0; l < P->d; ++l) {
-        double xm = G->lo[l] + (double)cube_cell(G, k, l) * G->h[l];
-        double xp = xm + G->h[l];
-        x[l] = stratify_one(P->mu, xm, xp, stream_uniform(s, l));
+        double c = (double)cube_cell(G, k, l), Fm, Fp;
+        if (G->kind == ORC_GRID_EQUAL_PROB) {
+            /* F at the quantile edges: c / C and (c + 1) / C */
+            Fm = c / (double)G->cells[l];
+            Fp = (c + 1.0) / (double)G->cells[l];
+        } else {
+            double xm = G->lo[l] + c * G->h[l];
+            Fm = logistic_cdf(P->mu, xm);
+            Fp = logistic_cdf(P->mu, xm + G->h[l]);
+        }
+        x[l] = stratify_one(P->mu, Fm, Fp, stream_uniform(s, l));
     }
 }
 

@@ -24,6 +24,7 @@ extern "C" {
 #endif
 
 enum { ORC_LP0 = 0, ORC_LP1 = 1 };
+enum { ORC_GRID_EQUAL_SIZE = 0, ORC_GRID_EQUAL_PROB = 1 };
 enum { ORC_DRV_LINEAR = 0, ORC_DRV_LOGISTIC = 1 };
 enum { ORC_G_COS_SUM = 0, ORC_G_LOGISTIC = 1 };
 
@@ -62,6 +63,12 @@ typedef struct {
     /* [d] diagonal linear part of the drift, b(t, x)_l = b_l + b_lin_l x_l
      * (Ornstein-Uhlenbeck dynamics), or NULL (zero) */
     const double *b_lin;
+    /* ORC_GRID_EQUAL_SIZE: cells of width (hi - lo) / cells inside [lo, hi),
+     * the outer ones extended to the nearest boundary cell for evaluation.
+     * ORC_GRID_EQUAL_PROB: per dimension the cells' edges are the logistic
+     * quantiles F^{-1}(c / cells), c = 0..cells, so that every cube has
+     * nu-probability 1/K and the cubes cover R^d (lo and hi are ignored). */
+    int32_t grid_kind;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */

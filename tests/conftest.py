@@ -16,5 +16,9 @@ def pytest_configure(config):
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
     import oracle
-    oracle.build(force=not os.path.exists(oracle._LIB_PATH))
+    # rebuilt when missing or older than its C source or header
+    lib = oracle._LIB_PATH
+    srcs = [oracle._SRC, os.path.splitext(oracle._SRC)[0] + ".h"]
+    stale = not os.path.exists(lib) or any(os.path.getmtime(s) > os.path.getmtime(lib) for s in srcs)
+    oracle.build(force=stale)
     yield

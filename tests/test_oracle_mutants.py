@@ -9,6 +9,7 @@ import pytest
 
 import oracle as O
 import test_oracle_closed_form as CF
+import test_oracle_equal_prob as EP
 import test_oracle_regression as RG
 import test_oracle_rng as RN
 
@@ -48,8 +49,9 @@ MUTANTS = [
      "for (int32_t j = i; j < P->N - 1; ++j) {\n        for (int l = 0; l < q; ++l)",
      _pure_expectation),
     ("start point uniform in the cube",
-     "x[l] = stratify_one(P->mu, xm, xp, stream_uniform(s, l));",
-     "x[l] = xm + stream_uniform(s, l) * (xp - xm);",
+     "x[l] = stratify_one(P->mu, Fm, Fp, stream_uniform(s, l));",
+     "x[l] = G->kind ? stratify_one(P->mu, Fm, Fp, stream_uniform(s, l))\n"
+     "                : G->lo[l] + (c + stream_uniform(s, l)) * G->h[l];",
      lambda: RN.test_start_sampler_in_cube_ks_and_mean(21, 1.0)),
     ("Box-Muller pair reuses the cosine",
      "return (n % 2 == 0) ? rho * cos(theta) : rho * sin(theta);",
@@ -60,9 +62,22 @@ MUTANTS = [
      "for (int t = 0; t < c; ++t) s -= L[t * n + r] * L[c * n + t];",
      _brute_force_lp1),
     ("uncentred basis",
-     "phi[1 + l] = 2.0 * (x[l] - centre) / G->h[l];",
-     "phi[1 + l] = 2.0 * (x[l] - lower) / G->h[l];",
+     "double centre = G->lo[l] + (c + 0.5) * G->h[l];",
+     "double centre = G->lo[l] + c * G->h[l];",
      _brute_force_lp1),
+    ("equal-probability edges at equal-size positions",
+     "Fm = c / (double)G->cells[l];\n            Fp = (c + 1.0) / (double)G->cells[l];",
+     "Fm = logistic_cdf(P->mu, -4.0 + 8.0 * c / G->cells[l]);\n"
+     "            Fp = logistic_cdf(P->mu, -4.0 + 8.0 * (c + 1.0) / G->cells[l]);",
+     lambda: EP.test_equal_probability_sampler_law(1.3, [5, 3])),
+    ("equal-probability look-up mirrored",
+     "return (double)G->cells[l] * logistic_cdf(G->mu, x);",
+     "return (double)G->cells[l] * logistic_cdf(G->mu, -x);",
+     lambda: EP.test_equal_probability_lookup_matches_strata(0.7, [4, 6])),
+    ("equal-probability basis centred on the lower edge",
+     "double m = logistic_quantile(G->mu, (c + 0.5) / (double)G->cells[l]);",
+     "double m = logistic_quantile(G->mu, (c + 0.01) / (double)G->cells[l]);",
+     lambda: EP.test_equal_probability_fits_match_projection(1, [8], 3, 20000)),
     ("logistic driver constant with the wrong sign",
      "return sz * (y - (2.0 + P->q) / (2.0 * P->q));",
      "return sz * (y + (2.0 + P->q) / (2.0 * P->q));",
