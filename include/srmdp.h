@@ -90,14 +90,26 @@ typedef struct {
                             * Euler scheme of Section 2); NULL = 0 */
 } srmdp_problem;
 
-/* Stratification (assumption (A_Strat) with equal-size cells, assumption
- * (A_nu) for the sampling law).  Cells are half-open; points outside
- * [lo, hi) are evaluated with the affine fit of the nearest boundary cell;
- * only the K = prod(cells) bounded cells are sampled. */
+/* Stratification: the two examples of hypercubes under assumption
+ * (A_Strat), with the sampling law of assumption (A_nu).
+ * SRMDP_GRID_EQUAL_SIZE: cells[l] half-open cells of equal width in
+ *   [lo, hi); points outside are evaluated with the fit of the nearest
+ *   boundary cell; only the K = prod(cells) bounded cells are sampled.
+ * SRMDP_GRID_EQUAL_PROB: the cells of dimension l are cut at the logistic
+ *   quantiles F^{-1}(c / cells[l]), F(x) = 1 / (1 + exp(-mu x)), so that each
+ *   of the K cubes has nu-probability 1/K and they cover R^d (the two outer
+ *   cells of each dimension are unbounded); lo and hi are ignored (may be
+ *   NULL).  The LP1 coordinate of an equal-probability cell is mu (x - m),
+ *   m the cell's nu-median F^{-1}((c + 1/2) / cells[l]); for an equal-size
+ *   cell it is 2 (x - centre) / width.  Table coefficients are in these
+ *   coordinates. */
+typedef enum { SRMDP_GRID_EQUAL_SIZE = 0, SRMDP_GRID_EQUAL_PROB = 1 } srmdp_grid_kind;
+
 typedef struct {
-    const double *lo, *hi;   /* host [d], lo < hi */
+    const double *lo, *hi;   /* host [d], lo < hi (SRMDP_GRID_EQUAL_SIZE only) */
     const int32_t *cells;    /* host [d], >= 1; K = prod(cells) <= 2^24 */
     double mu;               /* logistic parameter > 0 */
+    int32_t kind;            /* srmdp_grid_kind; 0 (a zero-initialised struct) = equal size */
 } srmdp_grid;
 
 /* Learned martingale control variate (not part of the paper's scheme).  A

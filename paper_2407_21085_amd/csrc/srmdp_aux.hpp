@@ -12,6 +12,17 @@ template <typename R>
 __device__ __forceinline__ CellF<R> cell_constants(const SetupArgs &a, int l, int c)
 {
     CellF<R> v{};
+    if (a.equal_prob) {
+        // F = c / n and (c + 1) / n at the edges, (c + 1/2) / n at the centre (the
+        // cell's nu-median); the outer cells are unbounded, which the inverse-CDF
+        // offset from the centre does not see
+        const double n = (double)a.cells[l], lo_n = c + 0.5, hi_n = n - c - 0.5;
+        v.uc = (R)0.5;
+        v.rp = (R)(1.0 / lo_n);
+        v.rs = (R)(1.0 / hi_n);
+        v.centre = (R)(log(lo_n / hi_n) / a.mu);
+        return v;
+    }
     const double h = (a.hi[l] - a.lo[l]) / (double)a.cells[l];
     const double xm = a.lo[l] + c * h, xp = xm + h, xc = xm + 0.5 * h;
     const double F_m = 1.0 / (1.0 + exp(-a.mu * xm)), F_p = 1.0 / (1.0 + exp(-a.mu * xp));
@@ -60,7 +71,7 @@ __global__ void lookup_rows_kernel(const R *__restrict__ table, R *__restrict__ 
 }
 
 // ----------------------------------------------------------------- eval
-template <typename R, int D, int NB>
+template <typename R, int D, int NB, bool EP>
 __global__ void eval_kernel(const StepArgs<R> a, const R *__restrict__ table, const double *__restrict__ x,
                             int64_t n, double *__restrict__ y, double *__restrict__ z)
 {
@@ -71,10 +82,7 @@ __global__ void eval_kernel(const StepArgs<R> a, const R *__restrict__ table, co
         uint32_t k = 0;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-            const R xv = (R)x[p * D + l];
-            const R tt = (xv - a.lo[l]) * a.scale[l];
-            const R c = RealOps<R>::clamp_cell(tt, a.cmax_f[l]);
-            xi[l] = (R)2 * (tt - c) - (R)1;
+            const R c = cell_and_xi<R, EP>(a, l, (R)x[p * D + l], xi[l]);
             k += (uint32_t)c * a.stride[l];
         }
         const R *rec = table + ((size_t)a.i * a.K + k) * REC;
@@ -98,7 +106,7 @@ __global__ void eval_kernel(const StepArgs<R> a, const R *__restrict__ table, co
 // Paths from the fixed point x0 at step 0 (counter stratum SRMDP_ROOT_STRATUM).
 // Per-block binary64 partial sums of S', y_1(X_1) and S' dW_0,l are written in
 // block order; root_finish_kernel reduces them in a fixed order.
-template <typename R, int D, int NB, int LK>
+template <typename R, int D, int NB, int LK, bool EP>
 __global__ void __launch_bounds__(256) root_paths_kernel(const StepArgs<R> a, const R *__restrict__ bsig,
                                                         const R *__restrict__ lk, RootPoint x0, int M_root,
                                                         double *__restrict__ partial)
@@ -116,7 +124,7 @@ __global__ void __launch_bounds__(256) root_paths_kernel(const StepArgs<R> a, co
         NormalStream<R, D> ns;
         ns.init(key, (uint32_t)m, 0xFFFFFFFFu, a.tag, a.sqrt_dt);
         R dW0[D], y1, Sp;
-        run_path<R, D, NB, LK>(a, bsig, lk, ns, x, dW0, y1, Sp);
+        run_path<R, D, NB, LK, false, EP>(a, bsig, lk, ns, x, dW0, y1, Sp);
         acc[0] += (double)Sp;
         acc[1] += (double)y1;
 #pragma unroll
@@ -196,11 +204,24 @@ __global__ void draw_kernel(const StepArgs<R> a, const SetupArgs sa, int kind,
 
 // ------------------------------------------------------------- launchers
 
+// Dimensions with the equal-probability grid (those of the binary64 and LDS
+// sweep kernels); the kernels of the other dimensions take equal-size cells only.
+template <int D>
+constexpr bool kEqualProbDim = D <= 6 || D == 8;
+
 template <typename R, int D, int NB>
 static hipError_t launch_face_flags_impl(const StepArgs<R> &a, const void *cellF, const void *bsig,
                                          void *counters, hipStream_t st)
 {
-    hipLaunchKernelGGL((face_flags_kernel<R, D, NB>), dim3(a.K), dim3(64), 0, st, a,
+    if (a.equal_prob) {
+        if constexpr (kEqualProbDim<D>) {
+            hipLaunchKernelGGL((face_flags_kernel<R, D, NB, true>), dim3(a.K), dim3(64), 0, st, a,
+                               (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((face_flags_kernel<R, D, NB, false>), dim3(a.K), dim3(64), 0, st, a,
                        (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
     return hipGetLastError();
 }
@@ -221,8 +242,17 @@ static hipError_t launch_root_impl(const StepArgs<R> &a, const void *bsig, const
                                    const RootPoint &x0, int M_root, int nblocks, double *partial,
                                    double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK>), dim3(nblocks), dim3(256), 0, st, a,
-                       (const R *)bsig, (const R *)lk, x0, M_root, partial);
+    if (a.equal_prob) {
+        if constexpr (kEqualProbDim<D>) {
+            hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK, true>), dim3(nblocks), dim3(256), 0, st, a,
+                               (const R *)bsig, (const R *)lk, x0, M_root, partial);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK, false>), dim3(nblocks), dim3(256), 0, st, a,
+                           (const R *)bsig, (const R *)lk, x0, M_root, partial);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((root_finish_kernel<R, D>), dim3(1), dim3(64), 0, st, a, partial, nblocks,
@@ -236,7 +266,15 @@ static hipError_t launch_eval_impl(const StepArgs<R> &a, const void *table, cons
 {
     const int64_t blocks64 = (n + 255) / 256;
     const int blocks = (int)(blocks64 < 16384 ? (blocks64 > 0 ? blocks64 : 1) : 16384);
-    hipLaunchKernelGGL((eval_kernel<R, D, NB>), dim3(blocks), dim3(256), 0, st, a, (const R *)table,
+    if (a.equal_prob) {
+        if constexpr (kEqualProbDim<D>) {
+            hipLaunchKernelGGL((eval_kernel<R, D, NB, true>), dim3(blocks), dim3(256), 0, st, a,
+                               (const R *)table, x, n, y, z);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((eval_kernel<R, D, NB, false>), dim3(blocks), dim3(256), 0, st, a, (const R *)table,
                        x, n, y, z);
     return hipGetLastError();
 }

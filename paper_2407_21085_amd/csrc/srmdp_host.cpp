@@ -56,6 +56,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Shape {
     int d, q, N, nb, cmax;
     uint64_t K;
+    bool equal_prob;  // SRMDP_GRID_EQUAL_PROB
 };
 
 srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s)
@@ -76,15 +77,20 @@ srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s
         return fail(SRMDP_E_INVALID, "truncation levels must be > 0 (INFINITY = off)");
     if (!std::isfinite(p->r) || !std::isfinite(p->kappa))
         return fail(SRMDP_E_INVALID, "driver parameters must be finite");
-    if (!g->lo || !g->hi || !g->cells) return fail(SRMDP_E_INVALID, "grid arrays must be non-NULL");
+    if (g->kind != SRMDP_GRID_EQUAL_SIZE && g->kind != SRMDP_GRID_EQUAL_PROB)
+        return fail(SRMDP_E_INVALID, "unknown grid kind %d", (int)g->kind);
+    const bool equal_size = g->kind == SRMDP_GRID_EQUAL_SIZE;
+    if (!g->cells || (equal_size && (!g->lo || !g->hi)))
+        return fail(SRMDP_E_INVALID, "grid arrays must be non-NULL");
     if (!(g->mu > 0.0) || !std::isfinite(g->mu)) return fail(SRMDP_E_INVALID, "mu must be > 0");
     s.d = p->d;
     s.q = p->q;
     s.N = p->N;
+    s.equal_prob = !equal_size;
     s.K = 1;
     s.cmax = 1;
     for (int l = 0; l < p->d; ++l) {
-        if (!(g->lo[l] < g->hi[l]) || !std::isfinite(g->lo[l]) || !std::isfinite(g->hi[l]))
+        if (equal_size && (!(g->lo[l] < g->hi[l]) || !std::isfinite(g->lo[l]) || !std::isfinite(g->hi[l])))
             return fail(SRMDP_E_INVALID, "grid dimension %d: need finite lo < hi", l);
         if (g->cells[l] < 1) return fail(SRMDP_E_INVALID, "grid dimension %d: cells < 1", l);
         s.K *= (uint64_t)g->cells[l];
@@ -123,6 +129,10 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     if (o->global_rows_strata < 0) return fail(SRMDP_E_INVALID, "global_rows_strata < 0");
     if ((o->flags & SRMDP_F_GLOBAL_ROWS) && o->cv != SRMDP_CV_NONE)
         return fail(SRMDP_E_UNSUPPORTED, "global cloud rows run without the control variate");
+    if (s.equal_prob && o->cv != SRMDP_CV_NONE)
+        return fail(SRMDP_E_UNSUPPORTED, "equal-probability cells run without the control variate");
+    if (s.equal_prob && !lds_dimension_compiled(s.d))
+        return fail(SRMDP_E_UNSUPPORTED, "equal-probability cells are compiled for d = 1..6 and 8, not %d", s.d);
     if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
         return fail(SRMDP_E_INVALID, "SRMDP_F_CV_CENTER_Z needs a control variate");
     if (o->cv_stride > 65535) return fail(SRMDP_E_INVALID, "cv_stride above 65535");
@@ -229,8 +239,13 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
     std::memset(&a, 0, sizeof a);
     uint32_t stride = 1;
     for (int l = 0; l < s.d; ++l) {
-        a.lo[l] = (R)g->lo[l];
-        a.scale[l] = (R)((double)g->cells[l] / (g->hi[l] - g->lo[l]));
+        if (g->kind == SRMDP_GRID_EQUAL_PROB) {
+            a.lo[l] = (R)0;
+            a.scale[l] = (R)(0.5 * g->mu);
+        } else {
+            a.lo[l] = (R)g->lo[l];
+            a.scale[l] = (R)((double)g->cells[l] / (g->hi[l] - g->lo[l]));
+        }
         a.cmax_f[l] = (R)(g->cells[l] - 1);
         a.stride[l] = stride;
         a.stride_f[l] = (R)stride;
@@ -246,6 +261,7 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
     a.sqrt_dt = (R)std::sqrt(a.dt_d);
     a.T = (R)p->T;
     a.inv_mu = (R)(1.0 / g->mu);
+    a.equal_prob = g->kind == SRMDP_GRID_EQUAL_PROB ? 1 : 0;
     a.driver = p->driver;
     a.terminal = p->terminal;
     a.r = (R)p->r;
@@ -287,8 +303,8 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
 {
     std::memset(&sa, 0, sizeof sa);
     for (int l = 0; l < s.d; ++l) {
-        sa.lo[l] = g->lo[l];
-        sa.hi[l] = g->hi[l];
+        sa.lo[l] = g->kind == SRMDP_GRID_EQUAL_SIZE ? g->lo[l] : 0.0;
+        sa.hi[l] = g->kind == SRMDP_GRID_EQUAL_SIZE ? g->hi[l] : 0.0;
         sa.cells[l] = g->cells[l];
         sa.b[l] = p->b ? p->b[l] : 0.0;
         sa.b_lin[l] = p->b_lin ? p->b_lin[l] : 0.0;
@@ -299,6 +315,7 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
     sa.q = s.q;
     sa.cmax = s.cmax;
     sa.mu = g->mu;
+    sa.equal_prob = g->kind == SRMDP_GRID_EQUAL_PROB ? 1 : 0;
 }
 
 // Lanes per stratum: enough to give every lane one path up to a wavefront.
@@ -360,7 +377,8 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
         return true;
     }
     const size_t lds_cap = 64 * 1024;
-    const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d);
+    // equal-probability cells run on the global-cloud kernels only
+    const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d) || s.equal_prob;
     if (force || per_cube > lds_cap) {
         ls.grows = true;
         per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
@@ -553,8 +571,11 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         if (p->b) put(p->b, sizeof(double) * s.d);
         if (p->sigma) put(p->sigma, sizeof(double) * s.d * s.q);
         if (p->b_lin) put(p->b_lin, sizeof(double) * s.d);
-        put(g->lo, sizeof(double) * s.d);
-        put(g->hi, sizeof(double) * s.d);
+        put(&g->kind, sizeof g->kind);
+        if (g->kind == SRMDP_GRID_EQUAL_SIZE) {
+            put(g->lo, sizeof(double) * s.d);
+            put(g->hi, sizeof(double) * s.d);
+        }
         put(g->cells, sizeof(int32_t) * s.d);
         put(&g->mu, sizeof g->mu);
         put(o, sizeof *o);
@@ -829,6 +850,8 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
         }
         if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0)
             return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
+        if (bp.shapes[b].equal_prob)
+            return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run equal-size cells", b);
         bp.gmax = std::max(bp.gmax, P[b].N);
     }
     if (!lds_dimension_compiled(P[0].d))
@@ -953,8 +976,11 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
             if (P[b].b) put(P[b].b, sizeof(double) * P[b].d);
             if (P[b].sigma) put(P[b].sigma, sizeof(double) * P[b].d * P[b].q);
             if (P[b].b_lin) put(P[b].b_lin, sizeof(double) * P[b].d);
-            put(G[b].lo, sizeof(double) * P[b].d);
-            put(G[b].hi, sizeof(double) * P[b].d);
+            put(&G[b].kind, sizeof G[b].kind);
+            if (G[b].kind == SRMDP_GRID_EQUAL_SIZE) {
+                put(G[b].lo, sizeof(double) * P[b].d);
+                put(G[b].hi, sizeof(double) * P[b].d);
+            }
             put(G[b].cells, sizeof(int32_t) * P[b].d);
             put(&G[b].mu, sizeof G[b].mu);
             put(&O[b], sizeof O[b]);
@@ -1015,7 +1041,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 104; }
+int32_t srmdp_abi_version(void) { return 105; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 

@@ -36,8 +36,9 @@ inline int lookup_width(int prec_is_float, int d, int nb, int lk)
 // Kernel arguments of one backward step (passed by value).
 template <typename R>
 struct StepArgs {
-    R lo[kMaxDim];        // domain lower corner
-    R scale[kMaxDim];     // cells / (hi - lo)
+    R lo[kMaxDim];        // domain lower corner (equal-size cells)
+    R scale[kMaxDim];     // cells / (hi - lo), or mu / 2 for equal-probability cells: the LP1
+                          // coordinate is 2 scale (x - centre of the cell) in both cases
     R cmax_f[kMaxDim];    // cells - 1
     R stride_f[kMaxDim];  // stride of the stratum index (exact: K <= 2^24)
     uint32_t stride[kMaxDim];
@@ -51,6 +52,7 @@ struct StepArgs {
     int driver, terminal;
     R r, kappa, c_logistic, clamp_y, clamp_z;
     int identity_sigma, has_drift, has_lin_drift;
+    int equal_prob;       // cells cut at the logistic quantiles F^{-1}(c / cells)
     int lanes;
     int check_finite;
     size_t lds_per_cube;
@@ -76,6 +78,7 @@ struct SetupArgs {
     double b_lin[kMaxDim];
     int d, q, cmax;
     double mu;
+    int equal_prob;
 };
 
 struct RootPoint {
@@ -196,6 +199,11 @@ size_t cube_global_bytes(int prec_is_float, int d, int nb, int M);
 int cube_stage_chunks(int prec_is_float, int d, int nb, int M);
 template <typename R>
 hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                          const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                          hipStream_t st);
+// Equal-probability cells (srmdp_kernels_ep.hip).
+template <typename R>
+hipError_t launch_step_ep(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,
                           hipStream_t st);
 

@@ -44,6 +44,10 @@ template <typename R>
 struct RealOps;
 // Cell of a coordinate along one dimension: floor((x - lo) * cells/(hi - lo))
 // clamped to [0, cells - 1] (points outside the domain use the boundary cell).
+// Equal-probability cells (the cells of dimension l cut at the logistic
+// quantiles F^{-1}(c / n)): the coordinate is t = n F(x), F(x) = 1/(1 + e^{-mu x}),
+// and mu times the offset of x from the nu-median of cell c is
+// mu x - log((c + 1/2) / (n - c - 1/2)).
 template <>
 struct RealOps<float> {
     // v_med3_f32 also maps +-inf into [0, cmax]; a NaN stays NaN and the index
@@ -52,6 +56,14 @@ struct RealOps<float> {
     {
         return __builtin_amdgcn_fmed3f(floorf(t), 0.0f, cmax);
     }
+    static __device__ __forceinline__ float prob_coord(float x, float mu, float n)
+    {
+        return __fdividef(n, 1.0f + __expf(-mu * x));  // n / inf = 0 far below the grid
+    }
+    static __device__ __forceinline__ float median_offset(float x, float mu, float c, float n)
+    {
+        return mu * x - __logf(__fdividef(c + 0.5f, n - c - 0.5f));
+    }
 };
 template <>
 struct RealOps<double> {
@@ -59,7 +71,41 @@ struct RealOps<double> {
     {
         return fmin(fmax(floor(t), 0.0), cmax);
     }
+    static __device__ __forceinline__ double prob_coord(double x, double mu, double n)
+    {
+        return n / (1.0 + exp(-mu * x));
+    }
+    static __device__ __forceinline__ double median_offset(double x, double mu, double c, double n)
+    {
+        return mu * x - log((c + 0.5) / (n - c - 0.5));
+    }
 };
+
+// Coordinate of x along dimension l in cell widths: (x - lo) cells / (hi - lo)
+// for equal-size cells, n F(x) for equal-probability cells (EP).  The grid
+// kind is a template parameter so that the equal-size kernels carry none of
+// the other kind's code.
+template <typename R, bool EP>
+__device__ __forceinline__ R cell_coord(const StepArgs<R> &a, int l, R x)
+{
+    if constexpr (EP) return RealOps<R>::prob_coord(x, a.scale[l] + a.scale[l], a.cmax_f[l] + (R)1);
+    return (x - a.lo[l]) * a.scale[l];
+}
+
+// Clamped cell c of x along dimension l and the LP1 coordinate xi of x in it
+// (2 (t - c) - 1 for equal-size cells, mu (x - median) for equal-probability
+// ones).
+template <typename R, bool EP>
+__device__ __forceinline__ R cell_and_xi(const StepArgs<R> &a, int l, R x, R &xi)
+{
+    const R t = cell_coord<R, EP>(a, l, x);
+    const R c = RealOps<R>::clamp_cell(t, a.cmax_f[l]);
+    if constexpr (EP)
+        xi = RealOps<R>::median_offset(x, a.scale[l] + a.scale[l], c, a.cmax_f[l] + (R)1);
+    else
+        xi = (R)2 * (t - c) - (R)1;
+    return c;
+}
 
 // Fitted y_{j}(x) and sum_l z_{j,l}(x) from the look-up row j.
 // True when the point with cell coordinate t (in cell widths from lo) lies
@@ -72,34 +118,30 @@ __device__ __forceinline__ bool near_interior_face(R t, R c, R cmax, R eps)
     return (frac < eps && c > (R)0 && t >= (R)0) || (frac > (R)1 - eps && c < cmax);
 }
 
-template <typename R, int D>
+template <typename R, int D, bool EP>
 __device__ __forceinline__ bool near_face(const StepArgs<R> &a, const R *x)
 {
     bool near = false;
     for (int l = 0; l < D; ++l) {
-        const R t = (x[l] - a.lo[l]) * a.scale[l];
+        const R t = cell_coord<R, EP>(a, l, x[l]);
         near |= near_interior_face<R>(t, RealOps<R>::clamp_cell(t, a.cmax_f[l]), a.cmax_f[l],
                                       a.face_eps);
     }
     return near;
 }
 
-// Cell of x per dimension: floor((x - lo) cells / (hi - lo)) clamped to the
-// grid, xi = 2 (t - cell) - 1, and the offset of the stratum's look-up record
-// in a row.  The stratum index is accumulated in the working precision, exact
+// Cell of x per dimension, clamped to the grid (equal-size cells:
+// floor((x - lo) cells / (hi - lo)), xi = 2 (t - cell) - 1; equal-probability
+// cells as in cell_and_xi), and the offset of the stratum's look-up record in a
+// row.  The stratum index is accumulated in the working precision, exact
 // because K <= 2^24; K W < 2^32 so the offset is a 24-bit product.
-template <typename R, int D, int NB, int LK>
+template <typename R, int D, int NB, int LK, bool EP>
 __device__ __forceinline__ uint32_t locate(const StepArgs<R> &a, const R *x, R *xi)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     R kf = (R)0;
 #pragma unroll
-    for (int l = 0; l < D; ++l) {
-        const R t = (x[l] - a.lo[l]) * a.scale[l];
-        const R c = RealOps<R>::clamp_cell(t, a.cmax_f[l]);
-        xi[l] = (R)2 * (t - c) - (R)1;
-        kf = c * a.stride_f[l] + kf;
-    }
+    for (int l = 0; l < D; ++l) kf = cell_and_xi<R, EP>(a, l, x[l], xi[l]) * a.stride_f[l] + kf;
     return __umul24((uint32_t)kf, (uint32_t)W);
 }
 
@@ -138,13 +180,13 @@ __device__ __forceinline__ void eval_record(const StepArgs<R> &a, const R *rec, 
     }
 }
 
-template <typename R, int D, int NB, int LK>
+template <typename R, int D, int NB, int LK, bool EP>
 __device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__restrict__ row, const R *x,
                                             R &y, R &zsum)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     R xi[D], rec[W];
-    load_record<R, W>(row + locate<R, D, NB, LK>(a, x, xi), rec);
+    load_record<R, W>(row + locate<R, D, NB, LK, EP>(a, x, xi), rec);
     eval_record<R, D, NB, LK>(a, rec, xi, y, zsum);
 }
 
@@ -205,7 +247,7 @@ struct CvWave {
 // response; every lane of the wavefront must then run the same steps.
 // The first and last steps are peeled off so that the steady loop has no
 // branch that depends on j.
-template <typename R, int D, int NB, int LK, bool CV = false>
+template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false>
 __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
                                          const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
                                          R *dWi_out, R &y1, R &Sp, const CvWave *cv = nullptr,
@@ -233,7 +275,7 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
     euler_step<R, D>(a, bsig, x, dW, xn);
     R zsum_cur = (R)0;
     if (i + 1 < N) {
-        lookup_eval<R, D, NB, LK>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
+        lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
     } else {
         y1 = terminal_at<R, D>(a, xn);
     }
@@ -251,7 +293,7 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         }
         euler_step<R, D>(a, bsig, x, dW, xn);
         R yn, zn;
-        lookup_eval<R, D, NB, LK>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
+        lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
         S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
         zsum_cur = zn;
 #pragma unroll
@@ -294,7 +336,8 @@ __device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R
                 const CellF<R> cf = cellF[l * a.cmax + cell];
                 const R off = stratified_offset<R>(cf, open_uniform<R>(ws[t]), a.inv_mu);
                 x[l] = cf.centre + off;
-                // xi = 2 (x - c) / h, and 1/h = scale
+                // xi = 2 scale (x - centre): 2 (x - c) / h, or mu times the offset
+                // from the cell's nu-median (the centre of an equal-probability cell)
                 if constexpr (NB > 1) phi_out[1 + l] = (off + off) * a.scale[l];
             }
         }
@@ -305,7 +348,7 @@ __device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R
 // With the control variate and z_center, *centre = y_{i+1}(X_i) (g(X_i) when
 // i + 1 = N): the fitted row i+1 of the stratum itself (X_i lies in it),
 // truncated, whose product with dW_i / dt has conditional mean zero.
-template <typename R, int D, int NB, int LK, bool CV>
+template <typename R, int D, int NB, int LK, bool CV, bool EP>
 __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
                                               uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
@@ -330,7 +373,7 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
     }
     NormalStream<R, D> ns;
     ns.init(Key{a.key0, a.key1}, m, k, a.tag, a.sqrt_dt);
-    run_path<R, D, NB, LK, CV>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
+    run_path<R, D, NB, LK, CV, EP>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
 }
 
 // Near-face diagnostic of step i: the positions of a simulation do not depend
@@ -338,7 +381,7 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
 // same Euler steps as the sweep, and stratum k is marked when one of its
 // simulations reaches a look-up point within face_eps of an interior face.
 // One wavefront per stratum.
-template <typename R, int D, int NB>
+template <typename R, int D, int NB, bool EP>
 __global__ void __launch_bounds__(64) face_flags_kernel(const StepArgs<R> a,
                                                        const CellF<R> *__restrict__ cellF,
                                                        const R *__restrict__ bsig,
@@ -355,7 +398,7 @@ __global__ void __launch_bounds__(64) face_flags_kernel(const StepArgs<R> a,
         for (int j = a.i; j < a.N - 1; ++j) {
             ns.step((uint32_t)(j - a.i), dW);
             euler_step<R, D>(a, bsig, x, dW, xn);
-            near |= near_face<R, D>(a, xn);
+            near |= near_face<R, D, EP>(a, xn);
 #pragma unroll
             for (int l = 0; l < D; ++l) x[l] = xn[l];
         }
@@ -414,7 +457,7 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // With GR (global rows) the cloud rows and the chunk sums of a stratum live in
 // a.grow_bytes of global memory (clouds too large for LDS), and the launch
 // covers strata a.k0 .. a.k_end-1; LDS keeps the small binary64 arrays only.
-template <typename R, int D, int NB, int LK, bool CV, bool GR = false>
+template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
                                             const R *__restrict__ bsig, R *__restrict__ lk,
@@ -486,7 +529,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         for (int m = t; m < mend; m += L) {
             R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
             R Sp, y1, cvi, centre;
-            simulate_path<R, D, NB, LK, CV>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp, y1,
+            simulate_path<R, D, NB, LK, CV, EP>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp, y1,
                                             &cv, &cvi, &centre);
             row[NB + D + 1] = y1;
             if constexpr (CV) {

@@ -21,6 +21,7 @@ FP64, FP32 = 0, 1
 DRV_LINEAR, DRV_LOGISTIC = 0, 1
 G_COS_SUM, G_LOGISTIC = 0, 1
 F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z, F_AUTOTUNE, F_GLOBAL_ROWS = 0x1, 0x2, 0x4, 0x8, 0x10
+GRID_EQUAL_SIZE, GRID_EQUAL_PROB = 0, 1
 CV_NONE, CV_FROZEN, CV_ONLINE = 0, 1, 2
 MAX_D = 16
 MLP_HIDDEN = 64
@@ -48,6 +49,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [
         ("lo", ctypes.POINTER(ctypes.c_double)), ("hi", ctypes.POINTER(ctypes.c_double)),
         ("cells", ctypes.POINTER(ctypes.c_int32)), ("mu", ctypes.c_double),
+        ("kind", ctypes.c_int32),
     ]
 
 
@@ -206,11 +208,14 @@ class Problem:
 
 @dataclass
 class Grid:
-    """Equal-size stratification of [lo, hi) with the logistic sampling law."""
-    lo: Sequence[float]
-    hi: Sequence[float]
+    """Stratification with the logistic sampling law: equal-size cells of
+    [lo, hi) (GRID_EQUAL_SIZE), or cells cut at the logistic quantiles so that
+    every cube has probability 1/K (GRID_EQUAL_PROB; lo and hi unused)."""
+    lo: Optional[Sequence[float]]
+    hi: Optional[Sequence[float]]
     cells: Sequence[int]
     mu: float = 1.0
+    kind: int = GRID_EQUAL_SIZE
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -221,12 +226,14 @@ class Grid:
         return k
 
     def c(self) -> _Grid:
-        lo, hi = _darr(self.lo), _darr(self.hi)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lo = _darr(self.lo) if self.lo is not None else None
+        hi = _darr(self.hi) if self.hi is not None else None
         cells = (ctypes.c_int32 * len(self.cells))(*[int(c) for c in self.cells])
         self._keep = [lo, hi, cells]
-        return _Grid(ctypes.cast(lo, ctypes.POINTER(ctypes.c_double)),
-                     ctypes.cast(hi, ctypes.POINTER(ctypes.c_double)),
-                     ctypes.cast(cells, ctypes.POINTER(ctypes.c_int32)), self.mu)
+        return _Grid(ctypes.cast(lo, dp) if lo is not None else None,
+                     ctypes.cast(hi, dp) if hi is not None else None,
+                     ctypes.cast(cells, ctypes.POINTER(ctypes.c_int32)), self.mu, int(self.kind))
 
 
 @dataclass

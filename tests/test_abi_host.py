@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 104
+    assert S.srmdp.lib.srmdp_abi_version() == 105
 
 
 def test_table_elems_and_paper_sizes():
@@ -265,3 +265,35 @@ def test_batch_workspace_and_rejections():
     ptrs = (ctypes.c_void_p * n)(*([4096] * n))
     assert lib.srmdp_solve_batch(0, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -1
     assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, total - 1, None, None) == -3
+
+
+def test_equal_probability_grid_host_checks():
+    """Equal-probability cells: lo and hi may be NULL; they always take the
+    global-cloud kernels (a workspace at least that of the forced global rows
+    of an equal-size grid of the same shape); the control variate, the
+    dimensions without the LDS kernel, batches and an unknown grid kind are
+    refused before anything is enqueued."""
+    import ctypes
+    S = _S()
+    lib = S.srmdp.lib
+    P = S.Problem(d=2, N=4)
+    Gp = S.Grid(None, None, [5, 4], 1.3, kind=S.GRID_EQUAL_PROB)
+    Gs = S.Grid([-2.0] * 2, [2.0] * 2, [5, 4], 1.3)
+    ws_p = S.workspace_bytes(P, Gp, S.Options(M=40))
+    assert ws_p == S.workspace_bytes(P, Gs, S.Options(M=40, flags=S.F_GLOBAL_ROWS))
+    assert ws_p > S.workspace_bytes(P, Gs, S.Options(M=40))
+    cv = S.Options(M=40, prec=S.FP32, cv=1, cv_params=_FakeTensor())
+    assert lib.srmdp_solve(P.c(), Gp.c(), cv.c(), 16, 16, 1 << 40, None, None) == -2
+    G7 = S.Grid(None, None, [2] * 7, kind=S.GRID_EQUAL_PROB)
+    rc = lib.srmdp_solve(S.Problem(d=7, N=3).c(), G7.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16, 1 << 40,
+                         None, None)
+    assert rc == -2, lib.srmdp_last_error().decode()
+    Gbad = S.Grid([-2.0] * 2, [2.0] * 2, [5, 4], 1.3, kind=7)
+    assert lib.srmdp_solve(P.c(), Gbad.c(), S.Options(M=40).c(), 16, 16, 1 << 40, None, None) == -1
+    Gnull = S.Grid(None, None, [5, 4], 1.3)   # equal size without lo/hi
+    assert lib.srmdp_solve(P.c(), Gnull.c(), S.Options(M=40).c(), 16, 16, 1 << 40, None, None) == -1
+    Pb, Gb, Ob = _batch(S)
+    Gb[1] = S.Grid(None, None, [3, 3], kind=S.GRID_EQUAL_PROB)
+    n, Pa, Ga, Oa = S.srmdp._arrays(Pb, Gb, Ob)
+    ptrs = (ctypes.c_void_p * n)(*([4096] * n))
+    assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -2

@@ -1,0 +1,123 @@
+"""Equal-probability strata (cells cut at the logistic quantiles F^{-1}(c / C),
+every cube of nu-probability 1/K, the outer cells unbounded) on the GPU,
+against the FP64 oracle on the same seeded inputs (GPU tests; they call the
+library through its C ABI):
+
+* start points drawn in every stratum, unbounded ones included, in both
+  precisions;
+* full binary64 sweeps at the 1e-9 bound over the look-up modes (Y, YZ and,
+  with z truncation, Full), both bases, drift, Ornstein-Uhlenbeck and diffusion
+  variants, and d = 8;
+* binary32 steps against the oracle's step from the same rows at the 2e-4
+  bound (strata with a near-face look-up compared separately);
+* the TABLE and ROOT read-outs of the oracle's own table, at points far out in
+  the unbounded cells too.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import test_gpu_parity as TP
+import workloads as W
+from sides import oracle_problem, product_args
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ep(base, name, **kw):
+    cfg = dict(W.config(base), name=name, lo=None, hi=None, grid_kind=O.GRID_EQUAL_PROB, seed=13)
+    cfg.update(kw)
+    cfg.setdefault("x0", [0.0] * cfg["d"])
+    return cfg
+
+
+@pytest.mark.parametrize("d,cells", [(1, [7]), (2, [5, 3]), (8, [2] * 8)])
+def test_equal_probability_starts_match_oracle(d, cells):
+    import paper_2407_21085_amd as S
+    cfg = _ep("cfg2", f"starts d={d}", d=d, cells=cells, mu=1.3)
+    Po = oracle_problem(cfg)
+    K = int(np.prod(cells))
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        P, G, Opt = product_args(cfg, prec=prec)
+        _say(f"[gpu] equal-probability starts d={d} {prec}")
+        st = S.draw(P, G, Opt, 2, 1, 0, K, 0, 5, d).cpu().numpy()
+        for k in range(K):
+            for m in range(5):
+                x = O.start_point(Po, 1, k, m)
+                np.testing.assert_allclose(st[k, m], x, rtol=tol, atol=tol)
+
+
+CASES = [
+    ("lp1 d=2 cos linear Y fp64", dict(d=2, N=6, cells=[5, 4], M=50, basis="LP1", driver="linear", r=0.2,
+                                        kappa=0.3, terminal="cos", mu=1.3)),
+    ("lp1 d=1 logistic YZ fp64", dict(d=1, N=8, cells=[16], M=40, basis="LP1", driver="logistic",
+                                      terminal="logistic", mu=0.8)),
+    ("lp0 d=3 logistic YZ fp64", dict(d=3, N=5, cells=[3, 4, 2], M=36, basis="LP0", driver="logistic",
+                                      terminal="logistic", mu=1.0)),
+    ("lp1 d=2 truncated z Full fp64", dict(d=2, N=5, cells=[4, 4], M=48, basis="LP1", driver="logistic",
+                                           terminal="logistic", clamp_y=2.0, clamp_z=0.3, mu=1.0)),
+    ("lp1 d=3 drift sigma ou fp64", dict(d=3, N=4, cells=[3, 2, 3], M=40, basis="LP1", driver="linear", r=0.1,
+                                         kappa=0.2, terminal="cos", b=[0.2, -0.1, 0.0],
+                                         b_lin=[-0.6, 0.0, 0.3],
+                                         sigma=list((0.8 * np.eye(3) + 0.1).ravel()), mu=1.2)),
+    ("lp1 d=8 logistic YZ fp64", dict(d=8, N=3, cells=[2] * 8, M=40, basis="LP1", driver="logistic",
+                                      terminal="logistic", mu=1.0)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_equal_probability_sweeps_parity(name, kw):
+    cfg = _ep("cfg1", name, prec="fp64", **kw)
+    orc, sing = TP.oracle_table(cfg)
+    gpu, stats = TP.gpu_table(cfg)
+    assert stats["singular_cubes"] == sing
+    err = TP.parity(gpu, orc, range(cfg["N"]))
+    _say(f"[gpu] {name}: parity {err:.3e}")
+    assert err <= TP.TOL["fp64"]
+
+
+@pytest.mark.parametrize("d,cells,M,basis", [(4, [3, 2, 2, 3], 48, "LP1"), (2, [6, 5], 40, "LP0"),
+                                             (8, [2] * 8, 40, "LP1")])
+def test_equal_probability_fp32_per_step_parity(d, cells, M, basis):
+    cfg = _ep("cfg2", f"equal-probability logistic d={d} {basis} fp32", d=d, N=3, cells=cells, M=M,
+              basis=basis, mu=1.0)
+    # the binary32 coordinate C F(x) carries a few ulps of exp and division
+    # (about 1e-6 at C = 6): the near-face band is widened to 2e-5
+    err, err_flagged, share = TP.fp32_step_parity(cfg, [2, 1, 0], eps=2e-5)
+    assert err <= TP.TOL["fp32"]
+    assert share < 0.1
+    assert err_flagged < 0.05
+
+
+@pytest.mark.parametrize("basis", ["LP0", "LP1"])
+def test_equal_probability_readouts_of_oracle_table(basis):
+    """TABLE at points spread over [-9, 9]^2 (far into the unbounded cells) and
+    ROOT from x0, in binary64, both reading the oracle's table."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    cfg = _ep("cfg1", f"read-outs {basis}", d=2, N=4, cells=[6, 5], M=40, basis=basis, prec="fp64",
+              driver="linear", r=0.1, kappa=0.2, terminal="cos", mu=1.3)
+    Po = oracle_problem(cfg)
+    orc, _ = O.solve(Po)
+    P, G, Opt = product_args(cfg)
+    table = torch.from_numpy(orc).cuda()
+    pts = np.random.default_rng(5).uniform(-9.0, 9.0, (513, 2))
+    for i in (0, 2):
+        _say(f"[gpu] equal-probability TABLE {basis} step {i}")
+        y, z = S.evaluate(P, G, Opt.basis, Opt.prec, table, i, torch.from_numpy(pts).cuda())
+        yo, zo = O.evaluate(Po, orc, i, pts)
+        np.testing.assert_allclose(y.cpu().numpy(), yo, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(z.cpu().numpy(), zo, rtol=1e-12, atol=1e-12)
+    x0 = [0.3, -0.2]
+    _say(f"[gpu] equal-probability ROOT {basis}")
+    y0, z0 = S.root(P, G, Opt, table, x0, 20000)
+    yr, zr = O.root(Po, orc, x0, 20000)
+    assert y0 == pytest.approx(yr, rel=1e-9)
+    np.testing.assert_allclose(z0, zr, rtol=1e-8, atol=1e-10)
