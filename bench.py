@@ -52,6 +52,10 @@ PHILOX_OPS = 10 * 8 + 9 * 2      # per block: 2 mul-hi, 2 mul-lo, 4 xor per roun
 UNIFORM_OPS = 4                  # shift, or, convert, scale
 BOX_MULLER_OPS = 8               # log, sqrt, sincos (2), 4 multiplies per pair
 LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma, xi fma
+# equal-probability cells: C F(x) (multiply, exp and its scaling, add, reciprocal,
+# multiply), floor, clamp, the median ratio (2 adds, reciprocal, multiply), log and
+# its scaling, the xi fma, convert, index fma
+LOCATE_OPS_EP = 17
 
 # Bytes beyond L2 per launch of the sweep-step kernel of the default workload, from
 # FETCH_SIZE / WRITE_SIZE counter passes scaled by a plain copy's readings (fetch 2.0,
@@ -60,7 +64,7 @@ LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma
 KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_sweep.hpp", "srmdp_device.hpp", "srmdp_internal.hpp",
                   "srmdp_mlp.hpp")
 MEASURED_TRAFFIC = {
-    "bec6f3334b1e98e9": {"bytes": 5.659110e9,
+    "a1f8f1cf8db797a3": {"bytes": 5.631806e9,
                          "profile": "profiles/sweep_step_kernel_logistic_d8_K65536_M64_N50.md"},
 }
 
@@ -88,8 +92,9 @@ def algorithmic_ops(cfg: dict, lookup_terms: int):
     d = q = cfg["d"]
     nb = d + 1 if cfg["basis"] == "LP1" else 1
     blocks = math.ceil(q / 4)
+    locate = LOCATE_OPS_EP if cfg.get("grid_kind", 0) else LOCATE_OPS
     per_step = (blocks * (PHILOX_OPS + 4 * UNIFORM_OPS) + (q // 2 + q % 2) * BOX_MULLER_OPS
-                + q + d + d * LOCATE_OPS + lookup_terms * d + 2 + 3)
+                + q + d + d * locate + lookup_terms * d + 2 + 3)
     per_sample = (math.ceil(d / 4) * PHILOX_OPS + d * (UNIFORM_OPS + 8)
                   + nb * (nb + 1) // 2 + q * nb + nb + q * nb + 5)
     flops_step = 2 * q + d + d * 6 + lookup_terms * 2 * d + 4 + (q // 2) * 6
@@ -134,9 +139,10 @@ def _product_args(S, cfg: dict):
                   terminal=S.G_LOGISTIC if cfg["terminal"] == "logistic" else S.G_COS_SUM,
                   r=cfg.get("r", 0.0), kappa=cfg.get("kappa", 0.0),
                   clamp_y=cfg.get("clamp_y", math.inf))
-    G = S.Grid(cfg["lo"], cfg["hi"], cfg["cells"], cfg["mu"])
+    G = S.Grid(cfg.get("lo"), cfg.get("hi"), cfg["cells"], cfg["mu"], kind=cfg.get("grid_kind", 0))
     Opt = S.Options(M=cfg["M"], basis=S.LP1 if cfg["basis"] == "LP1" else S.LP0,
-                    prec=S.FP32 if cfg["prec"] == "fp32" else S.FP64, seed=cfg["seed"])
+                    prec=S.FP32 if cfg["prec"] == "fp32" else S.FP64, seed=cfg["seed"],
+                    flags=cfg.get("flags", 0))
     return P, G, Opt
 
 
@@ -483,6 +489,52 @@ def ragged_batch(S, stream) -> dict:
             "autotuned_lanes": sorted({s["lanes_per_cube"] for s in st})}
 
 
+def equal_probability(S, cfg, stream, steps: int, root_paths: int) -> dict:
+    """The workload on equal-probability cells (the same cells per dimension,
+    cut at the logistic quantiles: every cube of probability 1/K, the outer
+    ones unbounded), and for reference on its equal-size cells through the
+    same global-cloud kernel body: ms per sweep from HIP events on the
+    library's stream after a warm-up, path-steps/s, the ALU roofline fraction
+    of the equal-probability kernel (its longer cell location counted), and
+    y(0, x0) from the ROOT read-out beside the equal-size grid's.
+
+    Both runs truncate y at C_y = 1 (eq. (TL); the logistic solution lies in
+    (0, 1)): on the unbounded outer cells the few far samples steer the LP1
+    slopes, and without truncation the fitted values grow step after step
+    until they overflow (in binary64 as in binary32)."""
+    import torch
+    out = {}
+    lookup_terms = 2 if (cfg["driver"] == "logistic" or cfg.get("kappa", 0.0)) else 1
+    for key, c in (("equal_probability", dict(cfg, lo=None, hi=None, grid_kind=1, clamp_y=1.0)),
+                   ("equal_size_global_rows", dict(cfg, flags=S.F_GLOBAL_ROWS, clamp_y=1.0))):
+        P, G, Opt = _product_args(S, c)
+        table = S.srmdp.alloc_table(P, G, Opt)
+        ws = S.srmdp.alloc_workspace(P, G, Opt)
+        with torch.cuda.stream(stream):
+            S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=False)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            st = [S.solve(P, G, Opt, table=table, workspace=ws, stream=stream, stats=True)[1]
+                  for _ in range(steps)]
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        ms_steps = sum(x["ms_steps"] for x in st) / steps
+        launches = st[0]["step_launches"]
+        ops_step, ops_sample, _ = algorithmic_ops(c, lookup_terms)
+        K = int(math.prod(c["cells"]))
+        ops = W.path_steps(c) * ops_step + K * c["M"] * c["N"] * ops_sample
+        y0, _ = S.root(P, G, Opt, table, c["x0"], root_paths, workspace=ws)
+        out[key] = {"ms_per_sweep": ms, "path_steps_per_s": W.path_steps(c) / (ms / 1e3),
+                    "launches_per_sweep": launches, "avg_launch_ms": ms_steps / launches,
+                    "roofline_frac": ops / (ms_steps / 1e3) / VALU_PEAK_OPS,
+                    "ops_per_path_step": ops_step, "kernel": "sweep_step_gr_kernel", "clamp_y": c["clamp_y"],
+                    "y0_root": y0}
+        del table, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,6 +551,8 @@ def main() -> int:
                     help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
     ap.add_argument("--no-paper-tables", action="store_true",
                     help="skip the paper's own workloads (Tables LP0d4 .. LP1d15_19)")
+    ap.add_argument("--no-equal-prob", action="store_true",
+                    help="skip the workload on equal-probability cells")
     ap.add_argument("--no-ragged-batch", action="store_true",
                     help="skip the 64-instance ragged batch measurement")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -598,6 +652,8 @@ def main() -> int:
         "y0_exact_continuous": 0.5 if cfg["terminal"] == "logistic" else None,
         "lanes_per_cube": stats[0]["lanes_per_cube"],
     }
+    if not args.no_equal_prob:
+        out["equal_probability"] = equal_probability(S, cfg, stream, args.steps, args.root_paths)
     if not args.no_ragged_batch:
         out["ragged_batch"] = ragged_batch(S, stream)
     if not args.no_paper_tables:

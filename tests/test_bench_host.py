@@ -21,6 +21,10 @@ def test_algorithmic_ops_of_the_headline_workload():
     per_step, per_sample, _ = B.algorithmic_ops(W.config("cfg5"), 2)
     assert per_step == 361
     assert per_sample == 495
+    # equal-probability cells: 17 operations per cell location instead of 8
+    per_step_ep, per_sample_ep, _ = B.algorithmic_ops(dict(W.config("cfg5"), grid_kind=1), 2)
+    assert per_step_ep == 361 + 8 * 9
+    assert per_sample_ep == 495
 
 
 PLAIN = [{"M": 64, "ms": 60.0, "stat_rmse": 0.008}, {"M": 128, "ms": 140.0, "stat_rmse": 0.004},

@@ -69,6 +69,10 @@ CASES = [
                                          sigma=list((0.8 * np.eye(3) + 0.1).ravel()), mu=1.2)),
     ("lp1 d=8 logistic YZ fp64", dict(d=8, N=3, cells=[2] * 8, M=40, basis="LP1", driver="logistic",
                                       terminal="logistic", mu=1.0)),
+    # all 256 cubes unbounded, 50 steps, y truncated at C_y = 1 (without it the
+    # fits of this workload grow to 1e29 on both sides)
+    ("lp1 d=8 N=50 truncated y fp64", dict(d=8, N=50, cells=[2] * 8, M=64, basis="LP1", driver="logistic",
+                                           terminal="logistic", clamp_y=1.0, mu=1.0)),
 ]
 
 

@@ -139,3 +139,19 @@ def test_equal_probability_coupled_driver_matches_discrete_closed_form():
         assert np.max(np.abs(y - yex(i)(xs))) < 0.025
         assert np.max(np.abs(z[:, 0] - zex(i)(xs))) < 0.06
         assert abs(np.mean(y - yex(i)(xs))) < 0.004
+
+
+def test_truncation_keeps_unbounded_strata_stable():
+    """With two cells per dimension every cube is unbounded.  Its few far
+    samples steer the LP1 slopes, and without truncation the logistic BSDE's
+    fits grow over the 50 backward steps (d = 8, K = 256, M = 64: coefficients
+    near 1e29 at step 0 for this seed); truncating y at C_y = 1, which bounds
+    the solution, as the estimator of eq. (TL) does, keeps every coefficient of
+    moderate size and y(0, 0) near its value 1/2."""
+    kw = dict(N=50, M=64, driver=O.DRV_LOGISTIC, terminal=O.G_LOGISTIC, seed=1)
+    tab, _ = O.solve(_prob([2] * 8, 1.0, **kw))
+    assert np.nanmax(np.abs(tab[0])) > 1e6
+    tab1, _ = O.solve(_prob([2] * 8, 1.0, clamp_y=1.0, **kw))
+    assert np.all(np.isfinite(tab1)) and np.max(np.abs(tab1)) < 100.0
+    y0, _ = O.root(_prob([2] * 8, 1.0, clamp_y=1.0, **kw), tab1, [0.0] * 8, 100000)
+    assert abs(y0 - 0.5) < 0.05, y0
