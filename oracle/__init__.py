@@ -79,6 +79,7 @@ class _Problem(ctypes.Structure):
         ("cv_stride", ctypes.c_int32), ("z_center", ctypes.c_int32),
         ("b_lin", ctypes.POINTER(ctypes.c_double)),
         ("grid_kind", ctypes.c_int32),
+        ("sigma_lin", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -163,6 +164,7 @@ class Problem:
     cv_stride: int = 1
     z_center: int = 0
     grid_kind: int = GRID_EQUAL_SIZE
+    sigma_lin: Optional[Sequence[float]] = None   # diffusion sigma + diag(sigma_lin) x
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -196,7 +198,7 @@ class Problem:
 
         lo, hi = arr(self.lo), arr(self.hi)
         cells = arr(self.cells, np.int32)
-        b, sig, blin = arr(self.b), arr(self.sigma), arr(self.b_lin)
+        b, sig, blin, slin = arr(self.b), arr(self.sigma), arr(self.b_lin), arr(self.sigma_lin)
         cvp = arr(self.cv_params)
         s = _Problem()
         s.d, s.q, s.T, s.N = self.d, self.q, self.T, self.N
@@ -221,6 +223,7 @@ class Problem:
         s.z_center = self.z_center
         s.b_lin = _dp(blin) if blin is not None else None
         s.grid_kind = self.grid_kind
+        s.sigma_lin = _dp(slin) if slin is not None else None
         self._keep = keep
         return s
 

@@ -9,7 +9,9 @@
  *  - Euler dynamics (Section 2, Algorithm "Euler dynamics") is read with the
  *    time index of the current step j, X_{j+1} = X_j + b(X_j) dt + sigma dW_j,
  *    with the drift b(x)_l = b_l + b_lin_l x_l (constant b, or the
- *    Ornstein-Uhlenbeck drift) and a constant sigma.
+ *    Ornstein-Uhlenbeck drift) and the diffusion sigma(x)_{l,c} = sigma_{l,c}
+ *    + [l = c] sigma_lin_l x_l (constant, or with a diagonal part linear in
+ *    the state as in geometric Brownian motion; q = d then).
  *  - The z-response of Algorithm SRMDP, eq. (PsiM), uses the tail
  *    g(X_N) + sum_{j=i+1}^{N-1} f_j dt of the same path started at X_i,
  *    multiplied by dW_i / dt, as in the MDP identity eq. (MDP:intro).
@@ -471,6 +473,7 @@ static int check_problem(const orc_problem *P, grid_t *G)
     if (P->N < 1 || P->N > 65535 || !(P->T > 0.0) || !(P->mu > 0.0)) return -1;
     if (P->basis != ORC_LP0 && P->basis != ORC_LP1) return -1;
     if (!P->sigma && P->q != P->d) return -1;
+    if (P->sigma_lin && P->q != P->d) return -1;
     if (P->M < basis_size(P)) return -1; /* M >= dim of the local space */
     if (P->cv_params && (P->cv_hidden < 1 || P->cv_hidden > 256 || P->q > 64)) return -1;
     return grid_init(P, G);
@@ -606,6 +609,7 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
                 for (int c = 0; c < q; ++c) diff += P->sigma[l * q + c] * dW[c];
             else
                 diff = dW[l];
+            if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];
             xn[l] = x[l] + drift * dt + diff;
         }
         double ynext = y_at(P, G, table, j + 1, xn);

@@ -69,6 +69,9 @@ typedef struct {
      * quantiles F^{-1}(c / cells), c = 0..cells, so that every cube has
      * nu-probability 1/K and the cubes cover R^d (lo and hi are ignored). */
     int32_t grid_kind;
+    /* [d] diagonal part of the diffusion linear in the state,
+     * sigma(x)_{l,c} = sigma_{l,c} + [l = c] sigma_lin_l x_l (q = d), or NULL */
+    const double *sigma_lin;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */

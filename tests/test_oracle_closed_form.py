@@ -266,3 +266,67 @@ def test_paper_sizes():
     nbytes = O.lib().orc_table_elems(P.c()) * 4
     assert nbytes == 50 * 14 ** 6 * 7 * 4
     assert nbytes / 2 ** 30 == pytest.approx(9.81, abs=0.01)   # the printed "9.81 GBytes"
+
+
+def _gbm_cos_exact(P):
+    """f = 0, g = cos(sum x), b = 0, sigma(x) = diag(s x) (sigma's constant part
+    zero): each step multiplies X_l by 1 + s_l dW_l.  From step N-1 the
+    Gaussian expectation is closed:
+        y_{N-1}(x) = cos(sum x) exp(-dt sum (s_l x_l)^2 / 2),
+        z_{N-1,l}(x) = -s_l x_l sin(sum x) exp(-dt sum (s_l x_l)^2 / 2)
+    (z by Gaussian integration by parts in dW_l); one step earlier
+    y_{N-2}(x) = E[y_{N-1}(x (1 + s dW))] and z_{N-2,l} = E[y_{N-1}(..) dW_l] / dt,
+    by Gauss-Hermite quadrature in dW."""
+    s = np.asarray(P.sigma_lin, dtype=float)
+    dt, d = P.dt, P.d
+    zs, ws = np.polynomial.hermite_e.hermegauss(24)
+    ws = ws / math.sqrt(2.0 * math.pi)
+    mesh = np.meshgrid(*([zs] * d), indexing="ij")
+    Z = np.stack([m.ravel() for m in mesh], axis=1)               # [G, d] standard normals
+    Wt = np.prod(np.stack(np.meshgrid(*([ws] * d), indexing="ij")).reshape(d, -1), axis=0)
+
+    def y_last(X):
+        return np.cos(X.sum(axis=1)) * np.exp(-dt * ((s * X) ** 2).sum(axis=1) / 2)
+
+    def z_last(l):
+        return lambda X: -s[l] * X[:, l] * np.sin(X.sum(axis=1)) * np.exp(-dt * ((s * X) ** 2).sum(axis=1) / 2)
+
+    def step_back(X, weight):
+        # E[y_last(X (1 + s sqrt(dt) Z)) weight(Z)] for every row of X
+        Xn = X[:, None, :] * (1.0 + s * math.sqrt(dt) * Z[None, :, :])
+        v = y_last(Xn.reshape(-1, d)).reshape(X.shape[0], -1)
+        return (v * weight[None, :] * Wt[None, :]).sum(axis=1)
+
+    def y(i):
+        assert i in (P.N - 1, P.N - 2)
+        return y_last if i == P.N - 1 else (lambda X: step_back(X, np.ones(len(Wt))))
+
+    def z(i, l):
+        assert i in (P.N - 1, P.N - 2)
+        return z_last(l) if i == P.N - 1 else (lambda X: step_back(X, Z[:, l] / math.sqrt(dt)))
+    return y, z
+
+
+@pytest.mark.parametrize("d,cells,M,s", [(1, [16], 20000, [0.6]), (2, [4, 4], 12000, [0.5, -0.8])])
+def test_state_dependent_diffusion_fits_match_projection_of_closed_form(d, cells, M, s):
+    """sigma(x) = diag(s x) with f = 0 (geometric Brownian motion in the Euler
+    scheme, one component with a negative scale): every coefficient of steps
+    N-1 and N-2 within 5 standard errors of the projection of the exact
+    discrete y and z on the local basis."""
+    P = O.Problem(d=d, N=2, lo=[-2.0] * d, hi=[2.0] * d, cells=cells, M=M, seed=3,
+                  sigma=[0.0] * (d * d), sigma_lin=s)
+    tab, sing = O.solve(P)
+    assert sing == 0
+    yex, zex = _gbm_cos_exact(P)
+    worst = 0.0
+    for i in range(P.N):
+        for k in range(P.K):
+            a, bb = _cube_bounds(P, k)
+            Xi, dW, Sp, y1, cvi = O.cloud(P, tab, i, k)
+            c, h = 0.5 * (a + bb), bb - a
+            A = np.hstack([np.ones((M, 1)), 2 * (Xi - c) / h])
+            worst = max(worst, np.max(np.abs(tab[i, k, 0] - _nu_proj(yex(i), a, bb)) / _sandwich_se(A, Sp)))
+            for l in range(P.q):
+                se_z = _sandwich_se(A, Sp * dW[:, l] / P.dt)
+                worst = max(worst, np.max(np.abs(tab[i, k, 1 + l] - _nu_proj(zex(i, l), a, bb)) / se_z))
+    assert worst < 5.0, worst

@@ -86,6 +86,16 @@ MUTANTS = [
      "(P->b_lin ? P->b_lin[l] * x[l] : 0.0)",
      "(P->b_lin ? -P->b_lin[l] * x[l] : 0.0)",
      lambda: CF.test_ornstein_uhlenbeck_fits_match_projection_of_closed_form(1, [16], 4, 20000, [0.3], [-0.8])),
+    ("state-dependent diffusion reads the first coordinate",
+     "if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];",
+     "if (P->sigma_lin) diff += P->sigma_lin[l] * x[0] * dW[l];",
+     lambda: CF.test_state_dependent_diffusion_fits_match_projection_of_closed_form(2, [4, 4], 12000,
+                                                                                    [0.5, -0.8])),
+    ("state-dependent diffusion on the wrong increment",
+     "if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];",
+     "if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[d - 1 - l];",
+     lambda: CF.test_state_dependent_diffusion_fits_match_projection_of_closed_form(2, [4, 4], 12000,
+                                                                                    [0.5, -0.8])),
     ("Philox key bump skipped",
      "k0 += weyl0;",
      "k0 += 0u;",
