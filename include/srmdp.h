@@ -88,6 +88,10 @@ typedef struct {
     const double *b_lin;   /* host [d]: diagonal linear drift, so that the drift is
                             * b_l + b_lin_l x_l (Ornstein-Uhlenbeck dynamics, through the
                             * Euler scheme of Section 2); NULL = 0 */
+    const double *sigma_lin; /* host [d]: diagonal part of the diffusion linear in the state,
+                              * sigma(x)_{l,c} = sigma_{l,c} + [l = c] sigma_lin_l x_l, evaluated at
+                              * X_j in the Euler scheme of Section 2 (geometric Brownian motion
+                              * when sigma is zero); NULL = 0 */
 } srmdp_problem;
 
 /* Stratification: the two examples of hypercubes under assumption

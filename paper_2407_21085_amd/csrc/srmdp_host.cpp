@@ -103,6 +103,12 @@ srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s
     if (p->sigma)
         for (int l = 0; l < p->d * p->q; ++l)
             if (!std::isfinite(p->sigma[l])) return fail(SRMDP_E_INVALID, "sigma must be finite");
+    if (p->b_lin)
+        for (int l = 0; l < p->d; ++l)
+            if (!std::isfinite(p->b_lin[l])) return fail(SRMDP_E_INVALID, "b_lin must be finite");
+    if (p->sigma_lin)
+        for (int l = 0; l < p->d; ++l)
+            if (!std::isfinite(p->sigma_lin[l])) return fail(SRMDP_E_INVALID, "sigma_lin must be finite");
     return SRMDP_OK;
 }
 
@@ -192,7 +198,7 @@ Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options 
     L.cellF = off;
     off = align_up(off + (size_t)s.d * s.cmax * 4 * rsz, 256);
     L.bsig = off;
-    off = align_up(off + (size_t)(2 * s.d + s.d * s.q) * rsz, 256);
+    off = align_up(off + (size_t)(3 * s.d + s.d * s.q) * rsz, 256);  // b | sigma | b_lin | sigma_lin
     L.root_partial = off;
     off = align_up(off + (size_t)kRootBlocks * (s.d + 2) * sizeof(double), 256);
     L.root_out = off;
@@ -285,6 +291,11 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
         for (int l = 0; l < s.d; ++l)
             if (p->b_lin[l] != 0.0) lin = true;
     a.has_lin_drift = lin ? 1 : 0;
+    bool lin_sigma = false;
+    if (p->sigma_lin)
+        for (int l = 0; l < s.d; ++l)
+            if (p->sigma_lin[l] != 0.0) lin_sigma = true;
+    a.has_lin_sigma = lin_sigma ? 1 : 0;
     if (o) {
         a.M = o->M;
         a.key0 = (uint32_t)(o->seed & 0xFFFFFFFFull);
@@ -308,6 +319,7 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
         sa.cells[l] = g->cells[l];
         sa.b[l] = p->b ? p->b[l] : 0.0;
         sa.b_lin[l] = p->b_lin ? p->b_lin[l] : 0.0;
+        sa.sigma_lin[l] = p->sigma_lin ? p->sigma_lin[l] : 0.0;
     }
     for (int t = 0; t < s.d * s.q; ++t)
         sa.sigma[t] = p->sigma ? p->sigma[t] : ((t / s.q) == (t % s.q) ? 1.0 : 0.0);
@@ -571,6 +583,7 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         if (p->b) put(p->b, sizeof(double) * s.d);
         if (p->sigma) put(p->sigma, sizeof(double) * s.d * s.q);
         if (p->b_lin) put(p->b_lin, sizeof(double) * s.d);
+        if (p->sigma_lin) put(p->sigma_lin, sizeof(double) * s.d);
         put(&g->kind, sizeof g->kind);
         if (g->kind == SRMDP_GRID_EQUAL_SIZE) {
             put(g->lo, sizeof(double) * s.d);
@@ -976,6 +989,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
             if (P[b].b) put(P[b].b, sizeof(double) * P[b].d);
             if (P[b].sigma) put(P[b].sigma, sizeof(double) * P[b].d * P[b].q);
             if (P[b].b_lin) put(P[b].b_lin, sizeof(double) * P[b].d);
+            if (P[b].sigma_lin) put(P[b].sigma_lin, sizeof(double) * P[b].d);
             put(&G[b].kind, sizeof G[b].kind);
             if (G[b].kind == SRMDP_GRID_EQUAL_SIZE) {
                 put(G[b].lo, sizeof(double) * P[b].d);
@@ -1041,7 +1055,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 105; }
+int32_t srmdp_abi_version(void) { return 106; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 

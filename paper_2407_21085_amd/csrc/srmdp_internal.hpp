@@ -51,7 +51,7 @@ struct StepArgs {
     double dt_d, inv_dt;
     int driver, terminal;
     R r, kappa, c_logistic, clamp_y, clamp_z;
-    int identity_sigma, has_drift, has_lin_drift;
+    int identity_sigma, has_drift, has_lin_drift, has_lin_sigma;
     int equal_prob;       // cells cut at the logistic quantiles F^{-1}(c / cells)
     int lanes;
     int check_finite;
@@ -76,6 +76,7 @@ struct SetupArgs {
     double b[kMaxDim];
     double sigma[kMaxDim * kMaxDim];
     double b_lin[kMaxDim];
+    double sigma_lin[kMaxDim];
     int d, q, cmax;
     double mu;
     int equal_prob;

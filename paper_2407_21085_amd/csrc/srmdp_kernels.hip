@@ -28,6 +28,7 @@ __global__ void setup_kernel(SetupArgs a, CellF<R> *cellF, R *bsig)
     if (t < a.d) bsig[t] = (R)a.b[t];
     if (t < a.d * a.q) bsig[a.d + t] = (R)a.sigma[t];
     if (t < a.d) bsig[a.d + a.d * a.q + t] = (R)a.b_lin[t];
+    if (t < a.d) bsig[2 * a.d + a.d * a.q + t] = (R)a.sigma_lin[t];
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n)

@@ -218,6 +218,10 @@ __device__ __forceinline__ void euler_step(const StepArgs<R> &a, const R *__rest
 #pragma unroll
         for (int l = 0; l < D; ++l) xn[l] += bsig[D + D * D + l] * x[l] * a.dt;
     }
+    if (a.has_lin_sigma) {  // sigma(X_j) = sigma + diag(sigma_lin) X_j
+#pragma unroll
+        for (int l = 0; l < D; ++l) xn[l] += bsig[2 * D + D * D + l] * x[l] * dW[l];
+    }
 }
 
 template <typename R, int D>

@@ -42,6 +42,7 @@ class _Problem(ctypes.Structure):
         ("r", ctypes.c_double), ("kappa", ctypes.c_double),
         ("clamp_y", ctypes.c_double), ("clamp_z", ctypes.c_double),
         ("b_lin", ctypes.POINTER(ctypes.c_double)),
+        ("sigma_lin", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -170,7 +171,8 @@ def _darr(v: Sequence[float]):
 
 @dataclass
 class Problem:
-    """Problem data of eq. (fbsde)-(eds): constant diffusion, drift b + diag(b_lin) x."""
+    """Problem data of eq. (fbsde)-(eds): drift b + diag(b_lin) x, diffusion
+    sigma + diag(sigma_lin) x."""
     d: int
     N: int
     T: float = 1.0
@@ -184,6 +186,7 @@ class Problem:
     b: Optional[Sequence[float]] = None
     sigma: Optional[Sequence[float]] = None
     b_lin: Optional[Sequence[float]] = None   # drift b_l + b_lin_l x_l (Ornstein-Uhlenbeck)
+    sigma_lin: Optional[Sequence[float]] = None   # diffusion sigma + diag(sigma_lin) x
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Problem:
@@ -203,6 +206,10 @@ class Problem:
             a = _darr(self.b_lin)
             self._keep.append(a)
             s.b_lin = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        if self.sigma_lin is not None:
+            a = _darr(self.sigma_lin)
+            self._keep.append(a)
+            s.sigma_lin = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
         return s
 
 

@@ -19,7 +19,7 @@ def oracle_problem(cfg, **kw):
                      inst=c.get("instance", 0), clamp_y=c.get("clamp_y", math.inf),
                      face_flags=c.get("face_flags"), face_eps=c.get("face_eps", 1e-5),
                      clamp_z=c.get("clamp_z", math.inf), b=c.get("b"), sigma=c.get("sigma"),
-                     b_lin=c.get("b_lin"), grid_kind=c.get("grid_kind", 0))
+                     b_lin=c.get("b_lin"), grid_kind=c.get("grid_kind", 0), sigma_lin=c.get("sigma_lin"))
 
 
 def product_args(cfg, **kw):
@@ -29,7 +29,7 @@ def product_args(cfg, **kw):
     P = S.Problem(d=c["d"], N=c["N"], T=c["T"], driver=_DRIVER[c["driver"]],
                   terminal=_TERMINAL[c["terminal"]], r=c.get("r", 0.0), kappa=c.get("kappa", 0.0),
                   clamp_y=c.get("clamp_y", math.inf), clamp_z=c.get("clamp_z", math.inf),
-                  b=c.get("b"), sigma=c.get("sigma"), b_lin=c.get("b_lin"))
+                  b=c.get("b"), sigma=c.get("sigma"), b_lin=c.get("b_lin"), sigma_lin=c.get("sigma_lin"))
     G = S.Grid(c.get("lo"), c.get("hi"), c["cells"], c["mu"], kind=c.get("grid_kind", 0))
     Opt = S.Options(M=c["M"], basis=_BASIS[c["basis"]], prec=S.FP32 if c["prec"] == "fp32" else S.FP64,
                     seed=c["seed"], instance=c.get("instance", 0), step_hi=c.get("step_hi", -1),

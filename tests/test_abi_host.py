@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 105
+    assert S.srmdp.lib.srmdp_abi_version() == 106
 
 
 def test_table_elems_and_paper_sizes():

@@ -67,6 +67,8 @@ CASES = [
                                          kappa=0.2, terminal="cos", b=[0.2, -0.1, 0.0],
                                          b_lin=[-0.6, 0.0, 0.3],
                                          sigma=list((0.8 * np.eye(3) + 0.1).ravel()), mu=1.2)),
+    ("lp1 d=2 state-dependent sigma fp64", dict(d=2, N=5, cells=[4, 5], M=40, basis="LP1", driver="linear",
+                                               r=0.1, kappa=0.2, terminal="cos", sigma_lin=[0.3, -0.4], mu=1.1)),
     ("lp1 d=8 logistic YZ fp64", dict(d=8, N=3, cells=[2] * 8, M=40, basis="LP1", driver="logistic",
                                       terminal="logistic", mu=1.0)),
     # all 256 cubes unbounded, 50 steps, y truncated at C_y = 1 (without it the

@@ -241,6 +241,19 @@ CASES = [
     ("lp0 d=3 ornstein-uhlenbeck fp32", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 2, 2], M=64,
                                             basis="LP0", prec="fp32", driver="linear", r=0.1,
                                             terminal="cos", b=[0.0, 0.2, 0.0], b_lin=[-1.0, -0.4, 0.5])),
+    # diffusion sigma + diag(sigma_lin) x: geometric Brownian motion (zero constant part), and with a full
+    # constant part, the Ornstein-Uhlenbeck drift and the logistic driver
+    ("lp1 d=2 geometric brownian fp64", dict(d=2, N=6, lo=[-2.0] * 2, hi=[2.0] * 2, cells=[4, 3], M=50,
+                                            basis="LP1", prec="fp64", driver="linear", r=0.2, kappa=0.3,
+                                            terminal="cos", sigma=[0.0] * 4, sigma_lin=[0.5, -0.8])),
+    ("lp1 d=4 state-dependent sigma fp64", dict(d=4, N=4, lo=[-2.0] * 4, hi=[2.0] * 4, cells=[2] * 4, M=40,
+                                               basis="LP1", prec="fp64", driver="logistic",
+                                               terminal="logistic", b_lin=[-0.5, 0.0, 0.2, 0.0],
+                                               sigma=list((0.9 * np.eye(4) + 0.05).ravel()),
+                                               sigma_lin=[0.3, 0.0, -0.2, 0.4])),
+    ("lp0 d=3 state-dependent sigma fp32", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 2, 2], M=64,
+                                               basis="LP0", prec="fp32", driver="linear", r=0.1,
+                                               terminal="cos", sigma_lin=[0.4, -0.3, 0.2])),
 ]
 
 
