@@ -401,6 +401,9 @@ PAPER_ROWS = (
     ("LP1d14", 14, "LP1", 5, 2, 4000, (-3.029663, -3.105833, -1.558935), 50.62),
     ("LP1d15_19", 15, "LP1", 5, 2, 5000, (-2.981181, -3.106590, -1.574532), 139.60),
     ("LP1d15_19", 16, "LP1", 5, 2, 6000, (-2.795353, -2.959375, -1.588716), 429.53),
+    ("LP1d15_19", 17, "LP1", 5, 2, 5000, (-2.772595, -2.936549, -1.371146), 793.61),
+    ("LP1d15_19", 18, "LP1", 5, 2, 4000, (-2.845755, -2.918057, -1.114600), 1589.30),
+    ("LP1d15_19", 19, "LP1", 5, 2, 3200, (-2.726427, -2.851617, -0.839849), 4370.31),
 )
 
 

@@ -44,7 +44,11 @@
 extern "C" {
 #endif
 
-#define SRMDP_MAX_D 16          /* largest d = q compiled */
+#define SRMDP_MAX_D 19          /* largest d = q compiled.  d = 1..6 and 8 run every
+                                 * option; d = 7 and 9..19 run binary32 sweeps with
+                                 * look-up modes Y and YZ (no z truncation), without
+                                 * the control variate, on equal-size cells; other
+                                 * requests return SRMDP_E_UNSUPPORTED */
 #define SRMDP_ROOT_STRATUM 0xFFFFFFFFu  /* counter stratum tag of ROOT paths */
 
 typedef enum {

@@ -310,7 +310,12 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
     }
 }
 
-void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g, const Shape &s)
+// The d x q diffusion matrix of the set-up (identity when the problem gives none).
+struct SigmaHost {
+    double v[kMaxDim * kMaxDim];
+};
+
+void fill_setup_args(SetupArgs &sa, SigmaHost &sg, const srmdp_problem *p, const srmdp_grid *g, const Shape &s)
 {
     std::memset(&sa, 0, sizeof sa);
     for (int l = 0; l < s.d; ++l) {
@@ -322,7 +327,7 @@ void fill_setup_args(SetupArgs &sa, const srmdp_problem *p, const srmdp_grid *g,
         sa.sigma_lin[l] = p->sigma_lin ? p->sigma_lin[l] : 0.0;
     }
     for (int t = 0; t < s.d * s.q; ++t)
-        sa.sigma[t] = p->sigma ? p->sigma[t] : ((t / s.q) == (t % s.q) ? 1.0 : 0.0);
+        sg.v[t] = p->sigma ? p->sigma[t] : ((t / s.q) == (t % s.q) ? 1.0 : 0.0);
     sa.d = s.d;
     sa.q = s.q;
     sa.cmax = s.cmax;
@@ -485,12 +490,13 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
     a.lanes = L;
     a.lds_per_cube = per_cube;
     SetupArgs sa;
-    fill_setup_args(sa, p, g, s);
+    SigmaHost sg;
+    fill_setup_args(sa, sg, p, g, s);
     const int hi = o->step_hi < 0 ? s.N - 1 : o->step_hi;
     const int lo = o->step_lo < 0 ? 0 : o->step_lo;
 
     HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
-    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    HIP_TRY(launch_setup<R>(sa, sg.v, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
     const MlpShape net{s.d + 1, s.q};
     if (cv) {
         a.cv_packed = ws + lay.cv_packed;
@@ -691,10 +697,11 @@ srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
     a.tag = (o->instance << 16);
     a.face_flags = nullptr;
     SetupArgs sa;
-    fill_setup_args(sa, p, g, s);
+    SigmaHost sg;
+    fill_setup_args(sa, sg, p, g, s);
     RootPoint rp{};
     for (int l = 0; l < s.d; ++l) rp.x[l] = x0[l];
-    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    HIP_TRY(launch_setup<R>(sa, sg.v, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
     if (s.N > 1)
         HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, 1, s.N - 1, st),
                 "look-up rows");
@@ -747,9 +754,10 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
     a.tag = ((uint32_t)it & 0xFFFFu) | (o->instance << 16);
     a.face_flags = nullptr;
     SetupArgs sa;
-    fill_setup_args(sa, p, g, s);
+    SigmaHost sg;
+    fill_setup_args(sa, sg, p, g, s);
     HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
-    HIP_TRY(launch_setup<R>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    HIP_TRY(launch_setup<R>(sa, sg.v, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
     if (it < s.N - 1)
         HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, it + 1, s.N - 1, st),
                 "look-up rows");
@@ -951,9 +959,10 @@ srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, c
         const Layout lay = layout(bp.shapes[b], bp.nb, is_float, bp.lk, &O[b]);
         unsigned char *w = ws + bp.ws_off[b];
         SetupArgs sa;
-        fill_setup_args(sa, &P[b], &G[b], bp.shapes[b]);
+        SigmaHost sg;
+        fill_setup_args(sa, sg, &P[b], &G[b], bp.shapes[b]);
         HIP_TRY(launch_zero_u64((unsigned long long *)(w + lay.counters), kCounterCount, st), "zero counters");
-        HIP_TRY(launch_setup<R>(sa, w + lay.cellF, w + lay.bsig, st), "setup kernel");
+        HIP_TRY(launch_setup<R>(sa, sg.v, w + lay.cellF, w + lay.bsig, st), "setup kernel");
     }
     HIP_TRY(launch_upload(ws, inst.data(), sizeof(BatchInstance<R>) * n, st), "instance upload");
     int active = n;
@@ -1239,12 +1248,13 @@ srmdp_status srmdp_cv_pairs(const srmdp_problem *problem, const srmdp_grid *grid
     const Layout lay = layout(s, nb, 1, lookup_mode(problem), opts);
     unsigned char *ws = (unsigned char *)workspace;
     SetupArgs sa;
-    fill_setup_args(sa, problem, grid, s);
+    SigmaHost sg;
+    fill_setup_args(sa, sg, problem, grid, s);
     StepArgs<float> a;
     fill_step_args<float>(a, problem, grid, s, opts);
     a.i = i;
     a.tag = ((uint32_t)i & 0xFFFFu) | (opts->instance << 16);
-    HIP_TRY(launch_setup<float>(sa, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    HIP_TRY(launch_setup<float>(sa, sg.v, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
     HIP_TRY(launch_cv_pairs(s.d, opts->basis, a, ws + lay.cellF, table, n, x16, z16, st), "training pairs");
     return SRMDP_OK;
 }
@@ -1398,7 +1408,8 @@ srmdp_status srmdp_draw(const srmdp_problem *problem, const srmdp_grid *grid, co
     if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
     hipStream_t st = (hipStream_t)stream;
     SetupArgs sa;
-    fill_setup_args(sa, problem, grid, s);
+    SigmaHost sg;
+    fill_setup_args(sa, sg, problem, grid, s);
     if (opts->prec == SRMDP_FP32) {
         StepArgs<float> a;
         fill_step_args<float>(a, problem, grid, s, opts);

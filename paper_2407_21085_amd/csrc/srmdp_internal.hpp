@@ -8,7 +8,7 @@
 
 namespace srmdp {
 
-constexpr int kMaxDim = 16;
+constexpr int kMaxDim = 19;
 
 // What a look-up row holds for each stratum: the y coefficients only (the
 // driver does not use z), y and the sum of the z_l coefficients (both built-in
@@ -70,11 +70,14 @@ struct StepArgs {
     int stage_chunks;  // chunks of rows per LDS window of the sums
 };
 
+// Arguments of the set-up kernel (cell constants and the coefficient block
+// b | sigma | b_lin | sigma_lin).  The d x q diffusion matrix is not among
+// them (at d = 19 it alone takes 2.9 KB of the kernel-argument block); it is
+// uploaded next to them by launch_setup.
 struct SetupArgs {
     double lo[kMaxDim], hi[kMaxDim];
     int cells[kMaxDim];
     double b[kMaxDim];
-    double sigma[kMaxDim * kMaxDim];
     double b_lin[kMaxDim];
     double sigma_lin[kMaxDim];
     int d, q, cmax;
@@ -96,7 +99,7 @@ struct LaunchShape {
 };
 
 template <typename R>
-hipError_t launch_setup(const SetupArgs &s, void *cellF, void *bsig, hipStream_t st);
+hipError_t launch_setup(const SetupArgs &s, const double *sigma, void *cellF, void *bsig, hipStream_t st);
 template <typename R>
 hipError_t launch_step(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                        const void *cellF, const void *bsig, void *lk, void *table, void *counters,
@@ -119,7 +122,7 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
                        uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
-// The dimensions of the high-dimension file (d = 7, 9, 10 and 11..16, the
+// The dimensions of the high-dimension files (d = 7, 9, 10 and 11..19, the
 // paper's Tables LP0d11 .. LP1d15_19): binary32 sweeps with the cloud in global
 // memory and look-up modes Y and YZ, and every kernel around the sweep.
 bool hd_dimension_compiled(int d);
@@ -163,6 +166,27 @@ hipError_t launch_eval_hd2(int d, int basis, const StepArgs<R> &a, const void *t
                           int64_t n, double *y, double *z, hipStream_t st);
 template <typename R>
 hipError_t launch_draw_hd2(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
+                          uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
+// The same for the third high-dimension file.
+template <typename R>
+hipError_t launch_step_gr_hd3(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                             const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                             hipStream_t st);
+template <typename R>
+hipError_t launch_face_flags_hd3(int d, int basis, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                                void *counters, hipStream_t st);
+template <typename R>
+hipError_t launch_lookup_rows_hd3(int d, int basis, int lkmode, const void *table, void *lk, uint32_t K,
+                                 int i_lo, int i_hi, hipStream_t st);
+template <typename R>
+hipError_t launch_root_hd3(int d, int basis, int lkmode, const StepArgs<R> &a, const void *bsig,
+                          const void *lk, const RootPoint &x0, int M_root, int nblocks, double *partial,
+                          double *out, hipStream_t st);
+template <typename R>
+hipError_t launch_eval_hd3(int d, int basis, const StepArgs<R> &a, const void *table, const double *x,
+                          int64_t n, double *y, double *z, hipStream_t st);
+template <typename R>
+hipError_t launch_draw_hd3(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
                           uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 
 // ------------------------------------------------------ batched sweeps

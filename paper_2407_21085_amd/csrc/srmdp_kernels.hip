@@ -26,7 +26,6 @@ __global__ void setup_kernel(SetupArgs a, CellF<R> *cellF, R *bsig)
         cellF[t] = c < a.cells[l] ? cell_constants<R>(a, l, c) : CellF<R>{};
     }
     if (t < a.d) bsig[t] = (R)a.b[t];
-    if (t < a.d * a.q) bsig[a.d + t] = (R)a.sigma[t];
     if (t < a.d) bsig[a.d + a.d * a.q + t] = (R)a.b_lin[t];
     if (t < a.d) bsig[2 * a.d + a.d * a.q + t] = (R)a.sigma_lin[t];
 }
@@ -60,12 +59,18 @@ static hipError_t launch_step_impl(const StepArgs<R> &a, const LaunchShape &s, c
 }
 
 template <typename R>
-static hipError_t launch_setup_impl(const SetupArgs &s, void *cellF, void *bsig, hipStream_t st)
+static hipError_t launch_setup_impl(const SetupArgs &s, const double *sigma, void *cellF, void *bsig,
+                                    hipStream_t st)
 {
-    const int n = s.d * s.cmax > s.d * s.q ? s.d * s.cmax : s.d * s.q;
+    const int n = s.d * s.cmax > s.d ? s.d * s.cmax : s.d;
     hipLaunchKernelGGL((setup_kernel<R>), dim3((n + 255) / 256), dim3(256), 0, st, s,
                        (CellF<R> *)cellF, (R *)bsig);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // sigma (row-major d x q) in the working precision after b
+    R v[kMaxDim * kMaxDim];
+    for (int t = 0; t < s.d * s.q; ++t) v[t] = (R)sigma[t];
+    return launch_upload((R *)bsig + s.d, v, sizeof(R) * s.d * s.q, st);
 }
 
 // Dispatch tables over the compiled dimensions.
@@ -187,9 +192,9 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &sa, int kin
 }
 
 template <typename R>
-hipError_t launch_setup(const SetupArgs &s, void *cellF, void *bsig, hipStream_t st)
+hipError_t launch_setup(const SetupArgs &s, const double *sigma, void *cellF, void *bsig, hipStream_t st)
 {
-    return launch_setup_impl<R>(s, cellF, bsig, st);
+    return launch_setup_impl<R>(s, sigma, cellF, bsig, st);
 }
 
 bool lds_dimension_compiled(int d)
@@ -258,7 +263,7 @@ size_t cube_global_bytes(int prec_is_float, int d, int nb, int M)
                                        int64_t, double *, double *, hipStream_t);                    \
     template hipError_t launch_draw<R>(int, const StepArgs<R> &, const SetupArgs &, int, uint32_t,  \
                                        uint32_t, uint32_t, uint32_t, int, double *, hipStream_t);    \
-    template hipError_t launch_setup<R>(const SetupArgs &, void *, void *, hipStream_t);
+    template hipError_t launch_setup<R>(const SetupArgs &, const double *, void *, void *, hipStream_t);
 
 SRMDP_INSTANTIATE(float)
 SRMDP_INSTANTIATE(double)

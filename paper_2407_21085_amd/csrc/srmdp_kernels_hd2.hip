@@ -1,24 +1,10 @@
 // The sweep for d = 13..16 (the paper's Tables LP1d13, LP1d14 and LP1d15_19
-// up to d = 16); the other dimensions without the LDS kernel are in
-// srmdp_kernels_hd.hip.
+// up to d = 16); d = 7, 9..12 are in srmdp_kernels_hd.hip and d = 17..19 in
+// srmdp_kernels_hd3.hip.
 #define HD_DIMS(X) X(13) X(14) X(15) X(16)
 #define HD_FN(name) name##2
-#define HD_NEXT(name) hd_none_##name
+#define HD_NEXT(name) name##3
 #define HD_KERNEL sweep_step_hd2_kernel
 #define HD_IMPL launch_hd2_impl
-
-#include <hip/hip_runtime.h>
-
-namespace srmdp {
-// Past the last high-dimension file: no such dimension.
-template <typename R, typename... A>
-static hipError_t hd_none(A...) { return hipErrorInvalidValue; }
-}  // namespace srmdp
-#define hd_none_launch_step_gr_hd hd_none
-#define hd_none_launch_face_flags_hd hd_none
-#define hd_none_launch_lookup_rows_hd hd_none
-#define hd_none_launch_root_hd hd_none
-#define hd_none_launch_eval_hd hd_none
-#define hd_none_launch_draw_hd hd_none
 
 #include "srmdp_hd_body.hpp"

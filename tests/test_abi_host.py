@@ -179,9 +179,9 @@ def test_global_rows_workspace_and_rejections():
 
 
 def test_high_dimensions_run_binary32_sweeps_only():
-    """d = 7, 9, 10 and 11..16 have the global-rows sweep in binary32 with
+    """d = 7, 9, 10 and 11..19 have the global-rows sweep in binary32 with
     look-up modes Y and YZ only: binary64, z truncation (mode Full) and the
-    control variate are refused before anything is enqueued; d = 17 is outside
+    control variate are refused before anything is enqueued; d = 20 is outside
     the ABI."""
     S = _S()
     G = S.Grid([-1.0] * 11, [1.0] * 11, [2] * 11)
@@ -192,8 +192,13 @@ def test_high_dimensions_run_binary32_sweeps_only():
     ]:
         rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
         assert rc == status, S.srmdp.lib.srmdp_last_error().decode()
-    G17 = S.Grid([-1.0] * 17, [1.0] * 17, [2] * 17)
-    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=17, N=3).c(), G17.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16,
+    G19 = S.Grid([-1.0] * 19, [1.0] * 19, [2] * 10 + [1] * 9)
+    assert S.workspace_bytes(S.Problem(d=19, N=3), G19, S.Options(M=40, prec=S.FP32)) > 0
+    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=19, N=3).c(), G19.c(), S.Options(M=40, prec=S.FP64).c(), 16, 16,
+                                 1 << 40, None, None)
+    assert rc == -2
+    G20 = S.Grid([-1.0] * 20, [1.0] * 20, [2] * 20)
+    rc = S.srmdp.lib.srmdp_solve(S.Problem(d=20, N=3).c(), G20.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16,
                                  1 << 40, None, None)
     assert rc == -1
 

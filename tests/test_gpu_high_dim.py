@@ -1,4 +1,4 @@
-"""The dimensions without the LDS kernel, d = 7, 9, 10 and 11..16 (the paper's
+"""The dimensions without the LDS kernel, d = 7, 9, 10 and 11..19 (the paper's
 Tables LP0d11 and LP1d11 .. LP1d15_19): binary32 sweeps with the clouds in
 global memory, per step against the FP64 oracle from the same rows (GPU tests,
 through the C ABI)."""
@@ -31,6 +31,9 @@ def _logistic(d, cells, M, N, basis="LP1"):
     (13, [2] * 5 + [1] * 8, 40, "LP1"),
     (16, [2] * 8 + [1] * 8, 64, "LP1"),
     (12, [3] * 4 + [1] * 8, 32, "LP0"),
+    (17, [2] * 6 + [1] * 11, 40, "LP1"),
+    (18, [3] * 3 + [1] * 15, 32, "LP0"),
+    (19, [2] * 7 + [1] * 12, 48, "LP1"),
 ])
 def test_high_dimension_per_step_parity(d, cells, M, basis):
     """The logistic BSDE (look-up mode YZ) at d = 11, 13, 16 (LP1) and 12 (LP0),
