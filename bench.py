@@ -64,7 +64,7 @@ LOCATE_OPS_EP = 17
 KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_sweep.hpp", "srmdp_device.hpp", "srmdp_internal.hpp",
                   "srmdp_mlp.hpp")
 MEASURED_TRAFFIC = {
-    "762ed011d98c7ef1": {"bytes": 5.629466e+09,
+    "7dd5716617f679b5": {"bytes": 5.660507e+09,
                          "profile": "profiles/sweep_step_kernel_logistic_d8_K65536_M64_N50.md"},
 }
 
@@ -580,6 +580,7 @@ def main() -> int:
 
     import paper_2407_21085_amd as S
 
+    t_start = time.perf_counter()
     cfg = W.config(args.workload)
     P, G, Opt = _product_args(S, cfg)
     dev = torch.device("cuda", 0)
@@ -655,19 +656,29 @@ def main() -> int:
         "y0_exact_continuous": 0.5 if cfg["terminal"] == "logistic" else None,
         "lanes_per_cube": stats[0]["lanes_per_cube"],
     }
+    def progress(section):
+        # one line per finished section on stderr (the JSON result is the only stdout line)
+        print(f"[bench] {section} done after {time.perf_counter() - t_start:.0f} s", file=sys.stderr, flush=True)
+
+    progress("headline sweep")
     if not args.no_equal_prob:
         out["equal_probability"] = equal_probability(S, cfg, stream, args.steps, args.root_paths)
+        progress("equal-probability cells")
     if not args.no_ragged_batch:
         out["ragged_batch"] = ragged_batch(S, stream)
+        progress("ragged batch")
     if not args.no_paper_tables:
         out["paper_tables"] = paper_tables(S, stream)
+        progress("paper tables")
     if not args.no_error_matched and cfg["driver"] == "logistic":
         M = cfg["M"]
         out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), [M, 2 * M, 4 * M, 8 * M],
                                              [M // 2, M, 2 * M], 8 * M, range(1001, 1001 + 2 * args.em_seeds),
                                              1 << 20, stream)
+        progress("error-matched comparison")
     if not args.no_cv_equal_m:
         out["cv_equal_M"] = cv_equal_m(S, W.config("cfg4"), range(1, 5), stream)
+        progress("equal-M comparison")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
