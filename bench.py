@@ -495,11 +495,11 @@ def ragged_batch(S, stream) -> dict:
 def equal_probability(S, cfg, stream, steps: int, root_paths: int) -> dict:
     """The workload on equal-probability cells (the same cells per dimension,
     cut at the logistic quantiles: every cube of probability 1/K, the outer
-    ones unbounded), and for reference on its equal-size cells through the
-    same global-cloud kernel body: ms per sweep from HIP events on the
-    library's stream after a warm-up, path-steps/s, the ALU roofline fraction
-    of the equal-probability kernel (its longer cell location counted), and
-    y(0, x0) from the ROOT read-out beside the equal-size grid's.
+    ones unbounded), and for reference on its equal-size cells, both with the
+    clouds in LDS: ms per sweep from HIP events on the library's stream after a
+    warm-up, path-steps/s, the ALU roofline fraction of each kernel (the longer
+    cell location of equal-probability cells counted), and y(0, x0) from the
+    ROOT read-out.
 
     Both runs truncate y at C_y = 1 (eq. (TL); the logistic solution lies in
     (0, 1)): on the unbounded outer cells the few far samples steer the LP1
@@ -508,8 +508,9 @@ def equal_probability(S, cfg, stream, steps: int, root_paths: int) -> dict:
     import torch
     out = {}
     lookup_terms = 2 if (cfg["driver"] == "logistic" or cfg.get("kappa", 0.0)) else 1
-    for key, c in (("equal_probability", dict(cfg, lo=None, hi=None, grid_kind=1, clamp_y=1.0)),
-                   ("equal_size_global_rows", dict(cfg, flags=S.F_GLOBAL_ROWS, clamp_y=1.0))):
+    for key, c, kernel in (("equal_probability", dict(cfg, lo=None, hi=None, grid_kind=1, clamp_y=1.0),
+                            "sweep_step_ep_kernel"),
+                           ("equal_size", dict(cfg, clamp_y=1.0), "sweep_step_kernel")):
         P, G, Opt = _product_args(S, c)
         table = S.srmdp.alloc_table(P, G, Opt)
         ws = S.srmdp.alloc_workspace(P, G, Opt)
@@ -531,7 +532,7 @@ def equal_probability(S, cfg, stream, steps: int, root_paths: int) -> dict:
         out[key] = {"ms_per_sweep": ms, "path_steps_per_s": W.path_steps(c) / (ms / 1e3),
                     "launches_per_sweep": launches, "avg_launch_ms": ms_steps / launches,
                     "roofline_frac": ops / (ms_steps / 1e3) / VALU_PEAK_OPS,
-                    "ops_per_path_step": ops_step, "kernel": "sweep_step_gr_kernel", "clamp_y": c["clamp_y"],
+                    "ops_per_path_step": ops_step, "kernel": kernel, "clamp_y": c["clamp_y"],
                     "y0_root": y0}
         del table, ws
         torch.cuda.empty_cache()

@@ -394,8 +394,7 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
         return true;
     }
     const size_t lds_cap = 64 * 1024;
-    // equal-probability cells run on the global-cloud kernels only
-    const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d) || s.equal_prob;
+    const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d);
     if (force || per_cube > lds_cap) {
         ls.grows = true;
         per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
@@ -419,6 +418,9 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
                              unsigned char *ws, size_t off_cellF, size_t off_bsig, size_t off_lookup,
                              size_t off_counters, size_t off_grows, void *table, hipStream_t st)
 {
+    if (!ls.grows && a.equal_prob)
+        return launch_step_ep_lds<R>(s.d, a, ls, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
+                                     ws + off_counters, st);
     if (!ls.grows)
         return launch_step<R>(s.d, a, ls, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
                               ws + off_counters, st);

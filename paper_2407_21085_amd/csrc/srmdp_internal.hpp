@@ -226,9 +226,13 @@ template <typename R>
 hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,
                           hipStream_t st);
-// Equal-probability cells (srmdp_kernels_ep.hip).
+// Equal-probability cells (srmdp_kernels_ep.hip): clouds in global memory, and in LDS.
 template <typename R>
 hipError_t launch_step_ep(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
+                          const void *cellF, const void *bsig, void *lk, void *table, void *counters,
+                          hipStream_t st);
+template <typename R>
+hipError_t launch_step_ep_lds(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,
                           hipStream_t st);
 

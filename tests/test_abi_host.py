@@ -273,11 +273,11 @@ def test_batch_workspace_and_rejections():
 
 
 def test_equal_probability_grid_host_checks():
-    """Equal-probability cells: lo and hi may be NULL; they always take the
-    global-cloud kernels (a workspace at least that of the forced global rows
-    of an equal-size grid of the same shape); the control variate, the
-    dimensions without the LDS kernel, batches and an unknown grid kind are
-    refused before anything is enqueued."""
+    """Equal-probability cells: lo and hi may be NULL; the workspace is that of
+    an equal-size grid of the same shape (clouds in LDS, or in global memory
+    with SRMDP_F_GLOBAL_ROWS); the control variate, the dimensions without the
+    LDS kernel, batches and an unknown grid kind are refused before anything is
+    enqueued."""
     import ctypes
     S = _S()
     lib = S.srmdp.lib
@@ -285,8 +285,9 @@ def test_equal_probability_grid_host_checks():
     Gp = S.Grid(None, None, [5, 4], 1.3, kind=S.GRID_EQUAL_PROB)
     Gs = S.Grid([-2.0] * 2, [2.0] * 2, [5, 4], 1.3)
     ws_p = S.workspace_bytes(P, Gp, S.Options(M=40))
-    assert ws_p == S.workspace_bytes(P, Gs, S.Options(M=40, flags=S.F_GLOBAL_ROWS))
-    assert ws_p > S.workspace_bytes(P, Gs, S.Options(M=40))
+    assert ws_p == S.workspace_bytes(P, Gs, S.Options(M=40))
+    assert (S.workspace_bytes(P, Gp, S.Options(M=40, flags=S.F_GLOBAL_ROWS)) ==
+            S.workspace_bytes(P, Gs, S.Options(M=40, flags=S.F_GLOBAL_ROWS)) > ws_p)
     cv = S.Options(M=40, prec=S.FP32, cv=1, cv_params=_FakeTensor())
     assert lib.srmdp_solve(P.c(), Gp.c(), cv.c(), 16, 16, 1 << 40, None, None) == -2
     G7 = S.Grid(None, None, [2] * 7, kind=S.GRID_EQUAL_PROB)

@@ -127,3 +127,14 @@ def test_equal_probability_readouts_of_oracle_table(basis):
     yr, zr = O.root(Po, orc, x0, 20000)
     assert y0 == pytest.approx(yr, rel=1e-9)
     np.testing.assert_allclose(z0, zr, rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_equal_probability_global_rows_bit_identical(prec):
+    """The clouds in global memory (SRMDP_F_GLOBAL_ROWS, 8 strata per launch)
+    give the same table, bit for bit, as the clouds in LDS."""
+    cfg = _ep("cfg2", f"equal-probability global rows {prec}", d=3, N=4, cells=[4, 3, 5], M=40, prec=prec, mu=1.2)
+    lds, _ = TP.gpu_table(cfg)
+    gr, _ = TP.gpu_table(cfg, flags=0x10, global_rows_strata=8)
+    np.testing.assert_array_equal(gr, lds)
+
