@@ -53,9 +53,9 @@ UNIFORM_OPS = 4                  # shift, or, convert, scale
 BOX_MULLER_OPS = 8               # log, sqrt, sincos (2), 4 multiplies per pair
 LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma, xi fma
 # equal-probability cells: C F(x) (multiply, exp and its scaling, add, reciprocal,
-# multiply), floor, clamp, the median ratio (2 adds, reciprocal, multiply), log and
-# its scaling, the xi fma, convert, index fma
-LOCATE_OPS_EP = 17
+# multiply), floor, clamp, the index of the cell median in the sampler's table,
+# xi = mu (x - median) (subtract, multiply), convert, index fma
+LOCATE_OPS_EP = 13
 
 # Bytes beyond L2 per launch of the sweep-step kernel of the default workload, from
 # FETCH_SIZE / WRITE_SIZE counter passes scaled by a plain copy's readings (fetch 2.0,

@@ -418,6 +418,7 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
                              unsigned char *ws, size_t off_cellF, size_t off_bsig, size_t off_lookup,
                              size_t off_counters, size_t off_grows, void *table, hipStream_t st)
 {
+    a.cell_table = ws + off_cellF;
     if (!ls.grows && a.equal_prob)
         return launch_step_ep_lds<R>(s.d, a, ls, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
                                      ws + off_counters, st);
@@ -708,6 +709,7 @@ srmdp_status root_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
         HIP_TRY(launch_lookup_rows<R>(s.d, o->basis, lk, table, ws + lay.lookup, (uint32_t)s.K, 1, s.N - 1, st),
                 "look-up rows");
     const int blocks = std::min(kRootBlocks, std::max(1, (M_root + 255) / 256));
+    a.cell_table = ws + lay.cellF;
     HIP_TRY(launch_root<R>(s.d, o->basis, lk, a, ws + lay.bsig, ws + lay.lookup, rp, M_root, blocks,
                            (double *)(ws + lay.root_partial), (double *)(ws + lay.root_out), st),
             "root kernels");

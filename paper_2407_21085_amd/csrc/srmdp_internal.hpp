@@ -53,6 +53,8 @@ struct StepArgs {
     R r, kappa, c_logistic, clamp_y, clamp_z;
     int identity_sigma, has_drift, has_lin_drift, has_lin_sigma;
     int equal_prob;       // cells cut at the logistic quantiles F^{-1}(c / cells)
+    const void *cell_table;  // the sampler's CellF<R> [d][cmax] (centre = nu-median of an
+                             // equal-probability cell), read by the sweep and ROOT paths
     int lanes;
     int check_finite;
     size_t lds_per_cube;

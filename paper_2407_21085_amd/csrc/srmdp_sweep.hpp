@@ -132,16 +132,29 @@ __device__ __forceinline__ bool near_face(const StepArgs<R> &a, const R *x)
 
 // Cell of x per dimension, clamped to the grid (equal-size cells:
 // floor((x - lo) cells / (hi - lo)), xi = 2 (t - cell) - 1; equal-probability
-// cells as in cell_and_xi), and the offset of the stratum's look-up record in a
-// row.  The stratum index is accumulated in the working precision, exact
-// because K <= 2^24; K W < 2^32 so the offset is a 24-bit product.
+// cells: t = C F(x), xi = mu (x - m_c) with the cell's nu-median m_c read from
+// the sampler's table instead of its logarithm), and the offset of the
+// stratum's look-up record in a row.  The stratum index is accumulated in the
+// working precision, exact because K <= 2^24; K W < 2^32 so the offset is a
+// 24-bit product.
 template <typename R, int D, int NB, int LK, bool EP>
 __device__ __forceinline__ uint32_t locate(const StepArgs<R> &a, const R *x, R *xi)
 {
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     R kf = (R)0;
+    if constexpr (EP) {
+        const CellF<R> *med = (const CellF<R> *)a.cell_table;
 #pragma unroll
-    for (int l = 0; l < D; ++l) kf = cell_and_xi<R, EP>(a, l, x[l], xi[l]) * a.stride_f[l] + kf;
+        for (int l = 0; l < D; ++l) {
+            const R mu = a.scale[l] + a.scale[l];
+            const R c = RealOps<R>::clamp_cell(cell_coord<R, true>(a, l, x[l]), a.cmax_f[l]);
+            xi[l] = mu * (x[l] - med[l * a.cmax + (int)c].centre);
+            kf = c * a.stride_f[l] + kf;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < D; ++l) kf = cell_and_xi<R, false>(a, l, x[l], xi[l]) * a.stride_f[l] + kf;
+    }
     return __umul24((uint32_t)kf, (uint32_t)W);
 }
 

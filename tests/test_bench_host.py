@@ -21,9 +21,9 @@ def test_algorithmic_ops_of_the_headline_workload():
     per_step, per_sample, _ = B.algorithmic_ops(W.config("cfg5"), 2)
     assert per_step == 361
     assert per_sample == 495
-    # equal-probability cells: 17 operations per cell location instead of 8
+    # equal-probability cells: 13 operations per cell location instead of 8
     per_step_ep, per_sample_ep, _ = B.algorithmic_ops(dict(W.config("cfg5"), grid_kind=1), 2)
-    assert per_step_ep == 361 + 8 * 9
+    assert per_step_ep == 361 + 8 * 5
     assert per_sample_ep == 495
 
 
