@@ -138,3 +138,37 @@ def test_equal_probability_global_rows_bit_identical(prec):
     gr, _ = TP.gpu_table(cfg, flags=0x10, global_rows_strata=8)
     np.testing.assert_array_equal(gr, lds)
 
+
+
+def test_equal_probability_graph_replay_and_resume():
+    """A captured sweep (SRMDP_F_GRAPH, binary32) replayed three times, with
+    eager work and synchronisations between the replays, gives the direct
+    sweep's table bit for bit; so does a binary64 sweep resumed from the
+    middle with a fresh workspace (in binary32 a resumed step rebuilds its
+    look-up rows from the rounded table, so it agrees to rounding only)."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    cfg = _ep("cfg2", "equal-probability graph and resume", d=4, N=6, cells=[4, 3, 2, 3], M=48, mu=0.9)
+    ref, _ = TP.gpu_table(cfg)
+    P, G, Opt = product_args(cfg, flags=S.F_GRAPH)
+    stream = torch.cuda.Stream()
+    table = S.srmdp.alloc_table(P, G, Opt)
+    ws = S.srmdp.alloc_workspace(P, G, Opt)
+    for rep in range(3):
+        _say(f"[gpu] equal-probability graph replay {rep}")
+        table.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            S.solve(P, G, Opt, table=table, workspace=ws, stream=stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(table.double().cpu().numpy(), ref)
+    S.release_graphs()
+    _say("[gpu] equal-probability resume (binary64): steps 5..3 then 2..0")
+    c64 = dict(cfg, prec="fp64")
+    ref64, _ = TP.gpu_table(c64)
+    P, G, Opt = product_args(c64, step_hi=5, step_lo=3)
+    part, _ = S.solve(P, G, Opt)
+    P, G, Opt = product_args(c64, step_hi=2, step_lo=0)
+    part, _ = S.solve(P, G, Opt, table=part)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(part.cpu().numpy(), ref64)
