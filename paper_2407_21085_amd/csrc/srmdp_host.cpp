@@ -870,13 +870,13 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
         if (b == 0) {
             bp.nb = nb;
             bp.lk = lk;
-        } else if (P[b].d != P[0].d || O[b].basis != O[0].basis || O[b].prec != O[0].prec || lk != bp.lk) {
-            return fail(SRMDP_E_INVALID, "instance %d: a batch shares d, basis, precision and look-up mode", b);
+        } else if (P[b].d != P[0].d || O[b].basis != O[0].basis || O[b].prec != O[0].prec || lk != bp.lk ||
+                   bp.shapes[b].equal_prob != bp.shapes[0].equal_prob) {
+            return fail(SRMDP_E_INVALID, "instance %d: a batch shares d, basis, precision, look-up mode and grid kind",
+                        b);
         }
         if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0)
             return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
-        if (bp.shapes[b].equal_prob)
-            return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run equal-size cells", b);
         bp.gmax = std::max(bp.gmax, P[b].N);
     }
     if (!lds_dimension_compiled(P[0].d))
@@ -948,6 +948,7 @@ srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, c
         I.a.lds_per_cube = per_cube;
         I.a.face_flags = nullptr;
         I.cellF = w + lay.cellF;
+        I.a.cell_table = I.cellF;
         I.bsig = w + lay.bsig;
         I.lk = w + lay.lookup;
         I.table = tables[b];
@@ -972,7 +973,8 @@ srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, c
     int active = n;
     for (int g = 0; g < bp.gmax; ++g) {
         while (active > 0 && P[bp.order[active - 1]].N <= g) --active;
-        HIP_TRY(launch_batch_step<R>(P[0].d, O[0].basis, bp.lk, ws, active, prefix[active], g, threads, lds, st),
+        HIP_TRY(launch_batch_step<R>(P[0].d, O[0].basis, bp.lk, bp.shapes[0].equal_prob, ws, active, prefix[active], g,
+                                     threads, lds, st),
                 "batched step");
     }
     return SRMDP_OK;

@@ -209,8 +209,8 @@ struct BatchInstance {
 };
 
 template <typename R>
-hipError_t launch_batch_step(int d, int basis, int lkmode, const void *inst, int n_active, uint32_t total_items,
-                             int g, unsigned threads, size_t lds_bytes, hipStream_t st);
+hipError_t launch_batch_step(int d, int basis, int lkmode, bool equal_prob, const void *inst, int n_active,
+                             uint32_t total_items, int g, unsigned threads, size_t lds_bytes, hipStream_t st);
 // Copies `bytes` from host memory to the device through kernel arguments (no
 // staging buffer, nothing to keep alive after the call, capturable).
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);

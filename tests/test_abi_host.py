@@ -276,8 +276,9 @@ def test_equal_probability_grid_host_checks():
     """Equal-probability cells: lo and hi may be NULL; the workspace is that of
     an equal-size grid of the same shape (clouds in LDS, or in global memory
     with SRMDP_F_GLOBAL_ROWS); the control variate, the dimensions without the
-    LDS kernel, batches and an unknown grid kind are refused before anything is
-    enqueued."""
+    LDS kernel and an unknown grid kind are refused before anything is
+    enqueued; a batch may hold equal-probability instances when all of them
+    do."""
     import ctypes
     S = _S()
     lib = S.srmdp.lib
@@ -298,8 +299,9 @@ def test_equal_probability_grid_host_checks():
     assert lib.srmdp_solve(P.c(), Gbad.c(), S.Options(M=40).c(), 16, 16, 1 << 40, None, None) == -1
     Gnull = S.Grid(None, None, [5, 4], 1.3)   # equal size without lo/hi
     assert lib.srmdp_solve(P.c(), Gnull.c(), S.Options(M=40).c(), 16, 16, 1 << 40, None, None) == -1
+    # a batch shares the grid kind
     Pb, Gb, Ob = _batch(S)
     Gb[1] = S.Grid(None, None, [3, 3], kind=S.GRID_EQUAL_PROB)
     n, Pa, Ga, Oa = S.srmdp._arrays(Pb, Gb, Ob)
     ptrs = (ctypes.c_void_p * n)(*([4096] * n))
-    assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -2
+    assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -1

@@ -73,6 +73,25 @@ def test_ragged_batch_equals_individual_sweeps(prec):
         assert torch.equal(t, ref), c["name"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_equal_probability_batch_equals_individual_sweeps(prec):
+    """A ragged batch on equal-probability cells (every instance of the batch
+    on that grid) gives each instance's own table bit for bit."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfgs = [dict(c, lo=None, hi=None, grid_kind=1, mu=0.8 + 0.1 * b)
+            for b, c in enumerate(_small_ragged(prec, n=6, seed=9))]
+    P, G, O = _args(cfgs)
+    _say(f"[gpu] equal-probability ragged batch of {len(cfgs)} ({prec})")
+    tables, stats = S.solve_batch(P, G, O)
+    torch.cuda.synchronize()
+    for c, p, g, o, t, st in zip(cfgs, P, G, O, tables, stats):
+        o.lanes_per_cube = st["lanes_per_cube"]
+        ref, _ = S.solve(p, g, o)
+        torch.cuda.synchronize()
+        assert torch.equal(t, ref), c["name"]
+
+
 def test_ragged_batch_graph_replays():
     import paper_2407_21085_amd as S
     torch = _torch()
