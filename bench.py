@@ -573,8 +573,8 @@ def main() -> int:
         print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 10}), flush=True)
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sweep's "
-              "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): it measures one GPU's share of the "
+              "sweep; sharding the strata over several GPUs is a design, not a measured path.", file=sys.stderr)
         return 2
 
     import torch
