@@ -449,10 +449,32 @@ sweep_step_cv_kernel(const StepArgs<float> a, const CellF<float> *__restrict__ c
                                         counters, smem);
 }
 
+// The same on equal-probability cells (look-up modes Y and YZ).
+template <int D, int NB, int LK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+sweep_step_cv_ep_kernel(const StepArgs<float> a, const CellF<float> *__restrict__ cellF,
+                        const float *__restrict__ bsig, float *__restrict__ lk, float *__restrict__ table,
+                        unsigned long long *__restrict__ counters)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_group<float, D, NB, LK, true, false, true>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk,
+                                                     table, counters, smem);
+}
+
 template <int D, int NB, int LK>
 static hipError_t launch_step_cv_impl(const StepArgs<float> &a, const LaunchShape &s, const void *cellF,
                                       const void *bsig, void *lk, void *table, void *counters, hipStream_t st)
 {
+    if (a.equal_prob) {
+        if constexpr (LK == kLookupFull) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((sweep_step_cv_ep_kernel<D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes,
+                               st, a, (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
+                               (unsigned long long *)counters);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((sweep_step_cv_kernel<D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st, a,
                        (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
                        (unsigned long long *)counters);

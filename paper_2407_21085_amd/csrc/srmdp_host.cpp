@@ -135,8 +135,7 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     if (o->global_rows_strata < 0) return fail(SRMDP_E_INVALID, "global_rows_strata < 0");
     if ((o->flags & SRMDP_F_GLOBAL_ROWS) && o->cv != SRMDP_CV_NONE)
         return fail(SRMDP_E_UNSUPPORTED, "global cloud rows run without the control variate");
-    if (s.equal_prob && o->cv != SRMDP_CV_NONE)
-        return fail(SRMDP_E_UNSUPPORTED, "equal-probability cells run without the control variate");
+
     if (s.equal_prob && !lds_dimension_compiled(s.d))
         return fail(SRMDP_E_UNSUPPORTED, "equal-probability cells are compiled for d = 1..6 and 8, not %d", s.d);
     if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
@@ -446,6 +445,8 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
 // (both precisions, every mode) exists for the dimensions of the main file.
 srmdp_status sweep_supported(const Shape &s, const srmdp_options *o, int lk)
 {
+    if (s.equal_prob && o->cv != SRMDP_CV_NONE && lk == kLookupFull)
+        return fail(SRMDP_E_UNSUPPORTED, "the control variate on equal-probability cells takes no z truncation");
     if (!dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "d = %d is not compiled", s.d);
     if (!lds_dimension_compiled(s.d) &&
         (o->prec != SRMDP_FP32 || (lk != kLookupY && lk != kLookupYZ) || o->cv != SRMDP_CV_NONE))
@@ -514,6 +515,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
                                       s.N - 1, st),
                 "look-up rows");
     if (steps0) HIP_TRY(hipEventRecord(steps0, st), "hipEventRecord");
+    a.cell_table = ws + lay.cellF;
     for (int i = hi; i >= lo; --i) {
         a.i = i;
         a.tag = ((uint32_t)i & 0xFFFFu) | (o->instance << 16);
@@ -786,10 +788,13 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
         a.lanes = L;
         a.lds_per_cube = per_cube;
         auto launch = [&]() -> hipError_t {
-            if constexpr (std::is_same<R, float>::value)
-                if (cv)
+            if constexpr (std::is_same<R, float>::value) {
+                if (cv) {
+                    a.cell_table = ws + lay.cellF;
                     return launch_step_cv(s.d, a, ls, o->basis, lk, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup,
                                           table, ws + lay.counters, st);
+                }
+            }
             return launch_plain_step<R>(s, a, ls, o->basis, lk, ws, lay.cellF, lay.bsig, lay.lookup, lay.counters,
                                         lay.grows, table, st);
         };

@@ -275,8 +275,9 @@ def test_batch_workspace_and_rejections():
 def test_equal_probability_grid_host_checks():
     """Equal-probability cells: lo and hi may be NULL; the workspace is that of
     an equal-size grid of the same shape (clouds in LDS, or in global memory
-    with SRMDP_F_GLOBAL_ROWS); the control variate, the dimensions without the
-    LDS kernel and an unknown grid kind are refused before anything is
+    with SRMDP_F_GLOBAL_ROWS); the control variate with z truncation, the
+    dimensions without the LDS kernel and an unknown grid kind are refused
+    before anything is
     enqueued; a batch may hold equal-probability instances when all of them
     do."""
     import ctypes
@@ -290,7 +291,8 @@ def test_equal_probability_grid_host_checks():
     assert (S.workspace_bytes(P, Gp, S.Options(M=40, flags=S.F_GLOBAL_ROWS)) ==
             S.workspace_bytes(P, Gs, S.Options(M=40, flags=S.F_GLOBAL_ROWS)) > ws_p)
     cv = S.Options(M=40, prec=S.FP32, cv=1, cv_params=_FakeTensor())
-    assert lib.srmdp_solve(P.c(), Gp.c(), cv.c(), 16, 16, 1 << 40, None, None) == -2
+    Pz = S.Problem(d=2, N=4, clamp_z=0.3)   # z truncation: look-up mode Full
+    assert lib.srmdp_solve(Pz.c(), Gp.c(), cv.c(), 16, 16, 1 << 40, None, None) == -2
     G7 = S.Grid(None, None, [2] * 7, kind=S.GRID_EQUAL_PROB)
     rc = lib.srmdp_solve(S.Problem(d=7, N=3).c(), G7.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16, 1 << 40,
                          None, None)
