@@ -1,6 +1,10 @@
 """Builds libsrmdp.so (HIP kernels + C ABI host runtime) for gfx950 in-tree.
 
-    python -m paper_2407_21085_amd.build
+    python -m paper_2407_21085_amd.build            # always compiles
+    python -m paper_2407_21085_amd.build --if-stale # only when a source is newer
+
+This module imports nothing from the package's binding, so it runs on a tree
+where the library has never been built.
 """
 from __future__ import annotations
 
@@ -44,7 +48,8 @@ def _compile(src: str, obj: str) -> None:
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles every source and links libsrmdp.so next to this file."""
+    """Compiles every source and links libsrmdp.so next to this file, then
+    records the hash of its sources beside it (libsrmdp.so.srchash)."""
     with tempfile.TemporaryDirectory(prefix="srmdp_build_") as tmp:
         objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
@@ -56,10 +61,54 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("link of libsrmdp.so failed")
         os.replace(out_tmp, LIB_PATH)
+    with open(STAMP_PATH + ".tmp", "w") as f:
+        f.write(source_hash() + "\n")
+    os.replace(STAMP_PATH + ".tmp", STAMP_PATH)
     if verbose:
         print(f"built {LIB_PATH}")
     return LIB_PATH
 
 
+STAMP_PATH = LIB_PATH + ".srchash"
+
+
+def source_hash() -> str:
+    """SHA-256 of every file under csrc/ and include/, this script and the flags.
+
+    Content, not modification times: a copied or extracted tree keeps its
+    hash, so a library built from the same sources is recognised as current."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(HIP_FLAGS[:-4]).encode())
+    files = [os.path.abspath(__file__)]
+    for root in (CSRC, INCLUDE):
+        files += [os.path.join(root, n) for n in sorted(os.listdir(root))]
+    for path in files:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def is_stale() -> bool:
+    """True when libsrmdp.so is missing or was built from other sources."""
+    if not os.path.exists(LIB_PATH) or not os.path.exists(STAMP_PATH):
+        return True
+    with open(STAMP_PATH) as f:
+        return f.read().strip() != source_hash()
+
+
+def ensure_built(verbose: bool = False) -> str:
+    """Builds the library only when `is_stale()`; returns its path."""
+    if is_stale():
+        if verbose:
+            print(f"building {LIB_PATH} (missing or built from other sources)", flush=True)
+        return build(verbose=verbose)
+    return LIB_PATH
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--if-stale" in sys.argv:
+        ensure_built(verbose=True)
+    else:
+        build(verbose=True)

@@ -14,6 +14,15 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session", autouse=True)
+def _library_built():
+    # libsrmdp.so is built in-tree when it is missing or was built from other
+    # sources (content hash); a current library is used as it is
+    from paper_2407_21085_amd import build as B
+    B.ensure_built(verbose=True)
+    yield
+
+
+@pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
     import oracle
     # rebuilt when missing or older than its C source or header
