@@ -1,7 +1,8 @@
 """Builds libsrmdp.so (HIP kernels + C ABI host runtime) for gfx950 in-tree.
 
     python -m paper_2407_21085_amd.build            # always compiles
-    python -m paper_2407_21085_amd.build --if-stale # only when a source is newer
+    python -m paper_2407_21085_amd.build --if-stale # only when the sources changed
+    python -m paper_2407_21085_amd.build --incremental  # reuse unchanged objects
 
 This module imports nothing from the package's binding, so it runs on a tree
 where the library has never been built.
@@ -47,13 +48,47 @@ def _compile(src: str, obj: str) -> None:
         raise RuntimeError(f"hipcc failed on {src}")
 
 
-def build(verbose: bool = False) -> str:
+OBJ_CACHE = os.path.join(os.path.dirname(HERE), "_build", "objects")
+
+
+def _unit_hash(src: str) -> str:
+    """Hash of one unit: its own text, every header it may include, the flags."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(HIP_FLAGS[:-4]).encode())
+    with open(os.path.join(CSRC, src), "rb") as f:
+        h.update(f.read())
+    for root in (CSRC, INCLUDE):
+        for n in sorted(os.listdir(root)):
+            if n.endswith((".h", ".hpp")):
+                with open(os.path.join(root, n), "rb") as f:
+                    h.update(n.encode() + f.read())
+    return h.hexdigest()[:24]
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compiles every source and links libsrmdp.so next to this file, then
-    records the hash of its sources beside it (libsrmdp.so.srchash)."""
+    records the hash of its sources beside it (libsrmdp.so.srchash).
+
+    incremental=True reuses objects under _build/objects whose unit and
+    headers are unchanged (a development aid; the default compiles all)."""
     with tempfile.TemporaryDirectory(prefix="srmdp_build_") as tmp:
-        objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
-        with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-            list(ex.map(_compile, SOURCES, objs))
+        if incremental:
+            os.makedirs(OBJ_CACHE, exist_ok=True)
+            objs = [os.path.join(OBJ_CACHE, f"{s}.{_unit_hash(s)}.o") for s in SOURCES]
+        else:
+            objs = [os.path.join(tmp, s + ".o") for s in SOURCES]
+        todo = [(s, o) for s, o in zip(SOURCES, objs) if not os.path.exists(o)]
+        if verbose and incremental:
+            print(f"compiling {[s for s, _ in todo]}", flush=True)
+
+        def one(so):
+            s, o = so
+            _compile(s, o + ".part")
+            os.replace(o + ".part", o)
+
+        with ThreadPoolExecutor(max_workers=max(1, len(todo))) as ex:
+            list(ex.map(one, todo))
         out_tmp = LIB_PATH + ".tmp"
         cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", out_tmp]
         res = subprocess.run(cmd, capture_output=True, text=True)
@@ -111,4 +146,4 @@ if __name__ == "__main__":
     if "--if-stale" in sys.argv:
         ensure_built(verbose=True)
     else:
-        build(verbose=True)
+        build(verbose=True, incremental="--incremental" in sys.argv)

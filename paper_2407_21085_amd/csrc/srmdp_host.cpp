@@ -52,6 +52,27 @@ srmdp_status hip_fail(hipError_t e, const char *what)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Timing events of one call, destroyed on every return path.
+struct EventSet {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    EventSet() = default;
+    EventSet(const EventSet &) = delete;
+    EventSet &operator=(const EventSet &) = delete;
+    ~EventSet()
+    {
+        for (hipEvent_t &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    hipError_t create(int n)
+    {
+        for (int j = 0; j < n; ++j) {
+            const hipError_t err = hipEventCreate(&e[j]);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+};
+
 // ------------------------------------------------------------- validation
 struct Shape {
     int d, q, N, nb, cmax;
@@ -574,13 +595,11 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
     const int lk = lookup_mode(p);
     const Layout lay = layout(s, nb, sizeof(R) == 4, lk, o);
     unsigned char *ws = (unsigned char *)workspace;
-    hipEvent_t e0 = nullptr, e1 = nullptr, s0 = nullptr, s1 = nullptr;
+    EventSet ev;
+    hipEvent_t &e0 = ev.e[0], &e1 = ev.e[1], &s0 = ev.e[2], &s1 = ev.e[3];
     bool graph_used = false;
     if (stats) {
-        HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&s0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&s1), "hipEventCreate");
+        HIP_TRY(ev.create(4), "hipEventCreate");
         HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
     }
     srmdp_status rc = SRMDP_OK;
@@ -675,10 +694,6 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
                 stats->cv_loss_first = (float)(first / U);
                 stats->cv_loss_last = (float)(last / U);
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            (void)hipEventDestroy(s0);
-            (void)hipEventDestroy(s1);
         }
         if ((o->flags & SRMDP_F_CHECK_FINITE) && ctr[kCounterNonFinite] != 0)
             return fail(SRMDP_E_NUMERIC, "%llu non-finite coefficients", ctr[kCounterNonFinite]);
@@ -771,9 +786,9 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
         a.cv_packed = ws + lay.cv_packed;
         HIP_TRY(launch_mlp_pack(s.d + 1, s.q, o->cv_params, ws + lay.cv_packed, st), "network pack");
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    EventSet ev;
+    hipEvent_t &e0 = ev.e[0], &e1 = ev.e[1];
+    HIP_TRY(ev.create(2), "hipEventCreate");
     const int cand[6] = {8, 16, 32, 64, 128, 256};
     float best_ms = 0.f;
     *best = 0;
@@ -816,8 +831,6 @@ srmdp_status tune_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_
             best_ms = ms;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc == SRMDP_OK && *best == 0) rc = fail(SRMDP_E_UNSUPPORTED, "no lanes-per-stratum candidate fits");
     return rc;
 }
@@ -991,10 +1004,10 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 {
     srmdp_status rc = resolve_batch_lanes(n, P, G, O, tables, ws, bp, st);
     if (rc != SRMDP_OK) return rc;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventSet ev;
+    hipEvent_t &e0 = ev.e[0], &e1 = ev.e[1];
     if (stats) {
-        HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+        HIP_TRY(ev.create(2), "hipEventCreate");
         HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
     }
     if ((O[0].flags & SRMDP_F_GRAPH) && st != nullptr) {
@@ -1050,8 +1063,6 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         const int is_float = sizeof(R) == 4;
         for (int b = 0; b < n; ++b) {
             const Layout lay = layout(bp.shapes[b], bp.nb, is_float, bp.lk, &O[b]);
