@@ -342,6 +342,33 @@ srmdp_status srmdp_mlp_train(int32_t in, int32_t out, float *params, float *adam
                              const srmdp_mlp_train_config *cfg, void *packed_out, float *loss,
                              void *workspace, size_t ws_bytes, void *stream);
 
+/* Workspace bytes that srmdp_solve_noalloc serves: one library-owned device
+ * array of this size on each GPU the library runs on, held until the process
+ * ends. */
+#define SRMDP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* srmdp_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same sweep with the same kernels and the same table; its workspace is the
+ * library's own device array of SRMDP_NOALLOC_SCRATCH_BYTES on the current
+ * device instead of a caller buffer.  The caller still owns `table` (device,
+ * layout and precision as for srmdp_solve) and the stream (of the current
+ * device, NULL = null stream).
+ *  - Allocates nothing: no hipMalloc, hipFree, events or graphs.  The device
+ *    address of the array is resolved once per device, on the first call there.
+ *  - Asynchronous: no stats, never synchronises.  Rejects, before enqueuing
+ *    anything, SRMDP_F_GRAPH, SRMDP_F_CHECK_FINITE and SRMDP_F_AUTOTUNE with
+ *    lanes_per_cube == 0 (SRMDP_E_INVALID), and any request whose
+ *    srmdp_workspace_bytes exceeds SRMDP_NOALLOC_SCRATCH_BYTES
+ *    (SRMDP_E_WORKSPACE; e.g. d = 8, K = 4^8, N = 50 needs 262 MB of look-up
+ *    rows).  Other argument errors as srmdp_solve.
+ *  - Every call on a GPU uses that GPU's one array, which keeps the previous
+ *    call's contents; the sweep zeroes its counters (with a kernel) and
+ *    writes every other part before reading it.  Calls that overlap in time
+ *    on one GPU (two streams, two threads) race on the array: serialise them. */
+srmdp_status srmdp_solve_noalloc(const srmdp_problem *problem, const srmdp_grid *grid,
+                                 const srmdp_options *opts, void *table, void *stream);
+
 /* Releases cached hipGraph executables. */
 void srmdp_release_graphs(void);
 

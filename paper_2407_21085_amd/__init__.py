@@ -20,7 +20,7 @@ _BINDING_NAMES = frozenset((
     "GRID_EQUAL_PROB", "GRID_EQUAL_SIZE", "G_COS_SUM", "G_LOGISTIC", "LP0", "LP1", "Grid",
     "Options", "Problem", "SrmdpError", "TrainConfig", "cv_pairs", "draw", "evaluate",
     "mlp_backward", "mlp_forward", "mlp_init", "mlp_pack", "mlp_param_count", "mlp_train",
-    "release_graphs", "root", "solve", "solve_batch", "table_elems", "tune_lanes",
+    "release_graphs", "root", "solve", "solve_batch", "solve_noalloc", "table_elems", "tune_lanes",
     "workspace_bytes", "workspace_bytes_batch",
 ))
 

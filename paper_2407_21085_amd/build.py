@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 SOURCES = ["srmdp_kernels.hip", "srmdp_kernels_gr.hip", "srmdp_kernels_ep.hip", "srmdp_kernels_hd.hip",
            "srmdp_kernels_hd2.hip", "srmdp_kernels_hd3.hip",
-           "srmdp_cv.hip", "srmdp_batch.hip", "srmdp_host.cpp"]
+           "srmdp_cv.hip", "srmdp_batch.hip", "srmdp_noalloc.hip", "srmdp_host.cpp"]
 
 # Packed FP32 instructions are kept out of the device code on purpose: some
 # of their forms have produced wrong results on this hardware.

@@ -23,9 +23,9 @@
 
 using namespace srmdp;
 
-namespace {
+static thread_local std::string g_error;
 
-thread_local std::string g_error;
+namespace {
 
 srmdp_status fail(srmdp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 srmdp_status fail(srmdp_status s, const char *fmt, ...)
@@ -38,6 +38,21 @@ srmdp_status fail(srmdp_status s, const char *fmt, ...)
     g_error = buf;
     return s;
 }
+
+}  // namespace
+
+srmdp_status srmdp::set_error(srmdp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+namespace {
 
 srmdp_status hip_fail(hipError_t e, const char *what)
 {

@@ -6,9 +6,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/srmdp.h"
+
 namespace srmdp {
 
 constexpr int kMaxDim = 19;
+
+// Records the message returned by srmdp_last_error() on this thread (host
+// runtime, srmdp_host.cpp) and returns `s`.
+srmdp_status set_error(srmdp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // What a look-up row holds for each stratum: the y coefficients only (the
 // driver does not use z), y and the sum of the z_l coefficients (both built-in

@@ -90,7 +90,7 @@ EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_e
            "srmdp_mlp_packed_bytes", "srmdp_mlp_init", "srmdp_mlp_pack", "srmdp_mlp_forward",
            "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train_workspace_bytes",
            "srmdp_mlp_train",
-           "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
+           "srmdp_solve_noalloc", "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
 
 
 def _load():
@@ -121,6 +121,8 @@ def _load():
                              vp, vp]
     L.srmdp_draw.restype = ctypes.c_int
     i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.srmdp_solve_noalloc.argtypes = [P, G, O, vp, vp]
+    L.srmdp_solve_noalloc.restype = ctypes.c_int
     L.srmdp_tune_lanes.argtypes = [P, G, O, vp, vp, sz, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp]
     L.srmdp_tune_lanes.restype = ctypes.c_int
     L.srmdp_workspace_bytes_batch.argtypes = [i32, P, G, O]
@@ -346,6 +348,19 @@ def solve(problem: Problem, grid: Grid, opts: Options, table=None, workspace=Non
                "near_face_paths": int(st.near_face_paths),
                "cv_loss_first": float(st.cv_loss_first), "cv_loss_last": float(st.cv_loss_last)}
     return table, out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SRMDP_NOALLOC_SCRATCH_BYTES
+
+
+def solve_noalloc(problem: Problem, grid: Grid, opts: Options, table=None, stream=None):
+    """srmdp_solve_noalloc: the sweep with the library's own device scratch
+    array as workspace (no allocation by the library; asynchronous, no stats).
+    Returns the table (allocated here by torch only when none is given)."""
+    if table is None:
+        table = alloc_table(problem, grid, opts)
+    _check(lib.srmdp_solve_noalloc(problem.c(), grid.c(), opts.c(), table.data_ptr(), _stream_ptr(stream)))
+    return table
 
 
 def evaluate(problem: Problem, grid: Grid, basis: int, prec: int, table, i: int, x, stream=None):

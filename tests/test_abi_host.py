@@ -307,3 +307,39 @@ def test_equal_probability_grid_host_checks():
     n, Pa, Ga, Oa = S.srmdp._arrays(Pb, Gb, Ob)
     ptrs = (ctypes.c_void_p * n)(*([4096] * n))
     assert lib.srmdp_solve_batch(n, Pa, Ga, Oa, ptrs, 16, 1 << 40, None, None) == -1
+
+
+NOALLOC_BAD = [
+    ("graph", dict(flags=0x1), -1),
+    ("check finite", dict(flags=0x2), -1),
+    ("autotune without lanes", dict(flags=0x8), -1),
+]
+
+
+@pytest.mark.parametrize("name,okw,status", NOALLOC_BAD, ids=[b[0] for b in NOALLOC_BAD])
+def test_noalloc_refuses_what_allocates_or_synchronises(name, okw, status):
+    """srmdp_solve_noalloc refuses graphs, finiteness checks (they copy to the
+    host and synchronise) and autotuning before any HIP call."""
+    S = _S()
+    P = S.Problem(d=2, N=4)
+    G = S.Grid([-1.0] * 2, [1.0] * 2, [4, 4])
+    O = S.Options(M=16, **okw)
+    rc = S.srmdp.lib.srmdp_solve_noalloc(P.c(), G.c(), O.c(), 16, None)
+    assert rc == status
+    assert "srmdp_solve_noalloc" in S.srmdp.lib.srmdp_last_error().decode()
+
+
+def test_noalloc_refuses_a_workspace_beyond_its_scratch():
+    """The headline workload (d = 8, K = 4^8, N = 50) needs 262 MB of look-up
+    rows, more than the 64 MiB array: SRMDP_E_WORKSPACE before any HIP call."""
+    S = _S()
+    P = S.Problem(d=8, N=50, driver=S.DRV_LOGISTIC, terminal=S.G_LOGISTIC)
+    G = S.Grid([-3.0] * 8, [3.0] * 8, [4] * 8)
+    O = S.Options(M=64, prec=S.FP32)
+    assert S.workspace_bytes(P, G, O) > S.srmdp.NOALLOC_SCRATCH_BYTES
+    rc = S.srmdp.lib.srmdp_solve_noalloc(P.c(), G.c(), O.c(), 16, None)
+    assert rc == S.srmdp.E_WORKSPACE
+    assert "SRMDP_NOALLOC_SCRATCH_BYTES" in S.srmdp.lib.srmdp_last_error().decode()
+    header = open(os.path.join(ROOT, "include", "srmdp.h")).read()
+    assert re.search(r"#define SRMDP_NOALLOC_SCRATCH_BYTES \(\(size_t\)64 << 20\)", header)
+    assert S.srmdp.NOALLOC_SCRATCH_BYTES == 64 << 20
