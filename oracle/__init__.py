@@ -80,6 +80,11 @@ class _Problem(ctypes.Structure):
         ("b_lin", ctypes.POINTER(ctypes.c_double)),
         ("grid_kind", ctypes.c_int32),
         ("sigma_lin", ctypes.POINTER(ctypes.c_double)),
+        ("flip_bound", ctypes.POINTER(ctypes.c_double)),
+        ("face_flip", ctypes.c_int32),
+        ("debug_singular", ctypes.c_int32),
+        ("debug_singular_step", ctypes.c_int32),
+        ("debug_singular_stratum", ctypes.c_int64),
     ]
 
 
@@ -165,6 +170,11 @@ class Problem:
     z_center: int = 0
     grid_kind: int = GRID_EQUAL_SIZE
     sigma_lin: Optional[Sequence[float]] = None   # diffusion sigma + diag(sigma_lin) x
+    # test diagnostics: per-coefficient bound of a face flip (float64 [N, K, 1+q, nb]
+    # output), forced flips, and a Gram matrix zeroed at (step, stratum)
+    flip_bound: Optional[np.ndarray] = None
+    face_flip: int = 0
+    debug_singular: Optional[tuple] = None
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -224,6 +234,14 @@ class Problem:
         s.b_lin = _dp(blin) if blin is not None else None
         s.grid_kind = self.grid_kind
         s.sigma_lin = _dp(slin) if slin is not None else None
+        if self.flip_bound is not None:
+            fb = self.flip_bound
+            assert fb.dtype == np.float64 and fb.flags["C_CONTIGUOUS"] and fb.shape == self.table_shape()
+            s.flip_bound = _dp(fb)
+        s.face_flip = int(self.face_flip)
+        if self.debug_singular is not None:
+            s.debug_singular = 1
+            s.debug_singular_step, s.debug_singular_stratum = (int(v) for v in self.debug_singular)
         self._keep = keep
         return s
 

@@ -214,22 +214,34 @@ static int64_t cube_of(const grid_t *G, const double *x)
     return k;
 }
 
-/* Diagnostic: is x within eps cell widths of a face between two cells? */
-static int near_interior_face(const grid_t *G, const double *x, double eps)
-{
-    for (int l = 0; l < G->d; ++l) {
-        double t = cell_coord(G, l, x[l]);
-        double c = (double)cell_of(G, l, x[l]);
-        double frac = t - c;
-        if (frac < eps && c > 0.0 && t >= 0.0) return 1;
-        if (frac > 1.0 - eps && c < (double)(G->cells[l] - 1)) return 1;
-    }
-    return 0;
-}
-
 static int64_t cube_cell(const grid_t *G, int64_t k, int l)
 {
     return (k / G->stride[l]) % G->cells[l];
+}
+
+/* Cubes that a look-up at x may take when rounding moves a coordinate lying
+ * within eps cell widths of an interior face across it: the cube of x first,
+ * then the cubes across each such face, every combination (at most 8, i.e.
+ * three faces; a fourth near face in one point is ignored).  Returns the
+ * count. */
+static int candidate_cubes(const grid_t *G, const double *x, double eps, int64_t *cand)
+{
+    int n = 1;
+    cand[0] = cube_of(G, x);
+    for (int l = 0; l < G->d && n <= 4; ++l) {
+        double t = cell_coord(G, l, x[l]);
+        double c = (double)cell_of(G, l, x[l]);
+        double frac = t - c;
+        int64_t step = 0;
+        if (frac < eps && c > 0.0 && t >= 0.0)
+            step = -G->stride[l];
+        else if (frac > 1.0 - eps && c < (double)(G->cells[l] - 1))
+            step = G->stride[l];
+        if (step == 0) continue;
+        for (int a = 0; a < n; ++a) cand[n + a] = cand[a] + step;
+        n *= 2;
+    }
+    return n;
 }
 
 /* Basis of the local spaces of assumption (A_Strat): LP0 = {1}, LP1 =
@@ -538,13 +550,13 @@ int orc_path_normals(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, in
 /* ----------------------------------------------- fitted-table evaluation -- */
 
 /* y-component (c = 0) or z-component c = 1..q of the fitted function at
- * row j, evaluated at x (with the cell of x, extended past the domain). */
-static double fitted(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
-                     int c, const double *x)
+ * row j, evaluated at x with the record and basis of cube k (fitted: the cell
+ * of x, extended past the domain). */
+static double fitted_in(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
+                        int c, const double *x, int64_t k)
 {
     int nb = basis_size(P);
     double phi[65];
-    int64_t k = cube_of(G, x);
     basis_eval(P, G, k, x, phi);
     const double *rec = table + ((int64_t)j * G->K + k) * rec_size(P) + (int64_t)c * nb;
     double v = 0.0;
@@ -552,12 +564,10 @@ static double fitted(const orc_problem *P, const grid_t *G, const double *table,
     return clampv(v, c == 0 ? P->clamp_y : P->clamp_z);
 }
 
-/* y_{j}(x) of the sweep: g at j = N, the fitted row otherwise. */
-static double y_at(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
-                   const double *x)
+static double fitted(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
+                     int c, const double *x)
 {
-    if (j == P->N) return orc_terminal(P, x);
-    return fitted(P, G, table, j, 0, x);
+    return fitted_in(P, G, table, j, c, x, cube_of(G, x));
 }
 
 static void z_at(const orc_problem *P, const grid_t *G, const double *table, int32_t j,
@@ -580,6 +590,19 @@ int orc_eval(const orc_problem *P, const double *table, int32_t i, int64_t n, co
 
 /* ------------------------------------------------------- one simulation -- */
 
+/* Largest |f(t, x, y_a, z_b) - f0| over the candidate look-ups y_a, z_b. */
+static double driver_spread(const orc_problem *P, double t, const double *x, int ny,
+                            const double *yc, int nz, double zc[][64], double f0)
+{
+    double worst = 0.0;
+    for (int a = 0; a < ny; ++a)
+        for (int b = 0; b < nz; ++b) {
+            double v = fabs(orc_driver(P, t, x, yc[a], zc[b]) - f0);
+            if (v > worst) worst = v;
+        }
+    return worst;
+}
+
 /* Simulates one path from X_i (already in x0) to X_N with the Euler scheme and
  * returns what the regressions of step i need:
  *   dWi  -- the increment Delta W_i,
@@ -587,17 +610,31 @@ int orc_eval(const orc_problem *P, const double *table, int32_t i, int64_t n, co
  *           minus the control-variate terms sum_{j=i+1}^{N-1} z_theta(t_j,X_j).dW_j,
  *   *y1  -- y_{i+1}(X_{i+1}) (g(X_N) when i+1 = N),
  *   *cvi -- z_theta(t_i, X_i) . dW_i (zero without control variate).
- * Eq. (MDP:intro) and eq. (PsiM). */
+ * Eq. (MDP:intro) and eq. (PsiM).
+ *
+ * Diagnostics (test use only).  A point X_{j+1}, j+1 < N, whose coordinate
+ * lies within face_eps cell widths of an interior face sets *near; its y and z
+ * look-ups may then take the cube across that face in another precision.
+ * With flip (non-NULL) the path also returns flip[0] >= |change of S'| and
+ * flip[1] >= |change of y1| over every such choice: per step the largest
+ * change of f_j dt over the candidate cubes of its two look-ups.  With
+ * P->face_flip every such point takes the first cube across its face (the
+ * forced-flip run that pins the bound). */
 static void simulate(const orc_problem *P, const grid_t *G, const double *table, int32_t i,
                      path_stream *s, const double *x0, double *dWi, double *Sp, double *y1,
-                     double *cvi, int *near)
+                     double *cvi, int *near, double *flip)
 {
     const int d = P->d, q = P->q;
     const double dt = P->T / P->N, sdt = sqrt(dt);
     const int stride = P->cv_stride > 1 ? P->cv_stride : 1;
-    double x[64], xn[64], dW[64], z[64], zcv[64];
+    const int track = near || flip || P->face_flip;
+    double x[64], xn[64], dW[64], zcv[64];
+    /* z candidates at X_j for row j (zc[zuse] is the look-up the path takes),
+     * computed when X_j is reached, i.e. at step j - 1 */
+    double zc[8][64], zn[8][64], yc[8];
+    int nzc = 0, zuse = 0;
     memcpy(x, x0, sizeof(double) * d);
-    double S = 0.0, cv_tail = 0.0;
+    double S = 0.0, cv_tail = 0.0, dS = 0.0, dy1 = 0.0;
     *cvi = 0.0;
     for (int32_t j = i; j < P->N; ++j) {
         for (int l = 0; l < q; ++l)
@@ -612,8 +649,25 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
             if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];
             xn[l] = x[l] + drift * dt + diff;
         }
-        double ynext = y_at(P, G, table, j + 1, xn);
-        if (near && j + 1 < P->N && near_interior_face(G, xn, P->face_eps)) *near = 1;
+        double ynext;
+        int nyc = 1, use = 0;
+        if (j + 1 < P->N) {
+            int64_t cand[8];
+            if (track) {
+                nyc = candidate_cubes(G, xn, P->face_eps, cand);
+            } else {
+                cand[0] = cube_of(G, xn);
+            }
+            if (P->face_flip && nyc > 1) use = 1;
+            if (near && nyc > 1) *near = 1;
+            for (int a = 0; a < nyc; ++a) {
+                yc[a] = fitted_in(P, G, table, j + 1, 0, xn, cand[a]);
+                for (int l = 0; l < q; ++l) zn[a][l] = fitted_in(P, G, table, j + 1, 1 + l, xn, cand[a]);
+            }
+            ynext = yc[use];
+        } else {
+            ynext = yc[0] = orc_terminal(P, xn);
+        }
         double cv = 0.0;
         if (P->cv_params) {
             if ((j - i) % stride == 0) cv_net(P, j * dt, x, zcv);
@@ -623,14 +677,26 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
             memcpy(dWi, dW, sizeof(double) * q);
             *y1 = ynext;
             *cvi = cv;
+            for (int a = 0; a < nyc; ++a)
+                if (fabs(yc[a] - ynext) > dy1) dy1 = fabs(yc[a] - ynext);
         } else {
-            z_at(P, G, table, j, x, z);
-            S += orc_driver(P, j * dt, x, ynext, z) * dt;
+            double f0 = orc_driver(P, j * dt, x, ynext, zc[zuse]);
+            S += f0 * dt;
             cv_tail += cv;
+            if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt;
+        }
+        if (j + 1 < P->N) {
+            memcpy(zc, zn, sizeof(double) * 64 * (size_t)nyc);
+            nzc = nyc;
+            zuse = use;
         }
         memcpy(x, xn, sizeof(double) * d);
     }
     *Sp = orc_terminal(P, x) + S - cv_tail;
+    if (flip) {
+        flip[0] = dS;
+        flip[1] = dy1;
+    }
 }
 
 /* ----------------------------------------------------- least squares -- */
@@ -673,35 +739,67 @@ static void chol_solve(int n, const double *L, const double *rhs, double *beta)
 
 /* ----------------------------------------------- one stratum at step i -- */
 
+/* The cloud C_{i,k}; flip (NULL or [2M]) receives each simulation's bounds of
+ * simulate(). */
+static void cloud(const orc_problem *P, const grid_t *G, const double *table, int32_t i, int64_t k,
+                  double *Xi, double *dWi, double *Sp, double *y1, double *cvi, double *flip)
+{
+    int near = 0;
+    int *np = P->face_flags ? &near : NULL;
+    for (int32_t m = 0; m < P->M; ++m) {
+        path_stream s;
+        stream_init(&s, P->seed, P->inst, i, (uint32_t)k, (uint32_t)m);
+        start_point(P, G, &s, k, Xi + (int64_t)m * P->d);
+        simulate(P, G, table, i, &s, Xi + (int64_t)m * P->d, dWi + (int64_t)m * P->q, Sp + m, y1 + m,
+                 cvi + m, np, flip ? flip + 2 * (int64_t)m : NULL);
+    }
+    if (P->face_flags) P->face_flags[(int64_t)i * G->K + k] = (uint8_t)near;
+}
+
 int orc_cloud(const orc_problem *P, const double *table, int32_t i, uint32_t k, double *Xi,
               double *dWi, double *Sp, double *y1, double *cvi)
 {
     grid_t G;
     if (check_problem(P, &G) != 0 || i < 0 || i >= P->N || (int64_t)k >= G.K) return -1;
-    int near = 0;
-    for (int32_t m = 0; m < P->M; ++m) {
-        path_stream s;
-        stream_init(&s, P->seed, P->inst, i, k, (uint32_t)m);
-        start_point(P, &G, &s, k, Xi + (int64_t)m * P->d);
-        simulate(P, &G, table, i, &s, Xi + (int64_t)m * P->d, dWi + (int64_t)m * P->q, Sp + m,
-                 y1 + m, cvi + m, &near);
-    }
-    if (P->face_flags) P->face_flags[(int64_t)i * G.K + k] = (uint8_t)near;
+    cloud(P, &G, table, i, (int64_t)k, Xi, dWi, Sp, y1, cvi, NULL);
     return 0;
+}
+
+/* Bound on |f(t, x, y', z') - f(t, x, y, z)| over |y' - y| <= dy and
+ * |z'_l - z_l| <= dz_l (test diagnostic of the face-flip bound). */
+static double driver_change_bound(const orc_problem *P, double y, const double *z, double dy,
+                                  const double *dz)
+{
+    double sz = 0.0, sdz = 0.0;
+    for (int l = 0; l < P->q; ++l) {
+        sz += z[l];
+        sdz += dz[l];
+    }
+    if (P->driver == ORC_DRV_LOGISTIC) {
+        double c = (2.0 + P->q) / (2.0 * P->q);
+        return sdz * (fabs(y - c) + dy) + fabs(sz) * dy;
+    }
+    return fabs(P->r) * dy + fabs(P->kappa) * sdz;
 }
 
 /* Algorithm SRMDP, one stratum k at step i: the cloud C_{i,k}, then the z
  * regression of S' dW_i / dt, then the y regression of
  * S_Y = S' + f_i(X_i, y_{i+1}(X_{i+1}), z_i(X_i)) dt, both on the local basis.
- * Writes row i, stratum k of the table; returns 1 if the Gram was singular. */
+ * Writes row i, stratum k of the table; returns 1 if the Gram was singular.
+ *
+ * Test diagnostics: debug_singular zeroes the Gram of one (step, stratum),
+ * which then takes the LP0 fallback; flip_bound receives, per coefficient, a
+ * bound on its change when near-face look-ups take the cube across the face
+ * (Delta beta = G^-1 sum_m phi_m Delta resp_m, bounded term by term). */
 static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int32_t i, int64_t k,
                        double *work)
 {
     const int d = P->d, q = P->q, nb = basis_size(P), M = P->M;
     const double dt = P->T / P->N;
     double *Xi = work, *dWi = Xi + (int64_t)M * d, *Sp = dWi + (int64_t)M * q, *y1 = Sp + M,
-           *cvi = y1 + M;
-    orc_cloud(P, table, i, (uint32_t)k, Xi, dWi, Sp, y1, cvi);
+           *cvi = y1 + M, *cz = cvi + M, *flip = cz + M, *dcz = flip + 2 * (int64_t)M;
+    double *fb = P->flip_bound ? P->flip_bound + ((int64_t)i * G->K + k) * rec_size(P) : NULL;
+    cloud(P, G, table, i, k, Xi, dWi, Sp, y1, cvi, fb ? flip : NULL);
 
     double Gm[65 * 65], L[65 * 65], phi[65], rhs[65], beta[65], zfit[64];
     double *rec = table + ((int64_t)i * G->K + k) * rec_size(P);
@@ -712,15 +810,32 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
         for (int a = 0; a < nb; ++a)
             for (int c = 0; c < nb; ++c) Gm[a * nb + c] += phi[a] * phi[c];
     }
+    if (P->debug_singular && i == P->debug_singular_step && k == P->debug_singular_stratum)
+        memset(Gm, 0, sizeof(Gm));
     for (int a = 0; a < nb; ++a) trace += Gm[a * nb + a];
     int singular = cholesky(nb, Gm, L, 1e-12 * trace);
 
     /* z first: q scalar regressions sharing the Gram matrix.  With z_center the
      * response loses y_{i+1}(X_i) dW_i / dt, whose conditional mean given X_i is
      * zero (y_{i+1} comes from clouds of later steps). */
-    double *cz = cvi + M;
-    for (int m = 0; m < M; ++m)
-        cz[m] = P->z_center ? y_at(P, G, table, i + 1, Xi + (int64_t)m * d) : 0.0;
+    for (int m = 0; m < M; ++m) {
+        const double *x = Xi + (int64_t)m * d;
+        cz[m] = 0.0;
+        dcz[m] = 0.0;
+        if (!P->z_center) continue;
+        if (i + 1 == P->N) {
+            cz[m] = orc_terminal(P, x);
+            continue;
+        }
+        int64_t cand[8];
+        int nc = candidate_cubes(G, x, P->face_eps, cand);
+        if (P->face_flags && nc > 1) P->face_flags[(int64_t)i * G->K + k] = 1;
+        cz[m] = fitted_in(P, G, table, i + 1, 0, x, cand[P->face_flip && nc > 1 ? 1 : 0]);
+        for (int a = 0; a < nc; ++a) {
+            double v = fabs(fitted_in(P, G, table, i + 1, 0, x, cand[a]) - cz[m]);
+            if (v > dcz[m]) dcz[m] = v;
+        }
+    }
     for (int l = 0; l < q; ++l) {
         memset(rhs, 0, sizeof(rhs));
         for (int m = 0; m < M; ++m) {
@@ -756,6 +871,49 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
         beta[0] = rhs[0] / M;
     }
     for (int a = 0; a < nb; ++a) rec[a] = beta[a];
+
+    if (fb) {
+        /* leverage w_m = G^-1 phi_m of each sample (the LP0 mean when singular) */
+        double bz[64][65], dz[64], w[65];
+        memset(bz, 0, sizeof(bz));
+        memset(fb, 0, sizeof(double) * (size_t)rec_size(P));
+        for (int m = 0; m < M; ++m) {
+            basis_eval(P, G, k, Xi + (int64_t)m * d, phi);
+            if (!singular) {
+                chol_solve(nb, L, phi, w);
+            } else {
+                memset(w, 0, sizeof(w));
+                w[0] = 1.0 / M;
+            }
+            for (int l = 0; l < q; ++l) {
+                double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;
+                for (int a = 0; a < nb; ++a) bz[l][a] += fabs(w[a]) * dr;
+            }
+        }
+        for (int m = 0; m < M; ++m) {
+            const double *x = Xi + (int64_t)m * d;
+            basis_eval(P, G, k, x, phi);
+            for (int l = 0; l < q; ++l) {
+                double v = 0.0;
+                dz[l] = 0.0;
+                for (int a = 0; a < nb; ++a) {
+                    v += rec[(1 + l) * nb + a] * phi[a];
+                    dz[l] += bz[l][a] * fabs(phi[a]);
+                }
+                zfit[l] = clampv(v, P->clamp_z);
+            }
+            double dSY = flip[2 * m] + driver_change_bound(P, y1[m], zfit, flip[2 * m + 1], dz) * dt;
+            if (!singular) {
+                chol_solve(nb, L, phi, w);
+            } else {
+                memset(w, 0, sizeof(w));
+                w[0] = 1.0 / M;
+            }
+            for (int a = 0; a < nb; ++a) fb[a] += fabs(w[a]) * dSY;
+        }
+        for (int l = 0; l < q; ++l)
+            for (int a = 0; a < nb; ++a) fb[(1 + l) * nb + a] = bz[l][a];
+    }
     return singular;
 }
 
@@ -767,7 +925,7 @@ int orc_solve(const orc_problem *P, double *table, int32_t i_hi, int32_t i_lo, i
     if (i_hi >= P->N || i_lo < 0 || i_lo > i_hi) return -1;
     if (P->d > 64 || basis_size(P) > 65) return -1;
     int64_t nsing = 0;
-    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 4);
+    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 7);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #else
@@ -807,7 +965,7 @@ int orc_root(const orc_problem *P, const double *table, const double *x0, int32_
     for (int32_t m = 0; m < M_root; ++m) {
         path_stream s;
         stream_init(&s, P->seed, P->inst, 0, 0xFFFFFFFFu, (uint32_t)m);
-        simulate(P, &G, table, 0, &s, x0, dW + (int64_t)m * q, Sp + m, y1 + m, cvi + m, NULL);
+        simulate(P, &G, table, 0, &s, x0, dW + (int64_t)m * q, Sp + m, y1 + m, cvi + m, NULL, NULL);
         for (int l = 0; l < q; ++l) z0[l] += Sp[m] * dW[(int64_t)m * q + l] / dt;
     }
     for (int l = 0; l < q; ++l) z0[l] /= M_root;

@@ -72,6 +72,21 @@ typedef struct {
     /* [d] diagonal part of the diffusion linear in the state,
      * sigma(x)_{l,c} = sigma_{l,c} + [l = c] sigma_lin_l x_l (q = d), or NULL */
     const double *sigma_lin;
+    /* Test diagnostics.
+     * flip_bound [N*K*(1+q)*nb] or NULL: per coefficient of each fitted
+     * stratum, a bound on its change if near-face look-ups (those that set
+     * face_flags) took the cube across their face, as rounding in another
+     * precision may make them do.
+     * face_flip: near-face look-ups take the first cube across their face
+     * (the run that pins flip_bound).
+     * debug_singular: the Gram matrix of stratum debug_singular_stratum at
+     * step debug_singular_step is replaced by zero, so that the stratum takes
+     * the LP0 fallback of a singular Gram. */
+    double *flip_bound;
+    int32_t face_flip;
+    int32_t debug_singular;
+    int32_t debug_singular_step;
+    int64_t debug_singular_stratum;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */

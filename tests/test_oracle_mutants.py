@@ -10,6 +10,7 @@ import pytest
 import oracle as O
 import test_oracle_closed_form as CF
 import test_oracle_equal_prob as EP
+import test_oracle_flip_bound as FB
 import test_oracle_regression as RG
 import test_oracle_rng as RN
 
@@ -29,8 +30,8 @@ MUTANTS = [
      "double SY = Sp[m] - cvi[m];",
      CF.test_coupled_driver_matches_discrete_closed_form),
     ("driver uses y_j(X_j) instead of y_{j+1}(X_{j+1})",
-     "S += orc_driver(P, j * dt, x, ynext, z) * dt;",
-     "S += orc_driver(P, j * dt, x, y_at(P, G, table, j, x), z) * dt;",
+     "double f0 = orc_driver(P, j * dt, x, ynext, zc[zuse]);",
+     "double f0 = orc_driver(P, j * dt, x, fitted(P, G, table, j, 0, x), zc[zuse]);",
      CF.test_coupled_driver_matches_discrete_closed_form),
     ("sign of the kappa term",
      "return -P->r * y + P->kappa * sz;",
@@ -96,6 +97,18 @@ MUTANTS = [
      "if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[d - 1 - l];",
      lambda: CF.test_state_dependent_diffusion_fits_match_projection_of_closed_form(2, [4, 4], 12000,
                                                                                     [0.5, -0.8])),
+    ("face-flip bound of z without the 1/dt of its response",
+     "double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;",
+     "double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]);",
+     lambda: FB.test_flip_bound_holds_against_forced_flips(*FB.CASES[0])),
+    ("face-flip bound of a path without the dt of its driver terms",
+     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt;",
+     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0);",
+     lambda: FB.test_flip_bound_holds_against_forced_flips(*FB.CASES[0])),
+    ("singular fallback divides by M - 1",
+     "beta[0] = rhs[0] / M;\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
+     "beta[0] = rhs[0] / (M - 1);\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
+     lambda: FB.test_singular_gram_takes_the_lp0_mean(O.LP1, O.DRV_LOGISTIC)),
     ("Philox key bump skipped",
      "k0 += weyl0;",
      "k0 += 0u;",
