@@ -163,6 +163,11 @@ typedef struct {
 #define SRMDP_F_GLOBAL_ROWS  0x10u /* keep every stratum's cloud in global memory (see
                                     * global_rows_strata); automatic, without the control
                                     * variate, when a cloud does not fit in 64 KB of LDS */
+#define SRMDP_F_DEBUG_SINGULAR 0x20u /* test aid: the Gram matrix of stratum debug_stratum at
+                                      * step debug_step is replaced by zero, so that this
+                                      * stratum takes the LP0 fallback of a singular Gram
+                                      * (explicit LP0 solution, Section 4.1) and is counted
+                                      * in srmdp_stats.singular_cubes; srmdp_solve only */
 
 typedef struct {
     int32_t M;              /* simulations per stratum, >= nb (Definition of the clouds) */
@@ -192,6 +197,8 @@ typedef struct {
                                  * multiple of 8); 0 = as many as 2 GiB of rows hold.  The
                                  * workspace then holds that many clouds (M rows of
                                  * nb + d + 2 values, plus binary64 chunk sums, each) */
+    int32_t debug_step;     /* SRMDP_F_DEBUG_SINGULAR: step and stratum of the zeroed Gram */
+    uint32_t debug_stratum;
 } srmdp_options;
 
 typedef struct {

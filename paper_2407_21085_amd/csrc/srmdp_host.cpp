@@ -166,8 +166,12 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     if (L != 0 && L != 8 && L != 16 && L != 32 && L != 64 && L != 128 && L != 256)
         return fail(SRMDP_E_INVALID, "lanes_per_cube must be 0, 8, 16, 32, 64, 128 or 256");
     if (o->flags & ~(uint32_t)(SRMDP_F_GRAPH | SRMDP_F_CHECK_FINITE | SRMDP_F_CV_CENTER_Z | SRMDP_F_AUTOTUNE |
-                               SRMDP_F_GLOBAL_ROWS))
+                               SRMDP_F_GLOBAL_ROWS | SRMDP_F_DEBUG_SINGULAR))
         return fail(SRMDP_E_INVALID, "unknown flag bits");
+    if ((o->flags & SRMDP_F_DEBUG_SINGULAR) &&
+        (o->debug_step < 0 || o->debug_step >= s.N || (uint64_t)o->debug_stratum >= s.K))
+        return fail(SRMDP_E_INVALID, "SRMDP_F_DEBUG_SINGULAR: step %d or stratum %u outside the grid", o->debug_step,
+                    o->debug_stratum);
     if (o->global_rows_strata < 0) return fail(SRMDP_E_INVALID, "global_rows_strata < 0");
     if ((o->flags & SRMDP_F_GLOBAL_ROWS) && o->cv != SRMDP_CV_NONE)
         return fail(SRMDP_E_UNSUPPORTED, "global cloud rows run without the control variate");
@@ -278,6 +282,7 @@ void fill_step_args(StepArgs<R> &a, const srmdp_problem *p, const srmdp_grid *g,
                     const srmdp_options *o)
 {
     std::memset(&a, 0, sizeof a);
+    a.debug_singular = 0xFFFFFFFFu;
     uint32_t stride = 1;
     for (int l = 0; l < s.d; ++l) {
         if (g->kind == SRMDP_GRID_EQUAL_PROB) {
@@ -555,6 +560,8 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
     for (int i = hi; i >= lo; --i) {
         a.i = i;
         a.tag = ((uint32_t)i & 0xFFFFu) | (o->instance << 16);
+        a.debug_singular =
+            (o->flags & SRMDP_F_DEBUG_SINGULAR) && i == o->debug_step ? o->debug_stratum : 0xFFFFFFFFu;
         bool launched = false;
         if constexpr (std::is_same<R, float>::value) {
             if (cv) {
@@ -908,7 +915,8 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
             return fail(SRMDP_E_INVALID, "instance %d: a batch shares d, basis, precision, look-up mode and grid kind",
                         b);
         }
-        if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0)
+        if (O[b].cv != SRMDP_CV_NONE || O[b].face_flags || O[b].step_hi >= 0 || O[b].step_lo >= 0 ||
+            (O[b].flags & SRMDP_F_DEBUG_SINGULAR))
             return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches run plain full sweeps", b);
         bp.gmax = std::max(bp.gmax, P[b].N);
     }
@@ -1101,7 +1109,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 106; }
+int32_t srmdp_abi_version(void) { return 107; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 

@@ -76,6 +76,7 @@ struct StepArgs {
     unsigned char *grows;
     size_t grow_bytes;
     int stage_chunks;  // chunks of rows per LDS window of the sums
+    uint32_t debug_singular;  // stratum whose Gram is zeroed in this launch (test aid), or ~0u
 };
 
 // Arguments of the set-up kernel (cell constants and the coefficient block

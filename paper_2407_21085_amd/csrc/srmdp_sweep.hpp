@@ -599,8 +599,9 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                 ++r;
             }
             const int c = r + rem;
-            G[r * NB + c] = acc;
-            G[c * NB + r] = acc;
+            const double g = k == a.debug_singular ? 0.0 : acc;
+            G[r * NB + c] = g;
+            G[c * NB + r] = g;
         } else {
             const int l = (e - NG) / NB, b = (e - NG) % NB;
             RHS[(1 + l) * NB + b] = acc * a.inv_dt;

@@ -21,6 +21,7 @@ FP64, FP32 = 0, 1
 DRV_LINEAR, DRV_LOGISTIC = 0, 1
 G_COS_SUM, G_LOGISTIC = 0, 1
 F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z, F_AUTOTUNE, F_GLOBAL_ROWS = 0x1, 0x2, 0x4, 0x8, 0x10
+F_DEBUG_SINGULAR = 0x20
 GRID_EQUAL_SIZE, GRID_EQUAL_PROB = 0, 1
 CV_NONE, CV_FROZEN, CV_ONLINE = 0, 1, 2
 MAX_D = 16
@@ -71,6 +72,7 @@ class _Options(ctypes.Structure):
         ("face_flags", ctypes.c_void_p), ("face_eps", ctypes.c_double),
         ("cv", ctypes.c_int32), ("cv_params", ctypes.c_void_p), ("cv_train", _TrainConfig),
         ("cv_stride", ctypes.c_int32), ("global_rows_strata", ctypes.c_int32),
+        ("debug_step", ctypes.c_int32), ("debug_stratum", ctypes.c_uint32),
     ]
 
 
@@ -278,13 +280,16 @@ class Options:
     cv_train: TrainConfig = field(default_factory=TrainConfig)
     cv_stride: int = 1
     global_rows_strata: int = 0
+    debug_step: int = 0         # F_DEBUG_SINGULAR: step and stratum of the zeroed Gram
+    debug_stratum: int = 0
 
     def c(self) -> _Options:
         ptr = self.face_flags.data_ptr() if self.face_flags is not None else None
         cvp = self.cv_params.data_ptr() if self.cv_params is not None else None
         return _Options(self.M, self.basis, self.prec, self.seed, self.instance, self.step_hi,
                         self.step_lo, self.lanes_per_cube, self.flags, ptr, self.face_eps,
-                        self.cv, cvp, self.cv_train.c(), self.cv_stride, self.global_rows_strata)
+                        self.cv, cvp, self.cv_train.c(), self.cv_stride, self.global_rows_strata,
+                        self.debug_step, self.debug_stratum)
 
 
 def table_elems(problem: Problem, grid: Grid, basis: int) -> int:

@@ -22,7 +22,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 106
+    assert S.srmdp.lib.srmdp_abi_version() == 107
 
 
 def test_table_elems_and_paper_sizes():
@@ -71,6 +71,8 @@ BAD = [
     ("steps reversed", dict(), dict(step_hi=2, step_lo=5)),
     ("instance too large", dict(), dict(instance=70000)),
     ("unknown flags", dict(), dict(flags=0x80)),
+    ("debug stratum outside the grid", dict(), dict(flags=0x20, debug_step=3, debug_stratum=8)),
+    ("debug step outside the sweep", dict(), dict(flags=0x20, debug_step=10, debug_stratum=0)),
 ]
 
 

@@ -60,10 +60,10 @@ def test_large_cloud_fp32_per_step_parity():
     their share grows with the look-ups per stratum (M (N - i) of them: 8.6 %
     observed here, against about 3 % at M = 128)."""
     cfg = dict(W.config("cfg2"), name="logistic d=4 K=3^4 M=3000 N=4 LP1 fp32", N=4, cells=[3] * 4, M=3000)
-    err, err_flagged, share = TP.fp32_step_parity(cfg, [3, 2, 0])
+    err, excess, share = TP.fp32_step_parity(cfg, [3, 2, 0])
     assert err <= TP.TOL["fp32"]
     assert share < 0.25
-    assert err_flagged < 0.05
+    assert excess <= 0.0
 
 
 def test_global_rows_graph_replays():
