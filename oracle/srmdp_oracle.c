@@ -361,8 +361,47 @@ static double maybe_bf16(double v, int on) { return on ? bf16_round(v) : v; }
  * pre-activations a1, a2 and the (possibly rounded) layer inputs h1, h2 are
  * returned.  `bf` selects the values rounded to bfloat16: weights (biases are
  * kept), the input vector, the hidden activations fed to the next layer. */
-static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
-                       double *y, double *a1, double *a2, double *h1, double *h2, int bf)
+/* The other bfloat16 neighbour of (float)v: the one round-to-nearest did not
+ * pick (the two values bracketing v in the 8-bit significand). */
+static double bf16_other(double v)
+{
+    float f = (float)v, r = (float)bf16_round(v);
+    uint32_t u, ur;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return v;
+    memcpy(&ur, &r, 4);
+    const uint32_t down = u & 0xFFFF0000u, other = ur == down ? down + 0x10000u : down;
+    memcpy(&f, &other, 4);
+    return (double)f;
+}
+
+/* Binary32 units around a bfloat16 rounding midpoint within which the
+ * flip-bound diagnostic treats a hidden activation as ambiguous. */
+#define ORC_BF16_FLIP_ULPS 32
+
+/* Is (float)v within `ulps` binary32 units of a bfloat16 rounding midpoint
+ * (where another rounding of the same value may take the other neighbour)? */
+static int bf16_near_midpoint(double v, int ulps)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return 0;
+    int low = (int)(u & 0xFFFFu);
+    return abs(low - 0x8000) <= ulps;
+}
+
+/* One sample through in -> H -> H -> out with SiLU after both hidden layers;
+ * pre-activations a1, a2 and the (possibly rounded) layer inputs h1, h2 are
+ * returned.  `bf` selects the values rounded to bfloat16: weights (biases are
+ * kept), the input vector, the hidden activations fed to the next layer.
+ * flip_layer 1 or 2 rounds hidden unit flip_unit of that layer to its other
+ * bfloat16 neighbour, 3 rounds every ambiguous hidden activation (within
+ * ORC_BF16_FLIP_ULPS of a midpoint) to its other neighbour (the flip-bound
+ * diagnostic and its forced run); 0 flips nothing. */
+static void mlp_one_flip(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
+                         double *y, double *a1, double *a2, double *h1, double *h2, int bf,
+                         int flip_layer, int flip_unit)
 {
     const double *W1 = p, *b1 = W1 + (int64_t)H * in, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H,
                  *W3 = b2 + H, *b3 = W3 + (int64_t)out * H;
@@ -372,13 +411,17 @@ static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, cons
         for (int c = 0; c < in; ++c)
             s += maybe_bf16(W1[(int64_t)a * in + c], rw) * input_value(x[c], bf);
         a1[a] = s;
-        h1[a] = maybe_bf16(silu(s), rh);
+        const int f1 = (flip_layer == 1 && a == flip_unit) ||
+                       (flip_layer == 3 && bf16_near_midpoint(silu(s), ORC_BF16_FLIP_ULPS));
+        h1[a] = f1 ? bf16_other(silu(s)) : maybe_bf16(silu(s), rh);
     }
     for (int a = 0; a < H; ++a) {
         double s = b2[a];
         for (int c = 0; c < H; ++c) s += maybe_bf16(W2[(int64_t)a * H + c], rw) * h1[c];
         a2[a] = s;
-        h2[a] = maybe_bf16(silu(s), rh);
+        const int f2 = (flip_layer == 2 && a == flip_unit) ||
+                       (flip_layer == 3 && bf16_near_midpoint(silu(s), ORC_BF16_FLIP_ULPS));
+        h2[a] = f2 ? bf16_other(silu(s)) : maybe_bf16(silu(s), rh);
     }
     for (int o = 0; o < out; ++o) {
         double s = b3[o];
@@ -387,10 +430,10 @@ static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, cons
     }
 }
 
-static void mlp_one(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
-                    double *y, double *a1, double *a2, double *h1, double *h2)
+static void mlp_one_bf(int32_t in, int32_t H, int32_t out, const double *p, const double *x,
+                       double *y, double *a1, double *a2, double *h1, double *h2, int bf)
 {
-    mlp_one_bf(in, H, out, p, x, y, a1, a2, h1, h2, 0);
+    mlp_one_flip(in, H, out, p, x, y, a1, a2, h1, h2, bf, 0, 0);
 }
 
 void orc_mlp_forward_bf(int32_t in, int32_t H, int32_t out, const double *params, const double *x,
@@ -468,13 +511,29 @@ void orc_mlp_backward(int32_t in, int32_t H, int32_t out, const double *params, 
 }
 
 /* The frozen network z_theta(t, x) (q values). */
-static void cv_net(const orc_problem *P, double t, const double *x, double *z)
+/* z_theta(t, x).  With dz (non-NULL, bfloat16 hidden activations), dz[l]
+ * receives the sum over the ambiguous hidden activations of the change of
+ * output l when that activation is rounded to its other neighbour. */
+static void cv_net(const orc_problem *P, double t, const double *x, double *z, double *dz)
 {
-    double inp[65], buf[4 * 256];
+    const int H = P->cv_hidden;
+    double inp[65], buf[4 * 256], alt[64], tmp[4 * 256];
     inp[0] = t;
     for (int l = 0; l < P->d; ++l) inp[1 + l] = x[l];
-    mlp_one_bf(P->d + 1, P->cv_hidden, P->q, P->cv_params, inp, z, buf, buf + P->cv_hidden,
-               buf + 2 * P->cv_hidden, buf + 3 * P->cv_hidden, P->cv_bf16);
+    const int forced = P->face_flip && (P->cv_bf16 & ORC_BF_HIDDEN) ? 3 : 0;
+    mlp_one_flip(P->d + 1, H, P->q, P->cv_params, inp, z, buf, buf + H, buf + 2 * H, buf + 3 * H, P->cv_bf16,
+                 forced, 0);
+    if (!dz) return;
+    for (int l = 0; l < P->q; ++l) dz[l] = 0.0;
+    if (!(P->cv_bf16 & ORC_BF_HIDDEN)) return;
+    for (int layer = 1; layer <= 2; ++layer)
+        for (int a = 0; a < H; ++a) {
+            double pre = buf[(layer - 1) * H + a];
+            if (!bf16_near_midpoint(silu(pre), ORC_BF16_FLIP_ULPS)) continue;
+            mlp_one_flip(P->d + 1, H, P->q, P->cv_params, inp, alt, tmp, tmp + H, tmp + 2 * H, tmp + 3 * H,
+                         P->cv_bf16, layer, a);
+            for (int l = 0; l < P->q; ++l) dz[l] += fabs(alt[l] - z[l]);
+        }
 }
 
 /* -------------------------------------------------------- validation -- */
@@ -615,9 +674,11 @@ static double driver_spread(const orc_problem *P, double t, const double *x, int
  * Diagnostics (test use only).  A point X_{j+1}, j+1 < N, whose coordinate
  * lies within face_eps cell widths of an interior face sets *near; its y and z
  * look-ups may then take the cube across that face in another precision.
- * With flip (non-NULL) the path also returns flip[0] >= |change of S'| and
- * flip[1] >= |change of y1| over every such choice: per step the largest
- * change of f_j dt over the candidate cubes of its two look-ups.  With
+ * With flip (non-NULL) the path also returns flip[0] >= |change of S'|,
+ * flip[1] >= |change of y1| and flip[2] >= |change of cvi| over every such
+ * choice: per step the largest change of f_j dt over the candidate cubes of
+ * its two look-ups, plus, with a bfloat16 network, the change of its
+ * z_theta . dW_j term when ambiguous hidden roundings go the other way.  With
  * P->face_flip every such point takes the first cube across its face (the
  * forced-flip run that pins the bound). */
 static void simulate(const orc_problem *P, const grid_t *G, const double *table, int32_t i,
@@ -628,13 +689,13 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
     const double dt = P->T / P->N, sdt = sqrt(dt);
     const int stride = P->cv_stride > 1 ? P->cv_stride : 1;
     const int track = near || flip || P->face_flip;
-    double x[64], xn[64], dW[64], zcv[64];
+    double x[64], xn[64], dW[64], zcv[64], dzcv[64];
     /* z candidates at X_j for row j (zc[zuse] is the look-up the path takes),
      * computed when X_j is reached, i.e. at step j - 1 */
     double zc[8][64], zn[8][64], yc[8];
     int nzc = 0, zuse = 0;
     memcpy(x, x0, sizeof(double) * d);
-    double S = 0.0, cv_tail = 0.0, dS = 0.0, dy1 = 0.0;
+    double S = 0.0, cv_tail = 0.0, dS = 0.0, dy1 = 0.0, dcvi = 0.0;
     *cvi = 0.0;
     for (int32_t j = i; j < P->N; ++j) {
         for (int l = 0; l < q; ++l)
@@ -668,22 +729,25 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
         } else {
             ynext = yc[0] = orc_terminal(P, xn);
         }
-        double cv = 0.0;
+        double cv = 0.0, dcv = 0.0;
         if (P->cv_params) {
-            if ((j - i) % stride == 0) cv_net(P, j * dt, x, zcv);
+            if ((j - i) % stride == 0) cv_net(P, j * dt, x, zcv, flip ? dzcv : NULL);
             for (int l = 0; l < q; ++l) cv += zcv[l] * dW[l];
+            if (flip)
+                for (int l = 0; l < q; ++l) dcv += dzcv[l] * fabs(dW[l]);
         }
         if (j == i) {
             memcpy(dWi, dW, sizeof(double) * q);
             *y1 = ynext;
             *cvi = cv;
+            dcvi = dcv;
             for (int a = 0; a < nyc; ++a)
                 if (fabs(yc[a] - ynext) > dy1) dy1 = fabs(yc[a] - ynext);
         } else {
             double f0 = orc_driver(P, j * dt, x, ynext, zc[zuse]);
             S += f0 * dt;
             cv_tail += cv;
-            if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt;
+            if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt + dcv;
         }
         if (j + 1 < P->N) {
             memcpy(zc, zn, sizeof(double) * 64 * (size_t)nyc);
@@ -696,6 +760,7 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
     if (flip) {
         flip[0] = dS;
         flip[1] = dy1;
+        flip[2] = dcvi;
     }
 }
 
@@ -739,7 +804,7 @@ static void chol_solve(int n, const double *L, const double *rhs, double *beta)
 
 /* ----------------------------------------------- one stratum at step i -- */
 
-/* The cloud C_{i,k}; flip (NULL or [2M]) receives each simulation's bounds of
+/* The cloud C_{i,k}; flip (NULL or [3M]) receives each simulation's bounds of
  * simulate(). */
 static void cloud(const orc_problem *P, const grid_t *G, const double *table, int32_t i, int64_t k,
                   double *Xi, double *dWi, double *Sp, double *y1, double *cvi, double *flip)
@@ -751,7 +816,7 @@ static void cloud(const orc_problem *P, const grid_t *G, const double *table, in
         stream_init(&s, P->seed, P->inst, i, (uint32_t)k, (uint32_t)m);
         start_point(P, G, &s, k, Xi + (int64_t)m * P->d);
         simulate(P, G, table, i, &s, Xi + (int64_t)m * P->d, dWi + (int64_t)m * P->q, Sp + m, y1 + m,
-                 cvi + m, np, flip ? flip + 2 * (int64_t)m : NULL);
+                 cvi + m, np, flip ? flip + 3 * (int64_t)m : NULL);
     }
     if (P->face_flags) P->face_flags[(int64_t)i * G->K + k] = (uint8_t)near;
 }
@@ -797,7 +862,7 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
     const int d = P->d, q = P->q, nb = basis_size(P), M = P->M;
     const double dt = P->T / P->N;
     double *Xi = work, *dWi = Xi + (int64_t)M * d, *Sp = dWi + (int64_t)M * q, *y1 = Sp + M,
-           *cvi = y1 + M, *cz = cvi + M, *flip = cz + M, *dcz = flip + 2 * (int64_t)M;
+           *cvi = y1 + M, *cz = cvi + M, *flip = cz + M, *dcz = flip + 3 * (int64_t)M;
     double *fb = P->flip_bound ? P->flip_bound + ((int64_t)i * G->K + k) * rec_size(P) : NULL;
     cloud(P, G, table, i, k, Xi, dWi, Sp, y1, cvi, fb ? flip : NULL);
 
@@ -886,7 +951,7 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
                 w[0] = 1.0 / M;
             }
             for (int l = 0; l < q; ++l) {
-                double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;
+                double dr = (flip[3 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;
                 for (int a = 0; a < nb; ++a) bz[l][a] += fabs(w[a]) * dr;
             }
         }
@@ -902,7 +967,8 @@ static int fit_stratum(const orc_problem *P, const grid_t *G, double *table, int
                 }
                 zfit[l] = clampv(v, P->clamp_z);
             }
-            double dSY = flip[2 * m] + driver_change_bound(P, y1[m], zfit, flip[2 * m + 1], dz) * dt;
+            double dSY = flip[3 * m] + driver_change_bound(P, y1[m], zfit, flip[3 * m + 1], dz) * dt +
+                         flip[3 * m + 2];
             if (!singular) {
                 chol_solve(nb, L, phi, w);
             } else {
@@ -925,7 +991,7 @@ int orc_solve(const orc_problem *P, double *table, int32_t i_hi, int32_t i_lo, i
     if (i_hi >= P->N || i_lo < 0 || i_lo > i_hi) return -1;
     if (P->d > 64 || basis_size(P) > 65) return -1;
     int64_t nsing = 0;
-    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 7);
+    const int64_t wsz = (int64_t)P->M * (P->d + P->q + 8);
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #else

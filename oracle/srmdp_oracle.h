@@ -77,8 +77,12 @@ typedef struct {
      * stratum, a bound on its change if near-face look-ups (those that set
      * face_flags) took the cube across their face, as rounding in another
      * precision may make them do.
-     * face_flip: near-face look-ups take the first cube across their face
-     * (the run that pins flip_bound).
+     * With a bfloat16 network (cv_bf16 with hidden rounding) the bound also
+     * covers hidden activations within 32 binary32 units of a bfloat16
+     * rounding midpoint rounded to their other neighbour.
+     * face_flip: near-face look-ups take the first cube across their face,
+     * and every such ambiguous hidden activation its other neighbour (the
+     * run that pins flip_bound).
      * debug_singular: the Gram matrix of stratum debug_singular_stratum at
      * step debug_singular_step is replaced by zero, so that the stratum takes
      * the LP0 fallback of a singular Gram. */

@@ -1,20 +1,27 @@
 """Ragged batches and the lanes-per-stratum autotuner on the GPU (called
 through the C ABI).
 
-A batched sweep computes every stratum group exactly as the per-instance sweep
-does (same draws, same sums in the same order), so each table of a batch must
-equal, bit for bit, the table srmdp_solve returns for that instance alone with
-the same lanes per stratum; the per-instance sweep is itself held to the oracle
-by test_gpu_parity.py.  The same holds across lane counts, which is what lets
-the autotuner change them freely.
+Against the oracle: a binary64 ragged batch, every instance over its whole
+sweep at 1e-9; and instances of the 64-instance binary32 workload (the
+smallest, the largest M, the largest N) step by step, each step against the
+oracle's step run from the batch's own rows above it, at 2e-4 plus the
+oracle's face-flip bound.
+
+Self-consistency: a batched sweep computes every stratum group exactly as the
+per-instance sweep does (same draws, same sums in the same order), so each
+table of a batch must also equal, bit for bit, the table srmdp_solve returns
+for that instance alone with the same lanes per stratum.  The same holds
+across lane counts, which is what lets the autotuner change them freely.
 """
 import sys
 
 import numpy as np
 import pytest
 
+import oracle as O
+import test_gpu_parity as TP
 import workloads as W
-from sides import product_args
+from sides import oracle_problem, product_args
 
 pytestmark = pytest.mark.gpu
 
@@ -174,3 +181,55 @@ def test_autotuned_batch_matches_individual_sweeps():
         ref, _ = S.solve(p, g, o)
         torch.cuda.synchronize()
         assert torch.equal(t, ref)
+
+
+def test_ragged_batch_fp64_against_oracle():
+    """Ten binary64 instances (K 4..100, M 8..300, N 3..12, different rates,
+    seeds and instance tags) in one batch: every table, whole sweep, within
+    1e-9 of the oracle's."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfgs = _small_ragged("fp64")
+    P, G, Ob = _args(cfgs)
+    _say(f"[gpu] binary64 ragged batch of {len(cfgs)} against the oracle")
+    tables, _ = S.solve_batch(P, G, Ob)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for c, t in zip(cfgs, tables):
+        orc, _ = O.solve(oracle_problem(c))
+        err = TP.parity(t.cpu().numpy(), orc, range(c["N"]))
+        worst = max(worst, err)
+        assert err <= TP.TOL["fp64"], c["name"]
+    _say(f"[gpu] worst instance parity {worst:.3e}")
+
+
+def test_full_ragged_batch_instances_against_oracle():
+    """The 64-instance binary32 ragged batch (K 16^2..64^2, M 64..1024,
+    N 10..50) in one batched sweep; its smallest instance, the one with the
+    largest M and the one with the largest N, each at steps N-1, N/2 and 0
+    against the oracle's step from the batch's own rows above it."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfgs = W.ragged_batch()
+    P, G, Ob = _args(cfgs)
+    _say(f"[gpu] the {len(cfgs)}-instance ragged batch")
+    tables, _ = S.solve_batch(P, G, Ob)
+    torch.cuda.synchronize()
+
+    def work(c):
+        return int(np.prod(c["cells"])) * c["M"] * c["N"] * (c["N"] + 1) // 2
+
+    picks = {min(range(len(cfgs)), key=lambda b: work(cfgs[b])),
+             max(range(len(cfgs)), key=lambda b: cfgs[b]["M"]),
+             max(range(len(cfgs)), key=lambda b: (cfgs[b]["N"], -work(cfgs[b])))}
+    for b in sorted(picks):
+        c = cfgs[b]
+        gpu = tables[b].double().cpu().numpy()
+        steps = sorted({c["N"] - 1, c["N"] // 2, 0}, reverse=True)
+        for i in steps:
+            _say(f"[gpu] {c['name']} (K = {int(np.prod(c['cells']))}, M = {c['M']}, N = {c['N']}): "
+                 f"oracle step {i} from the batch's rows")
+            orc, flags, bound = TP._oracle_with_flags(c, i, i, 2e-6, table=gpu.copy())
+            err, excess = TP.bounded_parity(gpu, orc, bound, [i], flags, TP.TOL["fp32"])
+            assert err <= TP.TOL["fp32"], (c["name"], i)
+            assert excess <= 0.0, (c["name"], i)

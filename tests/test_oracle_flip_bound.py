@@ -1,4 +1,4 @@
-"""Pins of two test diagnostics of the oracle (CPU only).
+"""Pins of test diagnostics of the oracle (CPU only).
 
 1. The face-flip bound.  A look-up point within eps cell widths of an interior
    cell face may fall in the neighbouring cube when computed in another
@@ -8,6 +8,11 @@
    which every near-face look-up takes the cube across its face must stay
    within the bound, coefficient by coefficient, and the bound must be of the
    size of the change it bounds (not vacuous).
+
+   The same bound covers the control-variate network's bfloat16 roundings:
+   a hidden activation within a few binary32 units of a rounding midpoint may
+   round to the other neighbour in another precision; the forced run rounds
+   every such activation the other way.
 
 2. The singular-Gram fallback.  A Gram matrix forced to zero at one (step,
    stratum) must give that stratum the LP0 fit, i.e. the empirical means of
@@ -111,3 +116,48 @@ def test_singular_gram_takes_the_lp0_mean(basis, driver):
     assert rec[0, 0] == pytest.approx(np.mean(SY), rel=1e-12, abs=1e-14)
     assert np.all(rec[0, 1:] == 0.0)
     assert math.isfinite(rec[0, 0])
+
+
+def _network(n_in, n_out, H=64, seed=3):
+    """Random network in the oracle's layout W1[H][in], b1, W2[H][H], b2, W3[out][H], b3."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (H, n_in)) * math.sqrt(6.0 / (n_in + H)), rng.uniform(-0.2, 0.2, H),
+             rng.uniform(-1, 1, (H, H)) * math.sqrt(6.0 / (2 * H)), rng.uniform(-0.2, 0.2, H),
+             rng.uniform(-1, 1, (n_out, H)) * math.sqrt(6.0 / (H + n_out)), rng.uniform(-0.2, 0.2, n_out)]
+    return np.concatenate([p.ravel() for p in parts])
+
+
+NET_CASES = [
+    ("logistic d=2 network stride 1", dict(d=2, N=5, lo=[-3.0] * 2, hi=[3.0] * 2, cells=[4, 4], M=64,
+                                           driver=O.DRV_LOGISTIC, terminal=O.G_LOGISTIC), 1, 0),
+    ("logistic d=3 network stride 2 centred", dict(d=3, N=5, lo=[-2.0] * 3, hi=[2.0] * 3, cells=[3, 2, 2], M=48,
+                                                   driver=O.DRV_LOGISTIC, terminal=O.G_LOGISTIC), 2, 1),
+]
+
+
+@pytest.mark.parametrize("name,kw,stride,center", NET_CASES, ids=[c[0] for c in NET_CASES])
+def test_flip_bound_covers_bfloat16_roundings_of_the_network(name, kw, stride, center):
+    """With the control-variate network rounding its hidden activations to
+    bfloat16, an activation within a few binary32 units of a rounding midpoint
+    may round the other way in another precision.  The forced run rounds every
+    such activation the other way (and takes every near-face look-up across
+    its face): each coefficient must move by no more than the bound."""
+    net = _network(kw["d"] + 1, kw["d"])
+    bf = O.BF_WEIGHTS | O.BF_PAIR | O.BF_HIDDEN
+    extra = dict(cv_params=net, cv_hidden=64, cv_bf16=bf, cv_stride=stride, z_center=center)
+    P0 = _problem(kw, **extra)
+    table, _ = O.solve(P0)
+    K, i, eps = P0.K, 1, 1e-6
+    bound = np.zeros(P0.table_shape())
+    base = table.copy()
+    O.solve(_problem(kw, face_eps=eps, flip_bound=bound, **extra), table=base, i_hi=i, i_lo=i)
+    flipped = table.copy()
+    O.solve(_problem(kw, face_eps=eps, face_flip=1, **extra), table=flipped, i_hi=i, i_lo=i)
+    change = np.abs(flipped[i] - base[i])
+    b = bound[i]
+    scale = np.max(np.abs(base[i]))
+    assert np.all(change <= b * (1 + 1e-6) + 1e-12 * scale), np.max(change - b)
+    moved = change.reshape(K, -1).max(axis=1) > 1e-12 * scale
+    assert moved.sum() >= K // 2, "most strata must meet an ambiguous rounding"
+    ratio = change.reshape(K, -1).max(axis=1)[moved] / b.reshape(K, -1).max(axis=1)[moved]
+    assert ratio.max() > 0.2, ratio

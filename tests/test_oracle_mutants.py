@@ -98,13 +98,17 @@ MUTANTS = [
      lambda: CF.test_state_dependent_diffusion_fits_match_projection_of_closed_form(2, [4, 4], 12000,
                                                                                     [0.5, -0.8])),
     ("face-flip bound of z without the 1/dt of its response",
-     "double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;",
-     "double dr = (flip[2 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]);",
+     "double dr = (flip[3 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]) / dt;",
+     "double dr = (flip[3 * m] + dcz[m]) * fabs(dWi[(int64_t)m * q + l]);",
      lambda: FB.test_flip_bound_holds_against_forced_flips(*FB.CASES[0])),
     ("face-flip bound of a path without the dt of its driver terms",
-     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt;",
-     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0);",
+     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) * dt + dcv;",
+     "if (flip) dS += driver_spread(P, j * dt, x, nyc, yc, nzc, zc, f0) + dcv;",
      lambda: FB.test_flip_bound_holds_against_forced_flips(*FB.CASES[0])),
+    ("network flip bound skips the second hidden layer",
+     "for (int layer = 1; layer <= 2; ++layer)",
+     "for (int layer = 1; layer <= 1; ++layer)",
+     lambda: FB.test_flip_bound_covers_bfloat16_roundings_of_the_network(*FB.NET_CASES[0])),
     ("singular fallback divides by M - 1",
      "beta[0] = rhs[0] / M;\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
      "beta[0] = rhs[0] / (M - 1);\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
