@@ -106,9 +106,23 @@ def _omp_threads() -> int:
     return int(O.max_threads())
 
 
-def cpu_baseline(cfg: dict, seconds: float) -> dict:
-    """The FP64 oracle as it stands, on the first backward steps of the same
-    workload (steps N-1, N-2, ... until about `seconds` of CPU work)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg: dict, seconds: float, full: bool = False) -> dict:
+    """The FP64 oracle as it stands.  `value`: the first backward steps of the
+    headline workload (steps N-1, N-2, ... until about `seconds` of CPU work,
+    all OpenMP threads).  Beside it, whole oracle sweeps of the small
+    workloads: cfg1 on all threads and on one, cfg2 and cfg4 on all threads,
+    and with `full` cfg2 on one thread (about a minute)."""
     import numpy as np
 
     import oracle as O
@@ -126,10 +140,23 @@ def cpu_baseline(cfg: dict, seconds: float) -> dict:
         i -= 1
         if t_total > seconds:
             break
-    return {"value": done / t_total, "unit": "path-steps/s", "cores": _omp_threads(),
+    threads = _omp_threads()
+    sweeps = []
+    runs = [("cfg1", 0), ("cfg1", 1), ("cfg2", 0), ("cfg4", 0)] + ([("cfg2", 1)] if full else [])
+    for name, nthr in runs:
+        c = W.config(name)
+        Pc = oracle_problem(c)
+        t0 = time.perf_counter()
+        O.solve(Pc, threads=nthr or threads)   # the count is sticky: always pass it
+        dt = time.perf_counter() - t0
+        sweeps.append({"workload": c["name"], "threads": nthr or threads, "sweep_s": dt,
+                       "path_steps_per_s": W.path_steps(c) / dt})
+    return {"value": done / t_total, "unit": "path-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{cfg['name']}: backward steps {cfg['N'] - 1}..{i + 1} "
-                      f"({done} FP64 path-steps in {t_total:.1f} s)"}
+                      f"({done} FP64 path-steps in {t_total:.1f} s)",
+            "host_cpu": _cpu_model(), "host_threads": os.cpu_count(),
+            "full_sweeps": sweeps}
 
 
 def _product_args(S, cfg: dict):
@@ -546,7 +573,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5, help="timed full sweeps")
     ap.add_argument("--warmup", type=int, default=2, help="untimed full sweeps")
     ap.add_argument("--workload", default="cfg5", choices=sorted(W.CONFIGS))
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle's cfg2 sweep on one thread (about a minute)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--root-paths", type=int, default=1 << 20)
     ap.add_argument("--no-error-matched", action="store_true",
@@ -684,7 +713,7 @@ def main() -> int:
         out["cv_equal_M"] = cv_equal_m(S, W.config("cfg4"), range(1, 5), stream)
         progress("equal-M comparison")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, full=args.cpu_full)
     print(json.dumps(out), flush=True)
     return 0
 

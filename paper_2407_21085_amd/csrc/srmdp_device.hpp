@@ -8,8 +8,6 @@
 
 namespace srmdp {
 
-constexpr int kMaxD = 16;
-
 // ------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
 // (SC'11): ten rounds of the two-multiplier S-box on a 128-bit counter, key

@@ -7,10 +7,12 @@
 // and the response accumulation live in registers, and only what the two
 // regressions need (phi(X_i), dW_i, S', y_{i+1}(X_{i+1})) goes to LDS.  The
 // Gram matrix and right-hand sides are then formed lane-parallel over their
-// entries with binary64 accumulators, the Cholesky factor and the solves run
-// in binary64, and the stratum's record is written once to the coefficient
-// table and once, projected on what the driver needs, to a compact look-up row
-// that later steps gather from L2/MALL.
+// entries with binary64 accumulators, the Gram matrix is inverted in binary64
+// by Gauss-Jordan elimination (its pivots are the squared diagonal of the
+// Cholesky factor, which the singular test reads), the coefficients are the
+// inverse times the right-hand sides, and the stratum's record is written once
+// to the coefficient table and once, projected on what the driver needs, to a
+// compact look-up row that later steps gather from L2/MALL.
 #include "srmdp_aux.hpp"
 
 namespace srmdp {

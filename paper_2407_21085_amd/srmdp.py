@@ -24,7 +24,7 @@ F_GRAPH, F_CHECK_FINITE, F_CV_CENTER_Z, F_AUTOTUNE, F_GLOBAL_ROWS = 0x1, 0x2, 0x
 F_DEBUG_SINGULAR = 0x20
 GRID_EQUAL_SIZE, GRID_EQUAL_PROB = 0, 1
 CV_NONE, CV_FROZEN, CV_ONLINE = 0, 1, 2
-MAX_D = 16
+MAX_D = 19   # SRMDP_MAX_D of include/srmdp.h
 MLP_HIDDEN = 64
 
 

@@ -23,6 +23,8 @@ def test_every_declared_function_is_exported():
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
     assert S.srmdp.lib.srmdp_abi_version() == 107
+    # the binding's largest dimension is the header's
+    assert int(re.search(r"#define SRMDP_MAX_D (\d+)", header).group(1)) == S.srmdp.MAX_D
 
 
 def test_table_elems_and_paper_sizes():
