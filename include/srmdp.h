@@ -37,8 +37,10 @@
 #ifndef SRMDP_H
 #define SRMDP_H
 
+#if !defined(__HIPCC_RTC__)  /* device code compiled at run time has the types built in */
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -77,7 +79,41 @@ typedef enum { SRMDP_DRV_LINEAR = 0, SRMDP_DRV_LOGISTIC = 1 } srmdp_driver;
  * benchmark, g = omega(T,x)/(1 + omega(T,x)), omega(t,x) = exp(t + sum_l x_l). */
 typedef enum { SRMDP_G_COS_SUM = 0, SRMDP_G_LOGISTIC = 1 } srmdp_terminal;
 
-/* Problem data (eq. (fbsde)-(eds) with constant coefficients). */
+/* A problem's own coefficients and data, compiled at run time (hipRTC, for
+ * the device the sweep runs on) into the sweep kernels: general b(t, x),
+ * sigma(t, x) through the Euler scheme of Section 2 (Algorithm "Euler
+ * dynamics", at (t_j, X_j)) and general f(t, x, y, z), g(x) of eq.
+ * (fbsde)-(MDP:intro).
+ *  source   host, NUL-terminated HIP C++ device code.  It is compiled with
+ *           `srmdp_real` (double for SRMDP_FP64 sweeps, float for SRMDP_FP32)
+ *           and the macros SRMDP_D (= d) and SRMDP_Q (= q = d) defined, and
+ *           must define
+ *     __device__ void srmdp_b(srmdp_real t, const srmdp_real *x, const srmdp_real *p,
+ *                             srmdp_real *out);                 out[SRMDP_D] = b(t, x)
+ *     __device__ void srmdp_sigma_dw(srmdp_real t, const srmdp_real *x, const srmdp_real *dw,
+ *                                    const srmdp_real *p, srmdp_real *out);   out[SRMDP_D] = sigma(t, x) dw
+ *     __device__ srmdp_real srmdp_f(srmdp_real t, const srmdp_real *x, srmdp_real y,
+ *                                   const srmdp_real *z, const srmdp_real *p);  f(t, x, y, z), z[SRMDP_Q]
+ *     __device__ srmdp_real srmdp_g(const srmdp_real *x, const srmdp_real *p);    g(x)
+ *           The Euler step is X_{j+1} = X_j + b(t_j, X_j) dt + sigma(t_j, X_j) dW_j
+ *           with t_j = j dt, in that order of additions.
+ *  params   host [n_params] or NULL: p[0..n_params-1] of the functions above,
+ *           converted to srmdp_real (a new value needs no new compilation).
+ *  n_params 0..64.
+ * Kernels are compiled once per (device, source, d, basis, precision) and
+ * kept for the process.  A compilation error returns SRMDP_E_INVALID with the
+ * compiler's log in srmdp_last_error().  Covered: srmdp_solve (equal-size
+ * cells, clouds in LDS, d <= 8, no control variate), srmdp_eval; other
+ * entry points return SRMDP_E_UNSUPPORTED for a problem with a model. */
+typedef struct {
+    const char *source;
+    const double *params;
+    int32_t n_params;
+} srmdp_model;
+
+/* Problem data (eq. (fbsde)-(eds)): the built-in families below, or a
+ * compiled model (then driver, terminal, r, kappa, b, sigma, b_lin and
+ * sigma_lin are not used and must be zero or NULL). */
 typedef struct {
     int32_t d, q;          /* 1..SRMDP_MAX_D; the built-in f and g need q == d */
     double T;              /* horizon > 0 */
@@ -96,6 +132,7 @@ typedef struct {
                               * sigma(x)_{l,c} = sigma_{l,c} + [l = c] sigma_lin_l x_l, evaluated at
                               * X_j in the Euler scheme of Section 2 (geometric Brownian motion
                               * when sigma is zero); NULL = 0 */
+    const srmdp_model *model; /* host or NULL: the problem's own coefficients (srmdp_model) */
 } srmdp_problem;
 
 /* Stratification: the two examples of hypercubes under assumption

@@ -61,6 +61,12 @@ def using_library(path: str):
         _lib = saved
 
 
+class _Model(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_void_p), ("sigma_dw", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("g", ctypes.c_void_p), ("params", ctypes.POINTER(ctypes.c_double)),
+                ("lip_y", ctypes.c_double), ("lip_z", ctypes.c_double)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [
         ("d", ctypes.c_int32), ("q", ctypes.c_int32),
@@ -85,6 +91,7 @@ class _Problem(ctypes.Structure):
         ("debug_singular", ctypes.c_int32),
         ("debug_singular_step", ctypes.c_int32),
         ("debug_singular_stratum", ctypes.c_int64),
+        ("model", ctypes.POINTER(_Model)),
     ]
 
 
@@ -137,6 +144,43 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+_MODEL_LIBS = {}
+
+
+@dataclass
+class Model:
+    """A problem's own coefficients as a small C plugin, compiled with gcc
+    (-DMODEL_D=d) and called by the oracle through function pointers.  The
+    source defines
+        void model_b(double t, const double *x, const double *p, double *out);
+        void model_sigma_dw(double t, const double *x, const double *dw, const double *p, double *out);
+        double model_f(double t, const double *x, double y, const double *z, const double *p);
+        double model_g(const double *x, const double *p);
+    lip_y, lip_z bound |df/dy| and |df/dz_l| (used by the face-flip bound only)."""
+    source: str
+    params: Sequence[float] = ()
+    lip_y: float = 0.0
+    lip_z: float = 0.0
+
+    def library(self, d: int):
+        import hashlib
+        import tempfile
+        key = hashlib.sha256(f"{d}\n{self.source}".encode()).hexdigest()[:20]
+        if key not in _MODEL_LIBS:
+            tmp = os.path.join(tempfile.gettempdir(), f"srmdp_oracle_model_{os.getuid()}")
+            os.makedirs(tmp, exist_ok=True)
+            src = os.path.join(tmp, f"model_{key}.c")
+            out = os.path.join(tmp, f"libmodel_{key}.so")
+            if not os.path.exists(out):
+                with open(src, "w") as f:
+                    f.write(self.source)
+                subprocess.run(["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+                                "-shared", f"-DMODEL_D={d}", src, "-o", out + ".tmp", "-lm"], check=True)
+                os.replace(out + ".tmp", out)
+            _MODEL_LIBS[key] = ctypes.CDLL(out)
+        return _MODEL_LIBS[key]
+
+
 @dataclass
 class Problem:
     """Problem data, stratification and simulation settings of one sweep."""
@@ -175,6 +219,7 @@ class Problem:
     flip_bound: Optional[np.ndarray] = None
     face_flip: int = 0
     debug_singular: Optional[tuple] = None
+    model: Optional[Model] = None   # the problem's own coefficients (C plugin)
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -242,6 +287,14 @@ class Problem:
         if self.debug_singular is not None:
             s.debug_singular = 1
             s.debug_singular_step, s.debug_singular_stratum = (int(v) for v in self.debug_singular)
+        if self.model is not None:
+            lib_m = self.model.library(self.d)
+            prm = arr(list(self.model.params) or [0.0])
+            fn = [ctypes.cast(getattr(lib_m, n), ctypes.c_void_p).value
+                  for n in ("model_b", "model_sigma_dw", "model_f", "model_g")]
+            m = _Model(*fn, _dp(prm), float(self.model.lip_y), float(self.model.lip_z))
+            keep += [lib_m, m]
+            s.model = ctypes.pointer(m)
         self._keep = keep
         return s
 

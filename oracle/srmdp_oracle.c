@@ -274,6 +274,7 @@ static void basis_eval(const orc_problem *P, const grid_t *G, int64_t k, const d
  * benchmark" for the logistic case; cos of the coordinate sum otherwise). */
 double orc_terminal(const orc_problem *P, const double *x)
 {
+    if (P->model) return P->model->g(x, P->model->params);
     double s = 0.0;
     for (int l = 0; l < P->d; ++l) s += x[l];
     if (P->terminal == ORC_G_LOGISTIC) {
@@ -287,8 +288,7 @@ double orc_terminal(const orc_problem *P, const double *x)
  * benchmark, or the linear f = -r y + kappa sum z. */
 double orc_driver(const orc_problem *P, double t, const double *x, double y, const double *z)
 {
-    (void)t;
-    (void)x;
+    if (P->model) return P->model->f(t, x, y, z, P->model->params);
     double sz = 0.0;
     for (int l = 0; l < P->q; ++l) sz += z[l];
     if (P->driver == ORC_DRV_LOGISTIC)
@@ -546,6 +546,9 @@ static int check_problem(const orc_problem *P, grid_t *G)
     if (!P->sigma && P->q != P->d) return -1;
     if (P->sigma_lin && P->q != P->d) return -1;
     if (P->M < basis_size(P)) return -1; /* M >= dim of the local space */
+    if (P->model && (P->q != P->d || !P->model->b || !P->model->sigma_dw || !P->model->f || !P->model->g ||
+                     P->b || P->sigma || P->b_lin || P->sigma_lin))
+        return -1;
     if (P->cv_params && (P->cv_hidden < 1 || P->cv_hidden > 256 || P->q > 64)) return -1;
     return grid_init(P, G);
 }
@@ -700,15 +703,23 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
     for (int32_t j = i; j < P->N; ++j) {
         for (int l = 0; l < q; ++l)
             dW[l] = sdt * stream_normal(s, d, (int64_t)(j - i) * q + l);
-        for (int l = 0; l < d; ++l) {
-            double drift = (P->b ? P->b[l] : 0.0) + (P->b_lin ? P->b_lin[l] * x[l] : 0.0);
-            double diff = 0.0;
-            if (P->sigma)
-                for (int c = 0; c < q; ++c) diff += P->sigma[l * q + c] * dW[c];
-            else
-                diff = dW[l];
-            if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];
-            xn[l] = x[l] + drift * dt + diff;
+        if (P->model) {
+            /* Algorithm "Euler dynamics" at (t_j, X_j) */
+            double bj[64], sj[64];
+            P->model->b(j * dt, x, P->model->params, bj);
+            P->model->sigma_dw(j * dt, x, dW, P->model->params, sj);
+            for (int l = 0; l < d; ++l) xn[l] = x[l] + bj[l] * dt + sj[l];
+        } else {
+            for (int l = 0; l < d; ++l) {
+                double drift = (P->b ? P->b[l] : 0.0) + (P->b_lin ? P->b_lin[l] * x[l] : 0.0);
+                double diff = 0.0;
+                if (P->sigma)
+                    for (int c = 0; c < q; ++c) diff += P->sigma[l * q + c] * dW[c];
+                else
+                    diff = dW[l];
+                if (P->sigma_lin) diff += P->sigma_lin[l] * x[l] * dW[l];
+                xn[l] = x[l] + drift * dt + diff;
+            }
         }
         double ynext;
         int nyc = 1, use = 0;
@@ -840,6 +851,7 @@ static double driver_change_bound(const orc_problem *P, double y, const double *
         sz += z[l];
         sdz += dz[l];
     }
+    if (P->model) return P->model->lip_y * dy + P->model->lip_z * sdz;
     if (P->driver == ORC_DRV_LOGISTIC) {
         double c = (2.0 + P->q) / (2.0 * P->q);
         return sdz * (fabs(y - c) + dy) + fabs(sz) * dy;

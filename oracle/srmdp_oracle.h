@@ -28,6 +28,18 @@ enum { ORC_GRID_EQUAL_SIZE = 0, ORC_GRID_EQUAL_PROB = 1 };
 enum { ORC_DRV_LINEAR = 0, ORC_DRV_LOGISTIC = 1 };
 enum { ORC_G_COS_SUM = 0, ORC_G_LOGISTIC = 1 };
 
+/* A problem's own coefficients: b(t, x), sigma(t, x) applied to dW, f(t, x, y, z)
+ * and g(x), with parameters p (used by the test-suite through small C plugins;
+ * the GPU library takes the same functions as HIP source). */
+typedef struct {
+    void (*b)(double t, const double *x, const double *p, double *out);                   /* out[d] */
+    void (*sigma_dw)(double t, const double *x, const double *dw, const double *p, double *out); /* out[d] */
+    double (*f)(double t, const double *x, double y, const double *z, const double *p);
+    double (*g)(const double *x, const double *p);
+    const double *params;
+    double lip_y, lip_z;     /* bounds of |df/dy| and |df/dz_l| (face-flip bound only) */
+} orc_model;
+
 typedef struct {
     int32_t d, q;            /* space and Brownian dimensions */
     double T;                /* horizon */
@@ -91,6 +103,11 @@ typedef struct {
     int32_t debug_singular;
     int32_t debug_singular_step;
     int64_t debug_singular_stratum;
+    /* NULL, or the problem's own coefficients: the Euler step is then
+     * X_{j+1} = X_j + b(t_j, X_j) dt + sigma(t_j, X_j) dW_j (t_j = j dt), the
+     * driver and terminal condition f and g; b, sigma, b_lin, sigma_lin and
+     * the built-in driver and terminal are not used. */
+    const orc_model *model;
 } orc_problem;
 
 /* Threads the OpenMP loops over strata use. */

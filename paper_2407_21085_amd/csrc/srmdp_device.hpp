@@ -3,8 +3,10 @@
 // Everything here is inlined into the kernels of srmdp_kernels.hip.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)  // under hipRTC the runtime is built in; the run-time source declares the integer types
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace srmdp {
 

@@ -67,6 +67,8 @@ srmdp_status hip_fail(hipError_t e, const char *what)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+constexpr int kMaxModelParams = 64;  // srmdp_model.n_params
+
 // Timing events of one call, destroyed on every return path.
 struct EventSet {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -103,6 +105,18 @@ srmdp_status check_problem(const srmdp_problem *p, const srmdp_grid *g, Shape &s
     if (p->q != p->d)
         return fail(SRMDP_E_INVALID, "the built-in driver and terminal need q == d (q = %d, d = %d)",
                     p->q, p->d);
+    if (p->model) {
+        const srmdp_model *m = p->model;
+        if (!m->source || !m->source[0]) return fail(SRMDP_E_INVALID, "model source must be non-empty");
+        if (m->n_params < 0 || m->n_params > kMaxModelParams)
+            return fail(SRMDP_E_INVALID, "model n_params = %d outside 0..%d", m->n_params, kMaxModelParams);
+        if (m->n_params > 0 && !m->params) return fail(SRMDP_E_INVALID, "model params NULL with n_params > 0");
+        for (int v = 0; v < m->n_params; ++v)
+            if (!std::isfinite(m->params[v])) return fail(SRMDP_E_INVALID, "model parameter %d is not finite", v);
+        if (p->b || p->sigma || p->b_lin || p->sigma_lin || p->r != 0.0 || p->kappa != 0.0 || p->driver != 0 ||
+            p->terminal != 0)
+            return fail(SRMDP_E_INVALID, "a problem with a model takes no built-in coefficients");
+    }
     if (!(p->T > 0.0) || !std::isfinite(p->T)) return fail(SRMDP_E_INVALID, "T must be finite and > 0");
     if (p->N < 1 || p->N > 65535) return fail(SRMDP_E_INVALID, "N = %d outside 1..65535", p->N);
     if (p->driver != SRMDP_DRV_LINEAR && p->driver != SRMDP_DRV_LOGISTIC)
@@ -207,7 +221,7 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
 
 int lookup_mode(const srmdp_problem *p)
 {
-    if (std::isfinite(p->clamp_z)) return kLookupFull;
+    if (p->model || std::isfinite(p->clamp_z)) return kLookupFull;  // a model's driver reads every z_c
     if (p->driver == SRMDP_DRV_LINEAR && p->kappa == 0.0) return kLookupY;
     return kLookupYZ;
 }
@@ -237,7 +251,8 @@ Layout layout(const Shape &s, int nb, int is_float, int lk, const srmdp_options 
     L.cellF = off;
     off = align_up(off + (size_t)s.d * s.cmax * 4 * rsz, 256);
     L.bsig = off;
-    off = align_up(off + (size_t)(3 * s.d + s.d * s.q) * rsz, 256);  // b | sigma | b_lin | sigma_lin
+    // b | sigma | b_lin | sigma_lin, or a model's parameters
+    off = align_up(off + (size_t)std::max(3 * s.d + s.d * s.q, kMaxModelParams) * rsz, 256);
     L.root_partial = off;
     off = align_up(off + (size_t)kRootBlocks * (s.d + 2) * sizeof(double), 256);
     L.root_out = off;
@@ -496,6 +511,23 @@ srmdp_status sweep_supported(const Shape &s, const srmdp_options *o, int lk)
     return SRMDP_OK;
 }
 
+// What a problem with its own model runs: the LDS sweep on equal-size cells
+// for the dimensions compiled with it, without the control variate, the
+// autotuner or clouds in global memory.
+srmdp_status model_supported(const Shape &s, int nb, const srmdp_options *o)
+{
+    if (s.equal_prob) return fail(SRMDP_E_UNSUPPORTED, "a model runs on equal-size cells");
+    if (!lds_dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "a model runs for d = 1..6 and 8");
+    if (o->cv != SRMDP_CV_NONE) return fail(SRMDP_E_UNSUPPORTED, "a model runs without the control variate");
+    if (o->flags & (SRMDP_F_AUTOTUNE | SRMDP_F_GLOBAL_ROWS))
+        return fail(SRMDP_E_UNSUPPORTED, "a model runs without the autotuner and global cloud rows");
+    LaunchShape ls;
+    size_t per_cube;
+    if (!make_shape(s, nb, o->prec == SRMDP_FP32, o->M, lanes_for(o), ls, per_cube, false, o) || ls.grows)
+        return fail(SRMDP_E_UNSUPPORTED, "a model runs with clouds in LDS (M = %d is too large)", o->M);
+    return SRMDP_OK;
+}
+
 // Backward-step launches per step.
 uint32_t launches_per_step(const Shape &s, const LaunchShape &ls)
 {
@@ -520,8 +552,8 @@ std::string graph_key(const void *args, size_t n, hipStream_t st)
 template <typename R>
 srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o,
                            const Shape &s, int nb, int lk, void *table, unsigned char *ws,
-                           const Layout &lay, hipStream_t st, hipEvent_t steps0 = nullptr,
-                           hipEvent_t steps1 = nullptr)
+                           const Layout &lay, hipStream_t st, const ModelKernels *mk,
+                           hipEvent_t steps0 = nullptr, hipEvent_t steps1 = nullptr)
 {
     const int is_float = sizeof(R) == 4;
     const int L = lanes_for(o);
@@ -542,6 +574,10 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
 
     HIP_TRY(launch_zero_u64((unsigned long long *)(ws + lay.counters), kCounterCount, st), "zero counters");
     HIP_TRY(launch_setup<R>(sa, sg.v, ws + lay.cellF, ws + lay.bsig, st), "setup kernel");
+    if (mk && p->model->n_params > 0) {  // a model reads its parameters where bsig was
+        std::vector<R> pv(p->model->params, p->model->params + p->model->n_params);
+        HIP_TRY(launch_upload(ws + lay.bsig, pv.data(), pv.size() * sizeof(R), st), "model parameters");
+    }
     const MlpShape net{s.d + 1, s.q};
     if (cv) {
         a.cv_packed = ws + lay.cv_packed;
@@ -596,11 +632,20 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
                 launched = true;
             }
         }
+        if (mk) {
+            HIP_TRY(launch_model_step<R>(*mk, a, ls, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup, table,
+                                         ws + lay.counters, st),
+                    "sweep step (model)");
+            launched = true;
+        }
         if (!launched)
             HIP_TRY(launch_plain_step<R>(s, a, ls, o->basis, lk, ws, lay.cellF, lay.bsig, lay.lookup, lay.counters,
                                          lay.grows, table, st),
                     "sweep step");
-        if (a.face_flags)
+        if (a.face_flags && mk)
+            HIP_TRY(launch_model_face_flags<R>(*mk, a, ws + lay.cellF, ws + lay.bsig, ws + lay.counters, st),
+                    "near-face flags (model)");
+        else if (a.face_flags)
             HIP_TRY(launch_face_flags<R>(s.d, o->basis, a, ws + lay.cellF, ws + lay.bsig,
                                          ws + lay.counters, st),
                     "near-face flags");
@@ -612,7 +657,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
 template <typename R>
 srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp_options *o,
                         const Shape &s, int nb, void *table, void *workspace, srmdp_stats *stats,
-                        hipStream_t st)
+                        hipStream_t st, const ModelKernels *mk)
 {
     const int lk = lookup_mode(p);
     const Layout lay = layout(s, nb, sizeof(R) == 4, lk, o);
@@ -636,6 +681,10 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         if (p->sigma) put(p->sigma, sizeof(double) * s.d * s.q);
         if (p->b_lin) put(p->b_lin, sizeof(double) * s.d);
         if (p->sigma_lin) put(p->sigma_lin, sizeof(double) * s.d);
+        if (p->model) {
+            put(p->model->source, std::strlen(p->model->source));
+            if (p->model->n_params > 0) put(p->model->params, sizeof(double) * p->model->n_params);
+        }
         put(&g->kind, sizeof g->kind);
         if (g->kind == SRMDP_GRID_EQUAL_SIZE) {
             put(g->lo, sizeof(double) * s.d);
@@ -652,7 +701,7 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         if (it == g_graphs.end()) {
             GraphEntry ent;
             HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-            rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st);
+            rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st, mk);
             hipGraph_t graph = nullptr;
             const hipError_t ec = hipStreamEndCapture(st, &graph);
             if (rc != SRMDP_OK) {
@@ -667,7 +716,7 @@ srmdp_status solve_impl(const srmdp_problem *p, const srmdp_grid *g, const srmdp
         HIP_TRY(hipGraphLaunch(it->second.exec, st), "hipGraphLaunch");
         graph_used = true;
     } else {
-        rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st, s0, s1);
+        rc = enqueue_sweep<R>(p, g, o, s, nb, lk, table, ws, lay, st, mk, s0, s1);
         if (rc != SRMDP_OK) return rc;
     }
     const bool need_sync = stats || (o->flags & SRMDP_F_CHECK_FINITE);
@@ -906,6 +955,7 @@ srmdp_status plan_batch(int n, const srmdp_problem *P, const srmdp_grid *G, cons
         srmdp_status rc = check_problem(&P[b], &G[b], bp.shapes[b]);
         if (rc == SRMDP_OK) rc = check_options(&O[b], bp.shapes[b], nb);
         if (rc != SRMDP_OK) return fail(rc, "instance %d: %s", b, g_error.c_str());
+        if (P[b].model) return fail(SRMDP_E_UNSUPPORTED, "instance %d: batches do not take a problem with a model", b);
         const int lk = lookup_mode(&P[b]);
         if (b == 0) {
             bp.nb = nb;
@@ -1151,14 +1201,23 @@ srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
     if (rc != SRMDP_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     srmdp_options o = *opts;
+    ModelKernels mk;
+    const ModelKernels *mkp = nullptr;
+    if (problem->model) {
+        rc = model_supported(s, nb, opts);
+        if (rc != SRMDP_OK) return rc;
+        rc = model_kernels(problem->model, s.d, nb, opts->prec == SRMDP_FP32, mk);
+        if (rc != SRMDP_OK) return rc;
+        mkp = &mk;
+    }
     if ((o.flags & SRMDP_F_AUTOTUNE) && o.lanes_per_cube == 0) {
         int L = 0;
         rc = tune_cached(problem, grid, &o, s, nb, table, (unsigned char *)workspace, st, &L, nullptr, false);
         if (rc != SRMDP_OK) return rc;
         o.lanes_per_cube = L;
     }
-    if (o.prec == SRMDP_FP32) return solve_impl<float>(problem, grid, &o, s, nb, table, workspace, stats, st);
-    return solve_impl<double>(problem, grid, &o, s, nb, table, workspace, stats, st);
+    if (o.prec == SRMDP_FP32) return solve_impl<float>(problem, grid, &o, s, nb, table, workspace, stats, st, mkp);
+    return solve_impl<double>(problem, grid, &o, s, nb, table, workspace, stats, st, mkp);
 }
 
 srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
@@ -1170,6 +1229,7 @@ srmdp_status srmdp_tune_lanes(const srmdp_problem *problem, const srmdp_grid *gr
     int nb;
     srmdp_status rc = check_problem(problem, grid, s);
     if (rc != SRMDP_OK) return rc;
+    if (problem->model) return fail(SRMDP_E_UNSUPPORTED, "srmdp_tune_lanes does not take a problem with a model");
     rc = check_options(opts, s, nb);
     if (rc != SRMDP_OK) return rc;
     if (!table || !workspace || !lanes) return fail(SRMDP_E_INVALID, "table, workspace and lanes are required");
@@ -1251,6 +1311,7 @@ srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid, co
     int nb;
     srmdp_status rc = check_problem(problem, grid, s);
     if (rc != SRMDP_OK) return rc;
+    if (problem->model) return fail(SRMDP_E_UNSUPPORTED, "srmdp_root does not take a problem with a model");
     rc = check_options(opts, s, nb);
     if (rc != SRMDP_OK) return rc;
     if (!table || !x0 || !y0 || !z0 || !workspace)
@@ -1278,6 +1339,7 @@ srmdp_status srmdp_cv_pairs(const srmdp_problem *problem, const srmdp_grid *grid
     int nb;
     srmdp_status rc = check_problem(problem, grid, s);
     if (rc != SRMDP_OK) return rc;
+    if (problem->model) return fail(SRMDP_E_UNSUPPORTED, "srmdp_cv_pairs does not take a problem with a model");
     rc = check_options(opts, s, nb);
     if (rc != SRMDP_OK) return rc;
     if (opts->prec != SRMDP_FP32) return fail(SRMDP_E_UNSUPPORTED, "training pairs come from binary32 tables");

@@ -2,9 +2,11 @@
 // kernels (srmdp_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)  // under hipRTC the runtime is built in; the run-time source declares the integer types
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #include "../../include/srmdp.h"
 
@@ -12,9 +14,11 @@ namespace srmdp {
 
 constexpr int kMaxDim = 19;
 
+#if !defined(__HIPCC_RTC__)
 // Records the message returned by srmdp_last_error() on this thread (host
 // runtime, srmdp_host.cpp) and returns `s`.
 srmdp_status set_error(srmdp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+#endif
 
 // What a look-up row holds for each stratum: the y coefficients only (the
 // driver does not use z), y and the sum of the z_l coefficients (both built-in
@@ -107,6 +111,7 @@ struct LaunchShape {
     int stage_chunks;          // chunks per LDS window of the sums
 };
 
+#if !defined(__HIPCC_RTC__)  // host launchers
 template <typename R>
 hipError_t launch_setup(const SetupArgs &s, const double *sigma, void *cellF, void *bsig, hipStream_t st);
 template <typename R>
@@ -198,6 +203,8 @@ template <typename R>
 hipError_t launch_draw_hd3(int d, const StepArgs<R> &a, const SetupArgs &s, int kind, uint32_t k0,
                           uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st);
 
+#endif
+
 // ------------------------------------------------------ batched sweeps
 // One instance of a batched sweep, as the batched kernel reads it.  Global
 // step g runs backward step i = N - 1 - g of every instance with N > g; the
@@ -215,12 +222,27 @@ struct BatchInstance {
     uint32_t pad;
 };
 
+#if !defined(__HIPCC_RTC__)  // host launchers
 template <typename R>
 hipError_t launch_batch_step(int d, int basis, int lkmode, bool equal_prob, const void *inst, int n_active,
                              uint32_t total_items, int g, unsigned threads, size_t lds_bytes, hipStream_t st);
 // Copies `bytes` from host memory to the device through kernel arguments (no
 // staging buffer, nothing to keep alive after the call, capturable).
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+// Kernels of a problem's own model (srmdp_model), compiled at run time for the
+// current device (srmdp_rtc.cpp): hipFunction_t of the step kernel and of the
+// near-face diagnostic.
+struct ModelKernels {
+    void *step = nullptr, *face_flags = nullptr;
+};
+srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, ModelKernels &out);
+template <typename R>
+hipError_t launch_model_step(const ModelKernels &k, const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
+                             const void *bsig, void *lk, void *table, void *counters, hipStream_t st);
+template <typename R>
+hipError_t launch_model_face_flags(const ModelKernels &k, const StepArgs<R> &a, const void *cellF, const void *bsig,
+                                   void *counters, hipStream_t st);
 
 // Dimensions with the LDS sweep kernel, and every dimension compiled at all.
 bool lds_dimension_compiled(int d);
@@ -277,5 +299,7 @@ size_t mlp_train_partial_bytes(int in, int out, int batch);
 // t.updates Adam updates, two launches each; partial: mlp_train_partial_bytes.
 hipError_t launch_mlp_train(const MlpTrainArgs &t, float *partial, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+
+#endif
 
 }  // namespace srmdp

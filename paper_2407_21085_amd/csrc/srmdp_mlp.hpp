@@ -24,8 +24,10 @@
 // W2 [64 x 64], b2 [64], W3 [out x 64], b3 [out], row-major.
 #pragma once
 
+#if !defined(__HIPCC_RTC__)  // under hipRTC the runtime is built in; the run-time source declares the integer types
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace srmdp {
 

@@ -49,6 +49,10 @@ extern "C" srmdp_status srmdp_solve_noalloc(const srmdp_problem *problem, const 
                                             const srmdp_options *opts, void *table, void *stream)
 {
     if (!opts) return srmdp::set_error(SRMDP_E_INVALID, "opts must be non-NULL");
+    if (problem && problem->model)
+        return srmdp::set_error(SRMDP_E_INVALID,
+                                "srmdp_solve_noalloc does not take a problem with a model (compiling and loading "
+                                "its kernels allocates)");
     if (opts->flags & SRMDP_F_GRAPH)
         return srmdp::set_error(SRMDP_E_INVALID,
                                 "srmdp_solve_noalloc does not take SRMDP_F_GRAPH (instantiating a graph allocates)");

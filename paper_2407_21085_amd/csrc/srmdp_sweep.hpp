@@ -203,6 +203,29 @@ __device__ __forceinline__ void lookup_eval(const StepArgs<R> &a, const R *__res
     eval_record<R, D, NB, LK>(a, rec, xi, y, zsum);
 }
 
+// Fitted y_j(x) and every z_{j,c}(x), each truncated, from a whole record
+// (look-up mode Full): what a model's own driver f(t, x, y, z) reads.
+template <typename R, int D, int NB, bool EP>
+__device__ __forceinline__ void lookup_eval_full(const StepArgs<R> &a, const R *__restrict__ row, const R *x,
+                                                 R &y, R *z)
+{
+    constexpr int W = LookupWidth<R, D, NB, kLookupFull>::value;
+    R xi[D], rec[W];
+    load_record<R, W>(row + locate<R, D, NB, kLookupFull, EP>(a, x, xi), rec);
+#pragma unroll
+    for (int c = 0; c <= D; ++c) {
+        R v = rec[c * NB];
+        if constexpr (NB > 1) {
+#pragma unroll
+            for (int l = 0; l < D; ++l) v += rec[c * NB + 1 + l] * xi[l];
+        }
+        if (c == 0)
+            y = clamp_level<R>(v, a.clamp_y);
+        else
+            z[c - 1] = clamp_level<R>(v, a.clamp_z);
+    }
+}
+
 // X_{j+1} = X_j + b(X_j) dt + sigma dW_j (Algorithm "Euler dynamics", read with
 // the time index of the current step), with b(x)_l = b_l + b_lin_l x_l: exact
 // for constant b, the Euler scheme of the Ornstein-Uhlenbeck drift otherwise.
@@ -246,6 +269,39 @@ __device__ __forceinline__ R terminal_at(const StepArgs<R> &a, const R *x)
     return terminal_g<R>(a.terminal, a.T, s);
 }
 
+// The problem data of eq. (fbsde): drift, diffusion, driver and terminal
+// condition.  BuiltinModel is the compiled families (drift and diffusion
+// affine in the state, the linear and logistic drivers through sum_l z_l, the
+// cos and logistic terminals), read from StepArgs and the bsig block.  A model
+// compiled at run time from a caller's source (srmdp_model) has kUser = true
+// and supplies
+//   step(a, p, t, x, dW, xn)      X_{j+1} = X_j + b(t_j, X_j) dt + sigma(t_j, X_j) dW_j,
+//   driver(a, p, t, x, y, z)      f(t, x, y, z) with every component of z,
+//   terminal(a, p, x)             g(x),
+// with p its parameters (in the bsig block); its look-ups read whole records.
+struct BuiltinModel {
+    static constexpr bool kUser = false;
+};
+
+template <typename R, int D, class Model>
+__device__ __forceinline__ void model_step(const StepArgs<R> &a, const R *__restrict__ bsig, int j, const R *x,
+                                           const R *dW, R *xn)
+{
+    if constexpr (Model::kUser)
+        Model::template step<R, D>(a, bsig, (R)j * a.dt, x, dW, xn);
+    else
+        euler_step<R, D>(a, bsig, x, dW, xn);
+}
+
+template <typename R, int D, class Model>
+__device__ __forceinline__ R model_terminal(const StepArgs<R> &a, const R *__restrict__ bsig, const R *x)
+{
+    if constexpr (Model::kUser)
+        return Model::template terminal<R, D>(a, bsig, x);
+    else
+        return terminal_at<R, D>(a, x);
+}
+
 // The control-variate network as one wavefront sees it (unused without it).
 struct CvWave {
     MlpWeights w;
@@ -264,13 +320,14 @@ struct CvWave {
 // response; every lane of the wavefront must then run the same steps.
 // The first and last steps are peeled off so that the steady loop has no
 // branch that depends on j.
-template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false>
+template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false, class Model = BuiltinModel>
 __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
                                          const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
                                          R *dWi_out, R &y1, R &Sp, const CvWave *cv = nullptr,
                                          R *cvi = nullptr)
 {
     static_assert(!CV || sizeof(R) == 4, "the control variate runs in binary32");
+    static_assert(!Model::kUser || (LK == kLookupFull && !CV), "a model's driver reads whole records");
     constexpr int W = LookupWidth<R, D, NB, LK>::value;
     const int i = a.i, N = a.N;
     const size_t row_elems = (size_t)a.K * W;
@@ -289,12 +346,16 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         mlp_eval_z<D, D>(cv->w, cv->lane, (R)i * dt, x, zc);
         *cvi = cv_dot(dW);
     }
-    euler_step<R, D>(a, bsig, x, dW, xn);
+    model_step<R, D, Model>(a, bsig, i, x, dW, xn);
     R zsum_cur = (R)0;
+    R zv_cur[Model::kUser ? D : 1];  // z_j(X_j), every component (a model's driver)
     if (i + 1 < N) {
-        lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
+        if constexpr (Model::kUser)
+            lookup_eval_full<R, D, NB, EP>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zv_cur);
+        else
+            lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(i + 1) * row_elems, xn, y1, zsum_cur);
     } else {
-        y1 = terminal_at<R, D>(a, xn);
+        y1 = model_terminal<R, D, Model>(a, bsig, xn);
     }
 #pragma unroll
     for (int l = 0; l < D; ++l) {
@@ -308,11 +369,19 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
             if ((j - i) % a.cv_stride == 0) mlp_eval_z<D, D>(cv->w, cv->lane, (R)j * dt, x, zc);
             cv_tail += cv_dot(dW);
         }
-        euler_step<R, D>(a, bsig, x, dW, xn);
-        R yn, zn;
-        lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
-        S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
-        zsum_cur = zn;
+        model_step<R, D, Model>(a, bsig, j, x, dW, xn);
+        if constexpr (Model::kUser) {
+            R yn, zn[D];
+            lookup_eval_full<R, D, NB, EP>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
+            S += Model::template driver<R, D>(a, bsig, (R)j * dt, x, yn, zv_cur) * dt;
+#pragma unroll
+            for (int l = 0; l < D; ++l) zv_cur[l] = zn[l];
+        } else {
+            R yn, zn;
+            lookup_eval<R, D, NB, LK, EP>(a, lk + (size_t)(j + 1) * row_elems, xn, yn, zn);
+            S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+            zsum_cur = zn;
+        }
 #pragma unroll
         for (int l = 0; l < D; ++l) x[l] = xn[l];
     }
@@ -323,9 +392,12 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
             if ((N - 1 - i) % a.cv_stride == 0) mlp_eval_z<D, D>(cv->w, cv->lane, (R)(N - 1) * dt, x, zc);
             cv_tail += cv_dot(dW);
         }
-        euler_step<R, D>(a, bsig, x, dW, xn);
-        gN = terminal_at<R, D>(a, xn);
-        S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, gN, zsum_cur) * dt;
+        model_step<R, D, Model>(a, bsig, N - 1, x, dW, xn);
+        gN = model_terminal<R, D, Model>(a, bsig, xn);
+        if constexpr (Model::kUser)
+            S += Model::template driver<R, D>(a, bsig, (R)(N - 1) * dt, x, gN, zv_cur) * dt;
+        else
+            S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, gN, zsum_cur) * dt;
     } else {
         gN = y1;
     }
@@ -365,7 +437,7 @@ __device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R
 // With the control variate and z_center, *centre = y_{i+1}(X_i) (g(X_i) when
 // i + 1 = N): the fitted row i+1 of the stratum itself (X_i lies in it),
 // truncated, whose product with dW_i / dt has conditional mean zero.
-template <typename R, int D, int NB, int LK, bool CV, bool EP>
+template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel>
 __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
                                               uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
@@ -390,7 +462,7 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
     }
     NormalStream<R, D> ns;
     ns.init(Key{a.key0, a.key1}, m, k, a.tag, a.sqrt_dt);
-    run_path<R, D, NB, LK, CV, EP>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
+    run_path<R, D, NB, LK, CV, EP, Model>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
 }
 
 // Near-face diagnostic of step i: the positions of a simulation do not depend
@@ -398,7 +470,7 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
 // same Euler steps as the sweep, and stratum k is marked when one of its
 // simulations reaches a look-up point within face_eps of an interior face.
 // One wavefront per stratum.
-template <typename R, int D, int NB, bool EP>
+template <typename R, int D, int NB, bool EP, class Model = BuiltinModel>
 __global__ void __launch_bounds__(64) face_flags_kernel(const StepArgs<R> a,
                                                        const CellF<R> *__restrict__ cellF,
                                                        const R *__restrict__ bsig,
@@ -414,7 +486,7 @@ __global__ void __launch_bounds__(64) face_flags_kernel(const StepArgs<R> a,
         bool near = false;
         for (int j = a.i; j < a.N - 1; ++j) {
             ns.step((uint32_t)(j - a.i), dW);
-            euler_step<R, D>(a, bsig, x, dW, xn);
+            model_step<R, D, Model>(a, bsig, j, x, dW, xn);
             near |= near_face<R, D, EP>(a, xn);
 #pragma unroll
             for (int l = 0; l < D; ++l) x[l] = xn[l];
@@ -474,7 +546,7 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // With GR (global rows) the cloud rows and the chunk sums of a stratum live in
 // a.grow_bytes of global memory (clouds too large for LDS), and the launch
 // covers strata a.k0 .. a.k_end-1; LDS keeps the small binary64 arrays only.
-template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false>
+template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false, class Model = BuiltinModel>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
                                             const R *__restrict__ bsig, R *__restrict__ lk,
@@ -546,8 +618,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         for (int m = t; m < mend; m += L) {
             R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
             R Sp, y1, cvi, centre;
-            simulate_path<R, D, NB, LK, CV, EP>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp, y1,
-                                            &cv, &cvi, &centre);
+            simulate_path<R, D, NB, LK, CV, EP, Model>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp,
+                                                   y1, &cv, &cvi, &centre);
             row[NB + D + 1] = y1;
             if constexpr (CV) {
                 row[NB + D] = Sp - centre;
@@ -716,7 +788,25 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         }
     }
     __syncthreads();
-    if (live) {
+    if constexpr (Model::kUser) {
+        // a model's driver reads X_i itself: drawn again from the same
+        // counter (bit-identical to the cloud's start), and every z_{i,c}(X_i)
+        if (live) {
+            for (int m = t; m < M; m += L) {
+                R *row = rows + (size_t)m * SW;
+                R x[D], phi[NB], z[D];
+                sample_start<R, D, NB>(a, cellF, k, (uint32_t)m, x, phi);
+#pragma unroll 1
+                for (int c = 0; c < D; ++c) {
+                    R v = (R)0;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * row[b];
+                    z[c] = clamp_level<R>(v, a.clamp_z);
+                }
+                row[NB + D] += Model::template driver<R, D>(a, bsig, (R)a.i * a.dt, x, row[NB + D + 1], z) * a.dt;
+            }
+        }
+    } else if (live) {
         for (int m = t; m < M; m += L) {
             R *row = rows + (size_t)m * SW;
             R zs = (R)0;

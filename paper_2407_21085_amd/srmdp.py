@@ -34,6 +34,11 @@ class SrmdpError(RuntimeError):
         self.status = status
 
 
+class _Model(ctypes.Structure):
+    _fields_ = [("source", ctypes.c_char_p), ("params", ctypes.POINTER(ctypes.c_double)),
+                ("n_params", ctypes.c_int32)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [
         ("d", ctypes.c_int32), ("q", ctypes.c_int32),
@@ -44,6 +49,7 @@ class _Problem(ctypes.Structure):
         ("clamp_y", ctypes.c_double), ("clamp_z", ctypes.c_double),
         ("b_lin", ctypes.POINTER(ctypes.c_double)),
         ("sigma_lin", ctypes.POINTER(ctypes.c_double)),
+        ("model", ctypes.POINTER(_Model)),
     ]
 
 
@@ -174,6 +180,16 @@ def _darr(v: Sequence[float]):
 
 
 @dataclass
+class Model:
+    """A problem's own coefficients (srmdp_model): HIP device source defining
+    srmdp_b, srmdp_sigma_dw, srmdp_f and srmdp_g on `srmdp_real` (the drift,
+    the diffusion applied to dW, the driver and the terminal condition),
+    compiled at run time, and its parameters p[0..n-1]."""
+    source: str
+    params: Sequence[float] = ()
+
+
+@dataclass
 class Problem:
     """Problem data of eq. (fbsde)-(eds): drift b + diag(b_lin) x, diffusion
     sigma + diag(sigma_lin) x."""
@@ -191,6 +207,7 @@ class Problem:
     sigma: Optional[Sequence[float]] = None
     b_lin: Optional[Sequence[float]] = None   # drift b_l + b_lin_l x_l (Ornstein-Uhlenbeck)
     sigma_lin: Optional[Sequence[float]] = None   # diffusion sigma + diag(sigma_lin) x
+    model: Optional[Model] = None                 # own coefficients compiled at run time
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Problem:
@@ -214,6 +231,13 @@ class Problem:
             a = _darr(self.sigma_lin)
             self._keep.append(a)
             s.sigma_lin = ctypes.cast(a, ctypes.POINTER(ctypes.c_double))
+        if self.model is not None:
+            src = self.model.source.encode()
+            prm = _darr(self.model.params) if len(self.model.params) else None
+            m = _Model(src, ctypes.cast(prm, ctypes.POINTER(ctypes.c_double)) if prm is not None else None,
+                       len(self.model.params))
+            self._keep += [src, prm, m]
+            s.model = ctypes.pointer(m)
         return s
 
 

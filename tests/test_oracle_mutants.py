@@ -11,6 +11,7 @@ import oracle as O
 import test_oracle_closed_form as CF
 import test_oracle_equal_prob as EP
 import test_oracle_flip_bound as FB
+import test_oracle_model as MD
 import test_oracle_regression as RG
 import test_oracle_rng as RN
 
@@ -109,6 +110,18 @@ MUTANTS = [
      "for (int layer = 1; layer <= 2; ++layer)",
      "for (int layer = 1; layer <= 1; ++layer)",
      lambda: FB.test_flip_bound_covers_bfloat16_roundings_of_the_network(*FB.NET_CASES[0])),
+    ("model drift taken at t_{j+1}",
+     "P->model->b(j * dt, x, P->model->params, bj);",
+     "P->model->b((j + 1) * dt, x, P->model->params, bj);",
+     lambda: MD.test_time_dependent_model_fits_match_projection_of_closed_form(1, [16], 4, 20000)),
+    ("driver of the y response taken at t_{i+1}",
+     "double SY = Sp[m] + orc_driver(P, i * dt, x, y1[m], zfit) * dt - cvi[m];",
+     "double SY = Sp[m] + orc_driver(P, (i + 1) * dt, x, y1[m], zfit) * dt - cvi[m];",
+     lambda: MD.test_time_dependent_model_fits_match_projection_of_closed_form(1, [16], 4, 20000)),
+    ("model diffusion 5 % too large",
+     "P->model->sigma_dw(j * dt, x, dW, P->model->params, sj);",
+     "P->model->sigma_dw(j * dt, x, dW, P->model->params, sj);\n            for (int l = 0; l < d; ++l) sj[l] *= 1.05;",
+     lambda: MD.test_time_dependent_model_fits_match_projection_of_closed_form(1, [16], 4, 20000)),
     ("singular fallback divides by M - 1",
      "beta[0] = rhs[0] / M;\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
      "beta[0] = rhs[0] / (M - 1);\n    }\n    for (int a = 0; a < nb; ++a) rec[a] = beta[a];",
