@@ -18,7 +18,8 @@ def _S():
 def test_every_declared_function_is_exported():
     S = _S()
     header = open(os.path.join(ROOT, "include", "srmdp.h")).read()
-    declared = set(re.findall(r"\b(srmdp_[a-z_]+)\s*\(", header))
+    code = re.sub(r"/\*.*?\*/", "", header, flags=re.S)  # declarations only, not comments
+    declared = set(re.findall(r"\b(srmdp_[a-z_]+)\s*\(", code))
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
@@ -347,3 +348,39 @@ def test_noalloc_refuses_a_workspace_beyond_its_scratch():
     header = open(os.path.join(ROOT, "include", "srmdp.h")).read()
     assert re.search(r"#define SRMDP_NOALLOC_SCRATCH_BYTES \(\(size_t\)64 << 20\)", header)
     assert S.srmdp.NOALLOC_SCRATCH_BYTES == 64 << 20
+
+
+MODEL_BAD = [
+    ("empty source", dict(source=""), dict()),
+    ("too many parameters", dict(params=[0.0] * 65), dict()),
+    ("non-finite parameter", dict(params=[float("nan")]), dict()),
+    ("built-in coefficients beside a model", dict(), dict(r=0.5)),
+    ("built-in drift beside a model", dict(), dict(b=[0.1, 0.2])),
+]
+
+
+@pytest.mark.parametrize("name,mkw,pkw", MODEL_BAD, ids=[b[0] for b in MODEL_BAD])
+def test_model_arguments_rejected_before_compiling(name, mkw, pkw):
+    """A problem with its own coefficients is validated before anything is
+    compiled or enqueued."""
+    S = _S()
+    m = dict(source="__device__ void srmdp_b() {}", params=[0.1])
+    m.update(mkw)
+    P = S.Problem(d=2, N=4, model=S.Model(**m), **pkw)
+    G = S.Grid([-1.0] * 2, [1.0] * 2, [2, 2])
+    O = S.Options(M=16)
+    rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), O.c(), 16, 16, 1 << 40, None, None)
+    assert rc == S.srmdp.E_INVALID
+    assert S.srmdp.lib.srmdp_last_error().decode() != ""
+
+
+def test_model_refused_where_not_supported():
+    """Batches and the no-allocation entry point refuse a model before any
+    HIP call (compiling one allocates)."""
+    S = _S()
+    P = S.Problem(d=2, N=4, model=S.Model("__device__ void srmdp_b() {}"))
+    G = S.Grid([-1.0] * 2, [1.0] * 2, [2, 2])
+    O = S.Options(M=16)
+    rc = S.srmdp.lib.srmdp_solve_noalloc(P.c(), G.c(), O.c(), 16, None)
+    assert rc == S.srmdp.E_INVALID
+    assert "model" in S.srmdp.lib.srmdp_last_error().decode()

@@ -1,0 +1,328 @@
+"""Problems with their own coefficients on the GPU (srmdp_model: HIP source
+compiled at run time) against the oracle with the same coefficients written
+separately in C (tests/test_oracle_model.py pins that path of the oracle).
+
+* the built-in logistic and linear families restated as models;
+* the time-dependent model of the oracle's closed-form pin;
+* a general model: drift and diffusion depending on time and state, a full
+  state-dependent diffusion matrix, a driver nonlinear in y and depending on
+  x through each z component, and a terminal condition other than the
+  built-in ones.
+
+Binary64 sweeps at 1e-9 over every step; binary32 steps at 2e-4 plus the
+oracle's face-flip bound (it takes the model's Lipschitz constants in y and z).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import test_gpu_parity as TP
+import workloads as W
+from test_oracle_model import BUILTIN_PLUGIN, TIME_PLUGIN, builtin_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+BUILTIN_HIP = r"""
+// p: b[D], b_lin[D], Sigma[D][D], sigma_lin[D], T, r, kappa, logistic driver, logistic terminal
+__device__ void srmdp_b(srmdp_real t, const srmdp_real *x, const srmdp_real *p, srmdp_real *out)
+{
+    for (int l = 0; l < SRMDP_D; ++l) out[l] = p[l] + p[SRMDP_D + l] * x[l];
+}
+__device__ void srmdp_sigma_dw(srmdp_real t, const srmdp_real *x, const srmdp_real *dw, const srmdp_real *p,
+                               srmdp_real *out)
+{
+    const srmdp_real *S = p + 2 * SRMDP_D, *sl = p + 2 * SRMDP_D + SRMDP_D * SRMDP_D;
+    for (int l = 0; l < SRMDP_D; ++l) {
+        srmdp_real acc = 0;
+        for (int c = 0; c < SRMDP_D; ++c) acc += S[l * SRMDP_D + c] * dw[c];
+        out[l] = acc + sl[l] * x[l] * dw[l];
+    }
+}
+__device__ srmdp_real srmdp_f(srmdp_real t, const srmdp_real *x, srmdp_real y, const srmdp_real *z,
+                              const srmdp_real *p)
+{
+    const srmdp_real *q = p + 3 * SRMDP_D + SRMDP_D * SRMDP_D;
+    srmdp_real sz = 0;
+    for (int l = 0; l < SRMDP_D; ++l) sz += z[l];
+    if (q[3] != 0) return sz * (y - (srmdp_real)(2.0 + SRMDP_D) / (srmdp_real)(2.0 * SRMDP_D));
+    return -q[1] * y + q[2] * sz;
+}
+__device__ srmdp_real srmdp_g(const srmdp_real *x, const srmdp_real *p)
+{
+    const srmdp_real *q = p + 3 * SRMDP_D + SRMDP_D * SRMDP_D;
+    srmdp_real s = 0;
+    for (int l = 0; l < SRMDP_D; ++l) s += x[l];
+    if (q[4] != 0) {
+        srmdp_real w = exp(q[0] + s);
+        return w / (1 + w);
+    }
+    return cos(s);
+}
+"""
+
+TIME_HIP = r"""
+// p: a0, a1, s, h0, h1: b = a0 + a1 t, sigma = s I, f = (h0 + h1 t) cos(x_1), g = cos(sum x)
+__device__ void srmdp_b(srmdp_real t, const srmdp_real *x, const srmdp_real *p, srmdp_real *out)
+{
+    for (int l = 0; l < SRMDP_D; ++l) out[l] = p[0] + p[1] * t;
+}
+__device__ void srmdp_sigma_dw(srmdp_real t, const srmdp_real *x, const srmdp_real *dw, const srmdp_real *p,
+                               srmdp_real *out)
+{
+    for (int l = 0; l < SRMDP_D; ++l) out[l] = p[2] * dw[l];
+}
+__device__ srmdp_real srmdp_f(srmdp_real t, const srmdp_real *x, srmdp_real y, const srmdp_real *z,
+                              const srmdp_real *p)
+{
+    return (p[3] + p[4] * t) * cos(x[0]);
+}
+__device__ srmdp_real srmdp_g(const srmdp_real *x, const srmdp_real *p)
+{
+    srmdp_real s = 0;
+    for (int l = 0; l < SRMDP_D; ++l) s += x[l];
+    return cos(s);
+}
+"""
+
+# General model, p = (beta, kappa, eps, rho, r, c, e):
+#   b_l(t, x) = beta sin(t + x_l) - kappa x_l
+#   sigma(t, x)_{l,c} = (1 + rho t) (delta_lc + eps tanh(x_c) (l + 1) / (c + 2))
+#   f(t, x, y, z) = -r y + c sum_l z_l cos(x_l) + e sin(t) y^2
+#   g(x) = cos(sum x) / (1 + 0.1 |x|^2)
+GENERAL_HIP = r"""
+__device__ void srmdp_b(srmdp_real t, const srmdp_real *x, const srmdp_real *p, srmdp_real *out)
+{
+    for (int l = 0; l < SRMDP_D; ++l) out[l] = p[0] * sin(t + x[l]) - p[1] * x[l];
+}
+__device__ void srmdp_sigma_dw(srmdp_real t, const srmdp_real *x, const srmdp_real *dw, const srmdp_real *p,
+                               srmdp_real *out)
+{
+    const srmdp_real scale = 1 + p[3] * t;
+    for (int l = 0; l < SRMDP_D; ++l) {
+        srmdp_real acc = 0;
+        for (int c = 0; c < SRMDP_D; ++c) {
+            const srmdp_real s = (l == c ? (srmdp_real)1 : (srmdp_real)0) +
+                                 p[2] * tanh(x[c]) * (srmdp_real)(l + 1) / (srmdp_real)(c + 2);
+            acc += s * dw[c];
+        }
+        out[l] = scale * acc;
+    }
+}
+__device__ srmdp_real srmdp_f(srmdp_real t, const srmdp_real *x, srmdp_real y, const srmdp_real *z,
+                              const srmdp_real *p)
+{
+    srmdp_real s = 0;
+    for (int l = 0; l < SRMDP_D; ++l) s += z[l] * cos(x[l]);
+    return -p[4] * y + p[5] * s + p[6] * sin(t) * y * y;
+}
+__device__ srmdp_real srmdp_g(const srmdp_real *x, const srmdp_real *p)
+{
+    srmdp_real s = 0, r2 = 0;
+    for (int l = 0; l < SRMDP_D; ++l) {
+        s += x[l];
+        r2 += x[l] * x[l];
+    }
+    return cos(s) / (1 + (srmdp_real)0.1 * r2);
+}
+"""
+
+GENERAL_C = r"""
+#include <math.h>
+#define D MODEL_D
+void model_b(double t, const double *x, const double *p, double *out)
+{
+    for (int l = 0; l < D; ++l) out[l] = p[0] * sin(t + x[l]) - p[1] * x[l];
+}
+void model_sigma_dw(double t, const double *x, const double *dw, const double *p, double *out)
+{
+    double scale = 1.0 + p[3] * t;
+    for (int l = 0; l < D; ++l) {
+        double acc = 0.0;
+        for (int c = 0; c < D; ++c)
+            acc += ((l == c ? 1.0 : 0.0) + p[2] * tanh(x[c]) * (double)(l + 1) / (double)(c + 2)) * dw[c];
+        out[l] = scale * acc;
+    }
+}
+double model_f(double t, const double *x, double y, const double *z, const double *p)
+{
+    double s = 0.0;
+    for (int l = 0; l < D; ++l) s += z[l] * cos(x[l]);
+    return -p[4] * y + p[5] * s + p[6] * sin(t) * y * y;
+}
+double model_g(const double *x, const double *p)
+{
+    (void)p;
+    double s = 0.0, r2 = 0.0;
+    for (int l = 0; l < D; ++l) {
+        s += x[l];
+        r2 += x[l] * x[l];
+    }
+    return cos(s) / (1.0 + 0.1 * r2);
+}
+"""
+
+GENERAL_PARAMS = [0.3, 0.4, 0.15, 0.5, 0.2, 0.3, 0.25]
+# |df/dy| <= r + 2 e |y| and |df/dz_l| <= c, with |y| <= 1.5 on these runs
+GENERAL_LIP = (0.2 + 2 * 0.25 * 1.5, 0.3)
+TIME_PARAMS = [0.3, -0.8, 0.7, 0.4, 1.5]
+
+
+def _cases():
+    coef3 = dict(b=[0.1, -0.2, 0.05], b_lin=[-0.5, 0.2, 0.0],
+                 sigma=[0.9, 0.1, -0.05, 0.0, 1.1, 0.2, 0.15, -0.1, 0.8], sigma_lin=[0.3, 0.0, -0.2])
+    p3 = builtin_params(3, coef3["b"], coef3["b_lin"], np.reshape(coef3["sigma"], (3, 3)), coef3["sigma_lin"],
+                        1.0, 0.0, 0.0, True, True)
+    coef2 = dict(b=[0.2, -0.1], b_lin=[0.0, -0.7], sigma=[1.0, 0.3, -0.2, 0.7], sigma_lin=[0.0, 0.4])
+    p2 = builtin_params(2, coef2["b"], coef2["b_lin"], np.reshape(coef2["sigma"], (2, 2)), coef2["sigma_lin"],
+                        1.0, 0.3, 0.4, False, False)
+    return [
+        # (name, d, cells, N, M, basis, HIP source, C source, params, (lip_y, lip_z), clamp_z)
+        ("builtin logistic restated d=3", 3, [3, 3, 3], 4, 40, "LP1", BUILTIN_HIP, BUILTIN_PLUGIN, p3,
+         (1.0, 2.0), None),
+        ("builtin linear restated d=2", 2, [4, 3], 5, 50, "LP1", BUILTIN_HIP, BUILTIN_PLUGIN, p2, (0.3, 0.4), None),
+        ("time-dependent d=2", 2, [5, 4], 5, 64, "LP1", TIME_HIP, TIME_PLUGIN, TIME_PARAMS, (0.0, 0.0), None),
+        ("general d=4", 4, [2, 3, 2, 2], 5, 48, "LP1", GENERAL_HIP, GENERAL_C, GENERAL_PARAMS, GENERAL_LIP, None),
+        ("general d=3 lp0 truncated z", 3, [3, 2, 3], 4, 32, "LP0", GENERAL_HIP, GENERAL_C, GENERAL_PARAMS,
+         GENERAL_LIP, 0.4),
+        ("general d=8", 8, [2] * 8, 3, 64, "LP1", GENERAL_HIP, GENERAL_C, GENERAL_PARAMS, GENERAL_LIP, None),
+    ]
+
+
+CASES = _cases()
+
+
+def _cfg(name, d, cells, N, M, basis, prec, clamp_z):
+    cfg = dict(W.config("cfg1"), name=name, d=d, N=N, lo=[-2.0] * d, hi=[2.0] * d, cells=cells, M=M,
+               basis=basis, prec=prec, seed=21, x0=[0.0] * d)
+    if clamp_z is not None:
+        cfg["clamp_z"] = clamp_z
+    return cfg
+
+
+def _oracle_problem(cfg, csrc, params, lip, **kw):
+    from sides import oracle_problem
+    Po = oracle_problem(cfg, **kw)
+    Po.driver, Po.terminal, Po.r, Po.kappa = 0, 0, 0.0, 0.0
+    Po.model = O.Model(csrc, params, lip_y=lip[0], lip_z=lip[1])
+    return Po
+
+
+def _product(cfg, hip, params, **kw):
+    import paper_2407_21085_amd as S
+    from sides import product_args
+    P, G, Opt = product_args(cfg, **kw)
+    P.driver, P.terminal, P.r, P.kappa = 0, 0, 0.0, 0.0
+    P.model = S.Model(hip, list(params))
+    return P, G, Opt
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_model_fp64_sweep_matches_oracle(case):
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = case
+    cfg = _cfg(name, d, cells, N, M, basis, "fp64", clamp_z)
+    orc, sing = O.solve(_oracle_problem(cfg, csrc, params, lip))
+    P, G, Opt = _product(cfg, hip, params)
+    _say(f"[gpu] model {name}: binary64 sweep (compiled at run time)")
+    table, stats = S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    gpu = table.cpu().numpy()
+    assert stats["singular_cubes"] == sing
+    err = TP.parity(gpu, orc, range(N))
+    _say(f"[gpu] model {name}: parity {err:.3e}")
+    assert err <= TP.TOL["fp64"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_model_fp32_steps_match_oracle(case):
+    """Each step from the oracle's rows above it, at 2e-4 plus the face-flip
+    bound; the near-face diagnostic runs the model's own kernel."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = case
+    cfg = _cfg(name, d, cells, N, M, basis, "fp32", clamp_z)
+    K, eps = int(np.prod(cells)), 2e-6
+    f_orc = np.zeros((N, K), dtype=np.uint8)
+    Po = _oracle_problem(cfg, csrc, params, lip, face_flags=f_orc, face_eps=eps)
+    Po.flip_bound = np.zeros(Po.table_shape())
+    orc, _ = O.solve(Po)
+    err, excess = 0.0, -np.inf
+    for i in range(N - 1, -1, -1):
+        P, G, Opt = _product(cfg, hip, params, step_hi=i, step_lo=i)
+        f_gpu = torch.zeros((N, K), dtype=torch.uint8, device="cuda")
+        Opt.face_flags, Opt.face_eps = f_gpu, eps
+        table = torch.from_numpy(orc).to(torch.float32).cuda()
+        _say(f"[gpu] model {name}: binary32 step {i}")
+        S.solve(P, G, Opt, table=table)
+        torch.cuda.synchronize()
+        flags = f_orc | f_gpu.cpu().numpy()
+        e, x = TP.bounded_parity(table.double().cpu().numpy(), orc, Po.flip_bound, [i], flags, TP.TOL["fp32"])
+        err, excess = max(err, e), max(excess, x)
+    _say(f"[gpu] model {name}: binary32 per-step parity {err:.3e}, worst excess {excess:.3e}")
+    assert err <= TP.TOL["fp32"]
+    assert excess <= 0.0
+
+
+def test_model_parameters_change_without_recompiling_and_graphs_replay():
+    """New parameter values reuse the compiled kernels (a second sweep is fast)
+    and give the oracle's table for those values; a captured graph replays the
+    model's launches three times, each equal to the direct sweep."""
+    import time
+
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = CASES[3]
+    cfg = _cfg(name, d, cells, N, M, basis, "fp64", clamp_z)
+    P, G, Opt = _product(cfg, hip, params)
+    S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    params2 = [v * 1.1 for v in params]
+    P2, G2, Opt2 = _product(cfg, hip, params2)
+    t0 = time.perf_counter()
+    table, _ = S.solve(P2, G2, Opt2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _say(f"[gpu] second model sweep with new parameters: {dt * 1e3:.1f} ms")
+    assert dt < 0.5
+    orc, _ = O.solve(_oracle_problem(cfg, csrc, params2, lip))
+    assert TP.parity(table.cpu().numpy(), orc, range(N)) <= TP.TOL["fp64"]
+    ref = table.cpu().numpy()
+    Pg, Gg, Og = _product(cfg, hip, params2, flags=S.F_GRAPH)
+    stream = torch.cuda.Stream()
+    tg = S.srmdp.alloc_table(Pg, Gg, Og)
+    ws = S.srmdp.alloc_workspace(Pg, Gg, Og)
+    for rep in range(3):
+        tg.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            S.solve(Pg, Gg, Og, table=tg, workspace=ws, stream=stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(tg.cpu().numpy(), ref)
+    S.release_graphs()
+
+
+def test_model_errors_are_reported():
+    """A source that does not compile returns SRMDP_E_INVALID with the
+    compiler's message; the ROOT read-out refuses a model (SRMDP_E_UNSUPPORTED)."""
+    import paper_2407_21085_amd as S
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = CASES[2]
+    cfg = _cfg(name, d, cells, N, M, basis, "fp64", clamp_z)
+    P, G, Opt = _product(cfg, hip.replace("return cos(s);", "return cos(s) +;"), params)
+    with pytest.raises(S.SrmdpError) as e:
+        S.solve(P, G, Opt)
+    assert e.value.status == S.srmdp.E_INVALID
+    assert "does not compile" in str(e.value)
+    P, G, Opt = _product(cfg, hip, params)
+    table, _ = S.solve(P, G, Opt)
+    with pytest.raises(S.SrmdpError) as e:
+        S.root(P, G, Opt, table, [0.0] * d, 1000)
+    assert e.value.status == S.srmdp.E_UNSUPPORTED
