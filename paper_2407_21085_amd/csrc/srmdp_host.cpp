@@ -452,10 +452,12 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
     const bool force = (o && (o->flags & SRMDP_F_GLOBAL_ROWS)) || !lds_dimension_compiled(s.d);
     if (force || per_cube > lds_cap) {
         ls.grows = true;
-        per_cube = align_up(cube_lds_bytes(is_float, s.d, nb, M, false, true), 16);
-        ls.grow_bytes = cube_global_bytes(is_float, s.d, nb, M);
+        const int pb = cube_stream_chunks(is_float, s.d, nb, L, lds_cap);
+        if (pb < 1) return false;
+        per_cube = align_up(cube_stream_lds_bytes(is_float, s.d, nb, L, pb), 16);
+        ls.grow_bytes = cube_global_bytes(is_float, M);
         ls.kc = grows_strata(s, ls.grow_bytes, o);
-        ls.stage_chunks = cube_stage_chunks(is_float, s.d, nb, M);
+        ls.stage_chunks = pb;
     }
     int cpw = std::max(1, 64 / L);
     while (cpw > 1 && (size_t)cpw * per_cube > lds_cap) cpw /= 2;

@@ -79,7 +79,7 @@ struct StepArgs {
     uint32_t k0, k_end;
     unsigned char *grows;
     size_t grow_bytes;
-    int stage_chunks;  // chunks of rows per LDS window of the sums
+    int stage_chunks;  // streamed clouds: chunks whose partial sums are formed together
     uint32_t debug_singular;  // stratum whose Gram is zeroed in this launch (test aid), or ~0u
 };
 
@@ -108,7 +108,7 @@ struct LaunchShape {
     bool grows;                // clouds in global memory, launches of `kc` strata
     uint32_t kc;
     size_t grow_bytes;         // global bytes per stratum
-    int stage_chunks;          // chunks per LDS window of the sums
+    int stage_chunks;          // streamed clouds: chunks whose partial sums are formed together
 };
 
 #if !defined(__HIPCC_RTC__)  // host launchers
@@ -247,12 +247,14 @@ hipError_t launch_model_face_flags(const ModelKernels &k, const StepArgs<R> &a, 
 // Dimensions with the LDS sweep kernel, and every dimension compiled at all.
 bool lds_dimension_compiled(int d);
 bool dimension_compiled(int d);
-// LDS bytes of one stratum's regression; with grows the cloud rows and chunk
-// sums are in global memory (cube_global_bytes per stratum) instead.
-size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false, bool grows = false);
-size_t cube_global_bytes(int prec_is_float, int d, int nb, int M);
-// Chunks of rows in the LDS window through which the sums read a global cloud.
-int cube_stage_chunks(int prec_is_float, int d, int nb, int M);
+// LDS bytes of one stratum's regression with its cloud in LDS.
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv = false);
+// Streamed clouds (too large for LDS): LDS bytes of one stratum with L lanes
+// and the partial sums of pb chunks at a time; the largest pb whose LDS fits
+// in `cap` (0 if none); global bytes per stratum (S' and y_{i+1} per sample).
+size_t cube_stream_lds_bytes(int prec_is_float, int d, int nb, int L, int pb);
+int cube_stream_chunks(int prec_is_float, int d, int nb, int L, size_t cap);
+size_t cube_global_bytes(int prec_is_float, int M);
 template <typename R>
 hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,

@@ -225,29 +225,42 @@ static size_t cube_part_bytes(int d, int nb, int M)
     return nch > 1 ? (size_t)(nb * (nb + 1) / 2 + d * nb) * nch * sizeof(double) : 0;
 }
 
-size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv, bool grows)
+// The stratum's cell constants (CellF, four values of the working precision per
+// dimension), first in a stratum's LDS.
+static size_t cube_cell_bytes(int prec_is_float, int d)
+{
+    return ((size_t)d * 4 * (prec_is_float ? 4 : 8) + 15) & ~(size_t)15;
+}
+
+size_t cube_lds_bytes(int prec_is_float, int d, int nb, int M, bool cv)
 {
     const size_t small = (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
-    if (grows) {  // binary64 arrays, then the window of rows
-        const size_t rsz = prec_is_float ? 4 : 8;
-        return ((small + 15) & ~(size_t)15) +
-               (size_t)cube_stage_chunks(prec_is_float, d, nb, M) * kChunk * (nb + d + 2) * rsz;
-    }
-    return cube_row_bytes(prec_is_float, d, nb, M, cv) + small + cube_part_bytes(d, nb, M);
+    return cube_cell_bytes(prec_is_float, d) + cube_row_bytes(prec_is_float, d, nb, M, cv) + small +
+           cube_part_bytes(d, nb, M);
 }
 
-int cube_stage_chunks(int prec_is_float, int d, int nb, int M)
+size_t cube_stream_lds_bytes(int prec_is_float, int d, int nb, int L, int pb)
 {
     const size_t rsz = prec_is_float ? 4 : 8;
-    const int fit = (int)(kStageBytes / ((size_t)kChunk * (nb + d + 2) * rsz));
-    const int nch = (M + kChunk - 1) / kChunk;
-    return fit < 1 ? 1 : (fit < nch ? fit : nch);
+    const size_t small = (size_t)(2 * nb * nb + 2 * (1 + d) * nb + 2 + nb) * sizeof(double);
+    const size_t part = (size_t)(nb * (nb + 1) / 2 + d * nb) * pb * sizeof(double);
+    const int RS = L >= kChunk ? L : kChunk;
+    return cube_cell_bytes(prec_is_float, d) + ((small + part + 15) & ~(size_t)15) +
+           (size_t)RS * (nb + d + 2) * rsz;
 }
 
-size_t cube_global_bytes(int prec_is_float, int d, int nb, int M)
+int cube_stream_chunks(int prec_is_float, int d, int nb, int L, size_t cap)
 {
-    const size_t b = cube_row_bytes(prec_is_float, d, nb, M, false) + cube_part_bytes(d, nb, M);
-    return (b + 255) & ~(size_t)255;
+    const int RS = L >= kChunk ? L : kChunk;
+    int pb = RS / kChunk;
+    while (pb > 1 && cube_stream_lds_bytes(prec_is_float, d, nb, L, pb) > cap) --pb;
+    return cube_stream_lds_bytes(prec_is_float, d, nb, L, pb) <= cap ? pb : 0;
+}
+
+size_t cube_global_bytes(int prec_is_float, int M)
+{
+    const size_t rsz = prec_is_float ? 4 : 8;
+    return ((size_t)M * 2 * rsz + 255) & ~(size_t)255;  // S' and y_{i+1}(X_{i+1}) per sample
 }
 
 #define SRMDP_INSTANTIATE(R)                                                                        \

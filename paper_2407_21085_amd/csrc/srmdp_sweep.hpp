@@ -408,9 +408,9 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
 // "stratify" (phi(X_i) to full precision from the centred offset), then
 // run_path.  phi(X_i) and dW_i go to the stratum's LDS row as soon as they are
 // known, so they do not occupy registers during the path.
-template <typename R, int D, int NB>
-__device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
-                                             uint32_t k, uint32_t m, R *x, R *phi_out)
+template <typename R, int D, int NB, typename CellAt>
+__device__ __forceinline__ void sample_start_with(const StepArgs<R> &a, CellAt cell_at, uint32_t k, uint32_t m,
+                                                  R *x, R *phi_out)
 {
     const Key key{a.key0, a.key1};
 #pragma unroll
@@ -421,8 +421,7 @@ __device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R
         for (int t = 0; t < 4; ++t) {
             const int l = 4 * b + t;
             if (l < D) {
-                const uint32_t cell = (k / a.stride[l]) % a.cells[l];
-                const CellF<R> cf = cellF[l * a.cmax + cell];
+                const CellF<R> cf = cell_at(l);
                 const R off = stratified_offset<R>(cf, open_uniform<R>(ws[t]), a.inv_mu);
                 x[l] = cf.centre + off;
                 // xi = 2 scale (x - centre): 2 (x - c) / h, or mu times the offset
@@ -434,17 +433,43 @@ __device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R
     phi_out[0] = (R)1;
 }
 
+// The cell constants of stratum k along dimension l.
+template <typename R>
+__device__ __forceinline__ CellF<R> stratum_cell(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF, uint32_t k,
+                                                 int l)
+{
+    return cellF[l * a.cmax + (k / a.stride[l]) % a.cells[l]];
+}
+
+// Start point from the sampler's table (cell of each dimension from k).
+template <typename R, int D, int NB>
+__device__ __forceinline__ void sample_start(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
+                                             uint32_t k, uint32_t m, R *x, R *phi_out)
+{
+    sample_start_with<R, D, NB>(a, [&](int l) { return stratum_cell<R>(a, cellF, k, l); }, k, m, x, phi_out);
+}
+
+// Start point from the stratum's own cell constants scf[0..D-1] (stratum_cell
+// of every dimension, formed once per stratum in LDS by the sweep).
+template <typename R, int D, int NB>
+__device__ __forceinline__ void sample_start_cached(const StepArgs<R> &a, const CellF<R> *scf, uint32_t k,
+                                                    uint32_t m, R *x, R *phi_out)
+{
+    sample_start_with<R, D, NB>(a, [&](int l) { return scf[l]; }, k, m, x, phi_out);
+}
+
 // With the control variate and z_center, *centre = y_{i+1}(X_i) (g(X_i) when
 // i + 1 = N): the fitted row i+1 of the stratum itself (X_i lies in it),
 // truncated, whose product with dW_i / dt has conditional mean zero.
+// scf: the stratum's cell constants (sample_start_cached).
 template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel>
-__device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *__restrict__ cellF,
+__device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *scf,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
                                               uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
                                               R &Sp, R &y1, const CvWave *cv, R *cvi, R *centre)
 {
     R x[D];
-    sample_start<R, D, NB>(a, cellF, k, m, x, phi_out);
+    sample_start_cached<R, D, NB>(a, scf, k, m, x, phi_out);
     if constexpr (CV) {
         R c = (R)0;
         if (a.z_center) {
@@ -525,9 +550,6 @@ struct CubeLds {
 // than one chunk the chunk sums (one per lane and entry, in parallel) are
 // added in chunk order.  The order depends on M only, not on the lanes.
 constexpr int kChunk = 64;
-// With the cloud in global memory, the sums read it through an LDS window of
-// a.stage_chunks chunks (about kStageBytes), copied in with coalesced loads.
-constexpr int kStageBytes = 32 * 1024;
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so block b
 // runs on XCD b % 8.  Give each XCD a contiguous range of strata so that
@@ -543,9 +565,17 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // One group of strata of backward step a.i: the workgroup's cpw = blockDim / L
 // strata k = group * cpw + slot, L = a.lanes lanes each.  Shared by the
 // per-step kernel and the batched (several instances) kernel.
-// With GR (global rows) the cloud rows and the chunk sums of a stratum live in
-// a.grow_bytes of global memory (clouds too large for LDS), and the launch
-// covers strata a.k0 .. a.k_end-1; LDS keeps the small binary64 arrays only.
+//
+// Clouds in LDS (GR = false): the M rows of regression inputs of a stratum are
+// held in LDS, then the sums run over them.
+// Streamed clouds (GR = true, clouds too large for LDS): the samples are
+// simulated in rounds of RS = max(L, kChunk) (whole chunks); a round's rows
+// live in an LDS window, their chunk sums are added to running sums in chunk
+// order (the same additions, in the same order, as the LDS form), and only
+// S' and y_{i+1}(X_{i+1}) of each sample go to global memory (a.grows,
+// a.grow_bytes per stratum).  The y pass draws X_i and phi(X_i) again from the
+// same counter and reads S', y_{i+1} back.  The launch covers strata
+// a.k0 .. a.k_end-1.
 template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false, class Model = BuiltinModel>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
@@ -554,6 +584,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                                             unsigned long long *__restrict__ counters,
                                             unsigned char *smem)
 {
+    static_assert(!(GR && (CV || Model::kUser)), "streamed clouds run without the control variate or a model");
     using Lay = CubeLds<R, D, NB, CV>;
     constexpr int SW = Lay::SW;
     constexpr int REC = (1 + D) * NB;
@@ -581,14 +612,29 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         __syncthreads();
     }
     unsigned char *base = smem + (CV ? kPackedFwdBytes : 0) + (size_t)slot * a.lds_per_cube;
+    // The stratum's cell constants along each dimension, formed once here for
+    // every start point of the stratum (slots past the last stratum: K - 1).
+    CellF<R> *scf = reinterpret_cast<CellF<R> *>(base);
+    base += (D * sizeof(CellF<R>) + 15) & ~(size_t)15;
+    {
+        const uint32_t ks = live ? k : a.K - 1;
+        for (int l = t; l < D; l += L) scf[l] = stratum_cell<R>(a, cellF, ks, l);
+    }
+    __syncthreads();
     const size_t row_bytes = ((size_t)(CV ? M + 1 : M) * SW * sizeof(R) + 15) & ~(size_t)15;
+    constexpr int NG = NB * (NB + 1) / 2;
+    constexpr int NE = Lay::NE;
+    // LDS form: rows [M][SW], then the binary64 arrays, then the chunk sums.
+    // Streamed form: the binary64 arrays, the partial sums of a.stage_chunks
+    // chunks, then the window of RS rows; S', y1 per sample in global memory.
     R *rows;
     double *f64;
-    unsigned char *gbase = nullptr;
+    R *sy = nullptr;
     if constexpr (GR) {
-        gbase = a.grows + (size_t)(group * (uint32_t)cpw + (uint32_t)slot) * a.grow_bytes;
-        rows = reinterpret_cast<R *>(gbase);
+        sy = reinterpret_cast<R *>(a.grows + (size_t)(group * (uint32_t)cpw + (uint32_t)slot) * a.grow_bytes);
         f64 = reinterpret_cast<double *>(base);
+        rows = reinterpret_cast<R *>(base + ((sizeof(double) * ((size_t)Lay::F64 + (size_t)NE * a.stage_chunks) +
+                                              15) & ~(size_t)15));
     } else {
         rows = reinterpret_cast<R *>(base);
         f64 = reinterpret_cast<double *>(base + row_bytes);
@@ -599,43 +645,12 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     double *beta = RHS + REC;
     double *flag = beta + REC;
     double *zsum = flag + 2;
-    // [entries][chunks] partial sums when M > kChunk
-    double *part = GR ? reinterpret_cast<double *>(gbase + row_bytes) : zsum + NB;
+    // [entries][chunks] partial sums when M > kChunk (streamed: [entries][a.stage_chunks])
+    double *part = zsum + NB;
     const int nch = (M + kChunk - 1) / kChunk;
-    // GR: LDS window of kStageChunks chunks of rows, after the binary64 arrays
-    R *stage = GR ? reinterpret_cast<R *>(base + ((sizeof(double) * (size_t)Lay::F64 + 15) & ~(size_t)15))
-                  : nullptr;
 
-    // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The
-    //    network needs every lane of a wavefront, so with the control variate
-    //    the slots past the last stratum simulate stratum K-1 and discard it,
-    //    and every lane makes ceil(M / L) trips: the lanes past simulation M-1
-    //    simulate one more (index >= M, a stream of its own) into the spare
-    //    row M, which nothing reads.
-    if (live || CV) {
-        const uint32_t ks = live ? k : a.K - 1;
-        const int mend = CV ? (M + L - 1) / L * L : M;
-        for (int m = t; m < mend; m += L) {
-            R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
-            R Sp, y1, cvi, centre;
-            simulate_path<R, D, NB, LK, CV, EP, Model>(a, cellF, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp,
-                                                   y1, &cv, &cvi, &centre);
-            row[NB + D + 1] = y1;
-            if constexpr (CV) {
-                row[NB + D] = Sp - centre;
-                row[NB + D + 2] = cvi;
-                row[NB + D + 3] = centre;
-            } else {
-                row[NB + D] = Sp;
-            }
-        }
-    }
-    __syncthreads();
-
-    // 2. Gram entries (a <= b) and z right-hand sides: binary64 sums over the
-    //    M samples, one (entry, chunk) pair per lane, then the chunks in order.
-    constexpr int NG = NB * (NB + 1) / 2;
-    constexpr int NE = Lay::NE;
+    // Gram entries (a <= b) and z right-hand sides: binary64 sums over samples
+    // m0..m1-1 of a block of rows, in sample order.
     auto gram_sum = [&](const R *rb, int e, int m0, int m1) {
         double acc = 0.0;
         if (e < NG) {
@@ -658,10 +673,18 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         }
         return acc;
     };
-    // GR: copy rows m0..m1-1 of the cloud into the LDS window (whole workgroup)
-    auto stage_rows = [&](int m0, int m1) {
-        if (live)
-            for (int e = t; e < (m1 - m0) * SW; e += L) stage[e] = rows[(size_t)m0 * SW + e];
+    // Where entry e is kept: the upper triangle of G, or the z right-hand side.
+    auto entry_slot = [&](int e) -> double * {
+        if (e < NG) {
+            int r = 0, rem = e;
+            while (rem >= NB - r) {
+                rem -= NB - r;
+                ++r;
+            }
+            return G + r * NB + r + rem;
+        }
+        const int l = (e - NG) / NB, b = (e - NG) % NB;
+        return RHS + (1 + l) * NB + b;
     };
     auto gram_store = [&](int e, double acc) {
         if (e < NG) {
@@ -679,25 +702,93 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             RHS[(1 + l) * NB + b] = acc * a.inv_dt;
         }
     };
+
     if constexpr (GR) {
-        for (int c0 = 0; c0 < nch; c0 += a.stage_chunks) {
-            const int c1 = min(nch, c0 + a.stage_chunks), m0 = c0 * kChunk, m1 = min(M, c1 * kChunk);
-            stage_rows(m0, m1);
-            __syncthreads();
+        // 1-2 (streamed). Rounds of RS samples: simulate into the window, then
+        //    add the round's chunk sums (a.stage_chunks chunks at a time) to the
+        //    running sums kept in place, in chunk order.
+        const int RS = L >= kChunk ? L : kChunk;
+        const int pb = a.stage_chunks;
+        if (live) {
+            for (int e = t; e < NB * NB; e += L) G[e] = 0.0;
+            for (int e = t; e < REC; e += L) RHS[e] = 0.0;
+        }
+        for (int r0 = 0; r0 < M; r0 += RS) {
+            const int rn = min(RS, M - r0);
             if (live) {
-                if (nch == 1) {
-                    for (int e = t; e < NE; e += L) gram_store(e, gram_sum(stage, e, 0, M));
-                } else {
-                    const int ncs = c1 - c0;
-                    for (int w = t; w < NE * ncs; w += L) {
-                        const int e = w / ncs, c = c0 + w % ncs;
-                        part[e * nch + c] = gram_sum(stage, e, c * kChunk - m0, min(M, (c + 1) * kChunk) - m0);
-                    }
+                for (int u = t; u < rn; u += L) {
+                    const int m = r0 + u;
+                    R *row = rows + (size_t)u * SW;
+                    R Sp, y1, cvi, centre;
+                    simulate_path<R, D, NB, LK, false, EP>(a, scf, bsig, lk, k, (uint32_t)m, row, row + NB, Sp,
+                                                           y1, &cv, &cvi, &centre);
+                    row[NB + D] = Sp;
+                    row[NB + D + 1] = y1;
+                    sy[2 * (size_t)m] = Sp;
+                    sy[2 * (size_t)m + 1] = y1;
                 }
             }
             __syncthreads();
+            const int rc = (rn + kChunk - 1) / kChunk;
+            for (int c0 = 0; c0 < rc; c0 += pb) {
+                const int nbc = min(pb, rc - c0);
+                if (live)
+                    for (int w = t; w < NE * nbc; w += L) {
+                        const int e = w / nbc, c = c0 + w % nbc;
+                        part[w] = gram_sum(rows, e, c * kChunk, min(rn, (c + 1) * kChunk));
+                    }
+                __syncthreads();
+                if (live)
+                    for (int e = t; e < NE; e += L) {
+                        double *acc = entry_slot(e);
+                        double v = *acc;
+                        for (int c = 0; c < nbc; ++c) v += part[e * nbc + c];
+                        *acc = v;
+                    }
+                __syncthreads();
+            }
         }
-        if (nch > 1) {
+        if (live)
+            for (int e = t; e < NE; e += L) gram_store(e, *entry_slot(e));
+    } else {
+        // 1. the cloud C_{i,k}: paths in registers, regression inputs to LDS.  The
+        //    network needs every lane of a wavefront, so with the control variate
+        //    the slots past the last stratum simulate stratum K-1 and discard it,
+        //    and every lane makes ceil(M / L) trips: the lanes past simulation M-1
+        //    simulate one more (index >= M, a stream of its own) into the spare
+        //    row M, which nothing reads.
+        if (live || CV) {
+            const uint32_t ks = live ? k : a.K - 1;
+            const int mend = CV ? (M + L - 1) / L * L : M;
+            for (int m = t; m < mend; m += L) {
+                R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
+                R Sp, y1, cvi, centre;
+                simulate_path<R, D, NB, LK, CV, EP, Model>(a, scf, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp,
+                                                           y1, &cv, &cvi, &centre);
+                row[NB + D + 1] = y1;
+                if constexpr (CV) {
+                    row[NB + D] = Sp - centre;
+                    row[NB + D + 2] = cvi;
+                    row[NB + D + 3] = centre;
+                } else {
+                    row[NB + D] = Sp;
+                }
+            }
+        }
+        __syncthreads();
+
+        // 2. Gram entries and z right-hand sides over the M samples, one
+        //    (entry, chunk) pair per lane, then the chunks in order.
+        if (nch == 1) {
+            if (live)
+                for (int e = t; e < NE; e += L) gram_store(e, gram_sum(rows, e, 0, M));
+        } else {
+            if (live)
+                for (int w = t; w < NE * nch; w += L) {
+                    const int e = w / nch, c = w % nch;
+                    part[w] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
+                }
+            __syncthreads();
             if (live)
                 for (int e = t; e < NE; e += L) {
                     double acc = 0.0;
@@ -705,22 +796,6 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                     gram_store(e, acc);
                 }
         }
-    } else if (nch == 1) {
-        if (live)
-            for (int e = t; e < NE; e += L) gram_store(e, gram_sum(rows, e, 0, M));
-    } else {
-        if (live)
-            for (int w = t; w < NE * nch; w += L) {
-                const int e = w / nch, c = w % nch;
-                part[w] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
-            }
-        __syncthreads();
-        if (live)
-            for (int e = t; e < NE; e += L) {
-                double acc = 0.0;
-                for (int c = 0; c < nch; ++c) acc += part[e * nch + c];
-                gram_store(e, acc);
-            }
     }
     __syncthreads();
 
@@ -777,8 +852,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     __syncthreads();
 
     // 5. y responses S_Y = S' + f_i(X_i, y_{i+1}(X_{i+1}), z_i(X_i)) dt with the
-    //    just-fitted (truncated) z_i, written over S' in LDS.  Without z
-    //    truncation sum_l z_l(X_i) = (sum_l beta_{z_l}) . phi(X_i).
+    //    just-fitted (truncated) z_i.  Without z truncation
+    //    sum_l z_l(X_i) = (sum_l beta_{z_l}) . phi(X_i).
     const bool z_clamped = LK == kLookupFull;
     if (live && !z_clamped) {
         for (int b = t; b < NB; b += L) {
@@ -788,77 +863,120 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         }
     }
     __syncthreads();
-    if constexpr (Model::kUser) {
-        // a model's driver reads X_i itself: drawn again from the same
-        // counter (bit-identical to the cloud's start), and every z_{i,c}(X_i)
-        if (live) {
-            for (int m = t; m < M; m += L) {
-                R *row = rows + (size_t)m * SW;
-                R x[D], phi[NB], z[D];
-                sample_start<R, D, NB>(a, cellF, k, (uint32_t)m, x, phi);
-#pragma unroll 1
-                for (int c = 0; c < D; ++c) {
-                    R v = (R)0;
+    // S_Y of one sample from phi(X_i), S' and y_{i+1}(X_{i+1}) (built-in drivers)
+    auto y_response = [&](const R *phi, R Sp, R y1) -> R {
+        R zs = (R)0;
+        if (!z_clamped) {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * row[b];
-                    z[c] = clamp_level<R>(v, a.clamp_z);
-                }
-                row[NB + D] += Model::template driver<R, D>(a, bsig, (R)a.i * a.dt, x, row[NB + D + 1], z) * a.dt;
+            for (int b = 0; b < NB; ++b) zs += (R)zsum[b] * phi[b];
+        } else {
+#pragma unroll 1
+            for (int c = 0; c < D; ++c) {
+                R v = (R)0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * phi[b];
+                zs += clamp_level<R>(v, a.clamp_z);
             }
         }
-    } else if (live) {
-        for (int m = t; m < M; m += L) {
-            R *row = rows + (size_t)m * SW;
-            R zs = (R)0;
-            if (!z_clamped) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) zs += (R)zsum[b] * row[b];
-            } else {
-#pragma unroll 1
-                for (int c = 0; c < D; ++c) {
-                    R v = (R)0;
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * row[b];
-                    zs += clamp_level<R>(v, a.clamp_z);
-                }
-            }
-            R Sp = row[NB + D];
-            if constexpr (CV) Sp += row[NB + D + 3];
-            R SY = Sp + driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, row[NB + D + 1], zs) * a.dt;
-            if constexpr (CV) SY -= row[NB + D + 2];
-            row[NB + D] = SY;
-        }
-    }
-    __syncthreads();
-
-    // 6. y right-hand side (chunked as the Gram sums) and solve
-    auto y_sum = [&](const R *rb, int b, int m0, int m1) {
-        double acc = 0.0;
-        for (int m = m0; m < m1; ++m) {
-            const R *row = rb + (size_t)m * SW;
-            acc += (double)row[b] * (double)row[NB + D];
-        }
-        return acc;
+        return Sp + driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, y1, zs) * a.dt;
     };
     if constexpr (GR) {
-        for (int c0 = 0; c0 < nch; c0 += a.stage_chunks) {
-            const int c1 = min(nch, c0 + a.stage_chunks), m0 = c0 * kChunk, m1 = min(M, c1 * kChunk);
-            stage_rows(m0, m1);
-            __syncthreads();
+        // 5-6 (streamed). Rounds again: X_i and phi(X_i) drawn again from the
+        //    same counter, S' and y_{i+1} read back; rows (phi, S_Y) in the
+        //    window; y right-hand side summed as the Gram sums.
+        constexpr int YW = NB + 1;
+        const int RS = L >= kChunk ? L : kChunk;
+        const int pb = a.stage_chunks;
+        if (live)
+            for (int b = t; b < NB; b += L) RHS[b] = 0.0;
+        for (int r0 = 0; r0 < M; r0 += RS) {
+            const int rn = min(RS, M - r0);
             if (live) {
-                if (nch == 1) {
-                    for (int b = t; b < NB; b += L) RHS[b] = y_sum(stage, b, 0, M);
-                } else {
-                    const int ncs = c1 - c0;
-                    for (int w = t; w < NB * ncs; w += L) {
-                        const int b = w / ncs, c = c0 + w % ncs;
-                        part[b * nch + c] = y_sum(stage, b, c * kChunk - m0, min(M, (c + 1) * kChunk) - m0);
-                    }
+                for (int u = t; u < rn; u += L) {
+                    const int m = r0 + u;
+                    R x[D], phi[NB];
+                    sample_start_cached<R, D, NB>(a, scf, k, (uint32_t)m, x, phi);
+                    R *row = rows + (size_t)u * YW;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) row[b] = phi[b];
+                    row[NB] = y_response(phi, sy[2 * (size_t)m], sy[2 * (size_t)m + 1]);
                 }
             }
             __syncthreads();
+            const int rc = (rn + kChunk - 1) / kChunk;
+            for (int c0 = 0; c0 < rc; c0 += pb) {
+                const int nbc = min(pb, rc - c0);
+                if (live)
+                    for (int w = t; w < NB * nbc; w += L) {
+                        const int b = w / nbc, c = c0 + w % nbc;
+                        double acc = 0.0;
+                        for (int m = c * kChunk; m < min(rn, (c + 1) * kChunk); ++m) {
+                            const R *row = rows + (size_t)m * YW;
+                            acc += (double)row[b] * (double)row[NB];
+                        }
+                        part[w] = acc;
+                    }
+                __syncthreads();
+                if (live)
+                    for (int b = t; b < NB; b += L) {
+                        double v = RHS[b];
+                        for (int c = 0; c < nbc; ++c) v += part[b * nbc + c];
+                        RHS[b] = v;
+                    }
+                __syncthreads();
+            }
         }
-        if (nch > 1) {
+    } else {
+        if constexpr (Model::kUser) {
+            // a model's driver reads X_i itself: drawn again from the same
+            // counter (bit-identical to the cloud's start), and every z_{i,c}(X_i)
+            if (live) {
+                for (int m = t; m < M; m += L) {
+                    R *row = rows + (size_t)m * SW;
+                    R x[D], phi[NB], z[D];
+                    sample_start_cached<R, D, NB>(a, scf, k, (uint32_t)m, x, phi);
+#pragma unroll 1
+                    for (int c = 0; c < D; ++c) {
+                        R v = (R)0;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * row[b];
+                        z[c] = clamp_level<R>(v, a.clamp_z);
+                    }
+                    row[NB + D] +=
+                        Model::template driver<R, D>(a, bsig, (R)a.i * a.dt, x, row[NB + D + 1], z) * a.dt;
+                }
+            }
+        } else if (live) {
+            for (int m = t; m < M; m += L) {
+                R *row = rows + (size_t)m * SW;
+                R Sp = row[NB + D];
+                if constexpr (CV) Sp += row[NB + D + 3];
+                R SY = y_response(row, Sp, row[NB + D + 1]);
+                if constexpr (CV) SY -= row[NB + D + 2];
+                row[NB + D] = SY;
+            }
+        }
+        __syncthreads();
+
+        // 6. y right-hand side (chunked as the Gram sums)
+        auto y_sum = [&](const R *rb, int b, int m0, int m1) {
+            double acc = 0.0;
+            for (int m = m0; m < m1; ++m) {
+                const R *row = rb + (size_t)m * SW;
+                acc += (double)row[b] * (double)row[NB + D];
+            }
+            return acc;
+        };
+        if (nch == 1) {
+            if (live)
+                for (int b = t; b < NB; b += L) RHS[b] = y_sum(rows, b, 0, M);
+        } else {
+            if (live)
+                for (int w = t; w < NB * nch; w += L) {
+                    const int b = w / nch, c = w % nch;
+                    part[w] = y_sum(rows, b, c * kChunk, min(M, (c + 1) * kChunk));
+                }
+            __syncthreads();
             if (live)
                 for (int b = t; b < NB; b += L) {
                     double acc = 0.0;
@@ -866,24 +984,9 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                     RHS[b] = acc;
                 }
         }
-    } else if (nch == 1) {
-        if (live)
-            for (int b = t; b < NB; b += L) RHS[b] = y_sum(rows, b, 0, M);
-    } else {
-        if (live)
-            for (int w = t; w < NB * nch; w += L) {
-                const int b = w / nch, c = w % nch;
-                part[w] = y_sum(rows, b, c * kChunk, min(M, (c + 1) * kChunk));
-            }
-        __syncthreads();
-        if (live)
-            for (int b = t; b < NB; b += L) {
-                double acc = 0.0;
-                for (int c = 0; c < nch; ++c) acc += part[b * nch + c];
-                RHS[b] = acc;
-            }
     }
     __syncthreads();
+    // y solve
     if (live) {
         for (int b = t; b < NB; b += L) {
             double v;
