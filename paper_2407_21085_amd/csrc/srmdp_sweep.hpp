@@ -660,12 +660,16 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                 ++r;
             }
             const int c = r + rem;
+            // unrolled so that the loads of later samples issue ahead; the
+            // additions stay in sample order
+#pragma unroll 8
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[r] * (double)row[c];
             }
         } else {
             const int l = (e - NG) / NB, b = (e - NG) % NB;
+#pragma unroll 8
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[b] * ((double)row[NB + D] * (double)row[NB + l]);
@@ -910,6 +914,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                     for (int w = t; w < NB * nbc; w += L) {
                         const int b = w / nbc, c = c0 + w % nbc;
                         double acc = 0.0;
+#pragma unroll 8
                         for (int m = c * kChunk; m < min(rn, (c + 1) * kChunk); ++m) {
                             const R *row = rows + (size_t)m * YW;
                             acc += (double)row[b] * (double)row[NB];
@@ -961,6 +966,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         // 6. y right-hand side (chunked as the Gram sums)
         auto y_sum = [&](const R *rb, int b, int m0, int m1) {
             double acc = 0.0;
+#pragma unroll 8
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[b] * (double)row[NB + D];
