@@ -617,8 +617,12 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     CellF<R> *scf = reinterpret_cast<CellF<R> *>(base);
     base += (D * sizeof(CellF<R>) + 15) & ~(size_t)15;
     {
+        // compile-time dimension indices: the batched kernel holds `a` in
+        // registers, where a run-time index would put it in scratch memory
         const uint32_t ks = live ? k : a.K - 1;
-        for (int l = t; l < D; l += L) scf[l] = stratum_cell<R>(a, cellF, ks, l);
+#pragma unroll
+        for (int l = 0; l < D; ++l)
+            if (l % L == t) scf[l] = stratum_cell<R>(a, cellF, ks, l);
     }
     __syncthreads();
     const size_t row_bytes = ((size_t)(CV ? M + 1 : M) * SW * sizeof(R) + 15) & ~(size_t)15;
@@ -649,6 +653,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     double *part = zsum + NB;
     const int nch = (M + kChunk - 1) / kChunk;
 
+    constexpr int kSumUnroll = 8;  // per-sample sums: loads of later samples issue ahead
     // Gram entries (a <= b) and z right-hand sides: binary64 sums over samples
     // m0..m1-1 of a block of rows, in sample order.
     auto gram_sum = [&](const R *rb, int e, int m0, int m1) {
@@ -660,16 +665,15 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                 ++r;
             }
             const int c = r + rem;
-            // unrolled so that the loads of later samples issue ahead; the
-            // additions stay in sample order
-#pragma unroll 8
+            // the additions stay in sample order
+#pragma unroll kSumUnroll
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[r] * (double)row[c];
             }
         } else {
             const int l = (e - NG) / NB, b = (e - NG) % NB;
-#pragma unroll 8
+#pragma unroll kSumUnroll
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[b] * ((double)row[NB + D] * (double)row[NB + l]);
@@ -736,10 +740,12 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             const int rc = (rn + kChunk - 1) / kChunk;
             for (int c0 = 0; c0 < rc; c0 += pb) {
                 const int nbc = min(pb, rc - c0);
+                // consecutive lanes take different entries of one chunk: rows
+                // kChunk apart would fall in the same LDS bank
                 if (live)
                     for (int w = t; w < NE * nbc; w += L) {
-                        const int e = w / nbc, c = c0 + w % nbc;
-                        part[w] = gram_sum(rows, e, c * kChunk, min(rn, (c + 1) * kChunk));
+                        const int e = w % NE, c = w / NE;
+                        part[e * nbc + c] = gram_sum(rows, e, (c0 + c) * kChunk, min(rn, (c0 + c + 1) * kChunk));
                     }
                 __syncthreads();
                 if (live)
@@ -789,8 +795,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         } else {
             if (live)
                 for (int w = t; w < NE * nch; w += L) {
-                    const int e = w / nch, c = w % nch;
-                    part[w] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
+                    const int e = w % NE, c = w / NE;
+                    part[e * nch + c] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
                 }
             __syncthreads();
             if (live)
@@ -912,14 +918,14 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                 const int nbc = min(pb, rc - c0);
                 if (live)
                     for (int w = t; w < NB * nbc; w += L) {
-                        const int b = w / nbc, c = c0 + w % nbc;
+                        const int b = w % NB, c = c0 + w / NB;
                         double acc = 0.0;
-#pragma unroll 8
+#pragma unroll kSumUnroll
                         for (int m = c * kChunk; m < min(rn, (c + 1) * kChunk); ++m) {
                             const R *row = rows + (size_t)m * YW;
                             acc += (double)row[b] * (double)row[NB];
                         }
-                        part[w] = acc;
+                        part[b * nbc + (c - c0)] = acc;
                     }
                 __syncthreads();
                 if (live)
@@ -966,7 +972,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         // 6. y right-hand side (chunked as the Gram sums)
         auto y_sum = [&](const R *rb, int b, int m0, int m1) {
             double acc = 0.0;
-#pragma unroll 8
+#pragma unroll kSumUnroll
             for (int m = m0; m < m1; ++m) {
                 const R *row = rb + (size_t)m * SW;
                 acc += (double)row[b] * (double)row[NB + D];
@@ -979,8 +985,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         } else {
             if (live)
                 for (int w = t; w < NB * nch; w += L) {
-                    const int b = w / nch, c = w % nch;
-                    part[w] = y_sum(rows, b, c * kChunk, min(M, (c + 1) * kChunk));
+                    const int b = w % NB, c = w / NB;
+                    part[b * nch + c] = y_sum(rows, b, c * kChunk, min(M, (c + 1) * kChunk));
                 }
             __syncthreads();
             if (live)
