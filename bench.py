@@ -64,7 +64,7 @@ LOCATE_OPS_EP = 13
 KERNEL_SOURCES = ("srmdp_kernels.hip", "srmdp_sweep.hpp", "srmdp_device.hpp", "srmdp_internal.hpp",
                   "srmdp_mlp.hpp")
 MEASURED_TRAFFIC = {
-    "39abcf9aa2028aa3": {"bytes": 5.651668e+09,
+    "6cca78d7bb7a47e3": {"bytes": 6.129442e+09,
                          "profile": "profiles/sweep_step_kernel_logistic_d8_K65536_M64_N50.md"},
 }
 
@@ -585,6 +585,8 @@ def main() -> int:
                     help="skip the plain vs control-variate comparison at equal M on the d = 4 workload")
     ap.add_argument("--no-paper-tables", action="store_true",
                     help="skip the paper's own workloads (Tables LP0d4 .. LP1d15_19)")
+    ap.add_argument("--paper-dims", default="",
+                    help="comma-separated dimensions d: run only the paper-table rows of these d (profiling)")
     ap.add_argument("--no-equal-prob", action="store_true",
                     help="skip the workload on equal-probability cells")
     ap.add_argument("--no-ragged-batch", action="store_true",
@@ -701,7 +703,9 @@ def main() -> int:
         out["ragged_batch"] = ragged_batch(S, stream)
         progress("ragged batch")
     if not args.no_paper_tables:
-        out["paper_tables"] = paper_tables(S, stream)
+        dims = {int(v) for v in args.paper_dims.split(",") if v.strip()}
+        rows = tuple(r for r in PAPER_ROWS if not dims or r[1] in dims)
+        out["paper_tables"] = paper_tables(S, stream, rows)
         progress("paper tables")
     if not args.no_error_matched and cfg["driver"] == "logistic":
         M = cfg["M"]
