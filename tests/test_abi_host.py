@@ -162,22 +162,25 @@ def test_control_variate_options_rejected(name, _unused, kw, status):
 
 
 def test_global_rows_workspace_and_rejections():
-    """Clouds in global memory: the workspace grows by the strata per launch
-    times the bytes of one cloud (M rows of nb + d + 2 binary64 values, 16-byte
-    aligned, plus chunk sums, the total 256-byte aligned), automatically when a
-    cloud exceeds 64 KB of LDS; a negative strata count is rejected."""
+    """Streamed clouds: the workspace grows by the strata per launch times the
+    global bytes of one stratum (S' and y_{i+1} of each of the M samples in
+    the working precision, 256-byte aligned), automatically when a cloud
+    exceeds 64 KB of LDS; a negative strata count is rejected."""
     S = _S()
     P = S.Problem(d=1, N=10)
     G = S.Grid([-4.0], [4.0], [32])
     base = S.workspace_bytes(P, G, S.Options(M=40))
     forced = S.workspace_bytes(P, G, S.Options(M=40, flags=S.F_GLOBAL_ROWS, global_rows_strata=8))
-    assert forced - base == 8 * 1792                        # 40 * 5 * 8 = 1600 -> 1792
+    assert forced - base == 8 * 768                         # 40 * 2 * 8 = 640 -> 768
     default = S.workspace_bytes(P, G, S.Options(M=40, flags=S.F_GLOBAL_ROWS))
-    assert default - base == 32 * 1792                      # every stratum in one launch
-    # M = 12000: 480000 bytes of rows, 188 chunks of 5 sums (7520 bytes): automatic
+    assert default - base == 32 * 768                       # every stratum in one launch
+    # M = 12000: 480000 bytes of rows per stratum do not fit in LDS: streamed automatically
     big = S.workspace_bytes(P, G, S.Options(M=12000))
     small_lds = S.workspace_bytes(P, G, S.Options(M=12000, global_rows_strata=8))
-    assert big - small_lds == 24 * 487680
+    assert big - small_lds == 24 * 192000                   # 12000 * 2 * 8
+    binary32 = S.workspace_bytes(P, G, S.Options(M=12000, prec=S.FP32, global_rows_strata=8))
+    binary32_16 = S.workspace_bytes(P, G, S.Options(M=12000, prec=S.FP32, global_rows_strata=16))
+    assert binary32_16 - binary32 == 8 * 96000              # 12000 * 2 * 4
     rc = S.srmdp.lib.srmdp_solve(P.c(), G.c(), S.Options(M=40, global_rows_strata=-1).c(), 16, 16, 1 << 40,
                                  None, None)
     assert rc == -1
