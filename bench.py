@@ -192,7 +192,8 @@ def _interp_at_error(points, err, value):
     return None
 
 
-def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_paths: int, stream) -> dict:
+def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_paths: int, stream,
+                  m_small=()) -> dict:
     """Plain estimator at each M in m_plain (the workload's M first) against the
     online control variate at each M in m_cv, over `seeds`: full-sweep time
     (HIP events on the library's stream, training included, mean over seeds)
@@ -216,7 +217,12 @@ def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_pat
     time is also priced at the plain cost per unit of M at the workload's M,
     and the smaller of the two is kept.  Outside a curve's measured range the
     figure is a bound (lower when the control variate already beats eps at its
-    smallest M, or when the plain form needs more than its largest M)."""
+    smallest M, or when the plain form needs more than its largest M).
+
+    Each M in m_small (below the curves' range, near the floor M >= d + 1 of
+    the LP1 regressions) is reported for both forms beside the curves, not on
+    them: there the finite-M bias of the regressions dominates and the error
+    is not monotone in M."""
     import torch
     d = cfg["d"]
 
@@ -254,17 +260,20 @@ def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_pat
 
     def summary(M, cv):
         rows = runs(M, cv, seeds)
-        ys = [y for _, y in rows]
+        ys = [y for _, y in rows if math.isfinite(y)]
+        out = {"M": M, "ms": sum(t for t, _ in rows) / len(rows), "nonfinite_seeds": len(rows) - len(ys)}
         n = len(ys)
+        if n < 2:
+            return dict(out, stat_rmse=None, stat_bias=None, sd=None, total_rmse=None)
         mean = sum(ys) / n
-        return {"M": M, "ms": sum(t for t, _ in rows) / n,
-                "stat_rmse": math.sqrt(sum((y - y_ref) ** 2 for y in ys) / n),
-                "stat_bias": mean - y_ref,
-                "sd": math.sqrt(sum((y - mean) ** 2 for y in ys) / (n - 1)),
-                "total_rmse": math.sqrt(sum((y - 0.5) ** 2 for y in ys) / n)}
+        return dict(out, stat_rmse=math.sqrt(sum((y - y_ref) ** 2 for y in ys) / n),
+                    stat_bias=mean - y_ref,
+                    sd=math.sqrt(sum((y - mean) ** 2 for y in ys) / (n - 1)),
+                    total_rmse=math.sqrt(sum((y - 0.5) ** 2 for y in ys) / n))
 
     plain = [summary(M, False) for M in m_plain]
     cv = [summary(M, True) for M in m_cv]
+    small = [{"M": M, "plain": summary(M, False), "cv": summary(M, True)} for M in m_small]
     ms_per_M = plain[0]["ms"] / plain[0]["M"]  # plain cost at the workload, per simulation per stratum
     for c in cv:
         p = next((q for q in plain if q["M"] == c["M"]), None) or summary(c["M"], False)
@@ -299,7 +308,7 @@ def error_matched(S, cfg: dict, seeds, m_plain, m_cv, m_ref, ref_seeds, root_pat
             "reference": {"M": m_ref, "seeds": list(ref_seeds), "y_ref": y_ref,
                           "se": ref_sd / math.sqrt(len(ref_y)), "discretisation_error": y_ref - 0.5},
             "cv_form": {"stride": CV_STRIDE, "centred_z": True, **CV_TRAIN},
-            "plain": plain, "cv": cv,
+            "plain": plain, "cv": cv, "small_M": small,
             "speedup_at_plain_errors": at_plain,
             "at_workload_error": at_plain[0],
             "at_4x_workload_M_error": next((r for r in at_plain if r["plain_M"] == 4 * plain[0]["M"]), None),
@@ -711,7 +720,7 @@ def main() -> int:
         M = cfg["M"]
         out["error_matched"] = error_matched(S, cfg, range(1, args.em_seeds + 1), [M, 2 * M, 4 * M, 8 * M],
                                              [M // 2, M, 2 * M], 8 * M, range(1001, 1001 + 2 * args.em_seeds),
-                                             1 << 20, stream)
+                                             1 << 20, stream, m_small=[M // 4])
         progress("error-matched comparison")
     if not args.no_cv_equal_m:
         out["cv_equal_M"] = cv_equal_m(S, W.config("cfg4"), range(1, 5), stream)
