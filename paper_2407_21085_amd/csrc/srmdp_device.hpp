@@ -183,12 +183,27 @@ __device__ __forceinline__ R stratified_offset(const CellF<R> &c, R u, R inv_mu)
     return (log1p(c.rp * v) - log1p(-c.rs * v)) * inv_mu;
 }
 
+// log1p(a), a > -1, in binary32 from the hardware log2 (v_log_f32): w = 1 + a
+// is rounded, and the factor a / (w - 1) puts back what the rounding dropped
+// (Goldberg, "What every computer scientist should know about floating-point
+// arithmetic", ACM Computing Surveys 1991, Theorem 4: a few units in the last
+// place when the logarithm is); w = 1 means |a| < 2^-24, where log1p(a) = a.
+// For a in [-1, -1/2], w is exact (Sterbenz), so the tail keeps the accuracy
+// of a itself.
+__device__ __forceinline__ float log1p_hw(float a)
+{
+    const float w = 1.0f + a;
+    const float wm1 = w - 1.0f;
+    const float l = __builtin_amdgcn_logf(w) * 0.69314718055994530942f;
+    return wm1 == 0.0f ? a : l * (a * __builtin_amdgcn_rcpf(wm1));
+}
+
 template <>
 __device__ __forceinline__ float stratified_offset<float>(const CellF<float> &c, float u,
                                                          float inv_mu)
 {
     const float v = u - c.uc;
-    return (log1pf(c.rp * v) - log1pf(-c.rs * v)) * inv_mu;
+    return (log1p_hw(c.rp * v) - log1p_hw(-c.rs * v)) * inv_mu;
 }
 
 // Terminal condition g.
