@@ -320,7 +320,13 @@ struct CvWave {
 // response; every lane of the wavefront must then run the same steps.
 // The first and last steps are peeled off so that the steady loop has no
 // branch that depends on j.
-template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false, class Model = BuiltinModel>
+// PF (built-in problems without the control variate): the positions do not
+// depend on the fitted rows, so X_{j+2} is formed and its record requested
+// while the record of X_{j+1} is evaluated: one gather in flight across a
+// step's arithmetic.  The same operations in the same order: results are
+// bit-identical.
+template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false, class Model = BuiltinModel,
+          bool PF = false>
 __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
                                          const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
                                          R *dWi_out, R &y1, R &Sp, const CvWave *cv = nullptr,
@@ -363,6 +369,42 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         x[l] = xn[l];
     }
     R S = (R)0;
+    if constexpr (PF && !CV && !Model::kUser) {
+        constexpr int V = LookupWidth<R, D, NB, LK>::value;
+        if (i + 1 < N - 1) {
+            // X_{i+2} and the request of its record (row i+2)
+            ns.step(1u, dW);
+            model_step<R, D, Model>(a, bsig, i + 1, x, dW, xn);
+            R xi[D], rec[V];
+            load_record<R, V>(lk + (size_t)(i + 2) * row_elems + locate<R, D, NB, LK, EP>(a, xn, xi), rec);
+#pragma unroll
+            for (int l = 0; l < D; ++l) x[l] = xn[l];
+            for (int j = i + 1; j < N - 2; ++j) {
+                // X_{j+2} from X_{j+1}, and its record requested
+                ns.step((uint32_t)(j + 1 - i), dW);
+                model_step<R, D, Model>(a, bsig, j + 1, x, dW, xn);
+                R xi2[D], rec2[V];
+                load_record<R, V>(lk + (size_t)(j + 2) * row_elems + locate<R, D, NB, LK, EP>(a, xn, xi2), rec2);
+                // f_j from the record of X_{j+1}
+                R yn, zn;
+                eval_record<R, D, NB, LK>(a, rec, xi, yn, zn);
+                S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+                zsum_cur = zn;
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    x[l] = xn[l];
+                    xi[l] = xi2[l];
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) rec[v] = rec2[v];
+            }
+            // f_{N-2} from the record of X_{N-1}
+            R yn, zn;
+            eval_record<R, D, NB, LK>(a, rec, xi, yn, zn);
+            S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+            zsum_cur = zn;
+        }
+    } else
     for (int j = i + 1; j < N - 1; ++j) {
         ns.step((uint32_t)(j - i), dW);
         if constexpr (CV) {
@@ -462,7 +504,7 @@ __device__ __forceinline__ void sample_start_cached(const StepArgs<R> &a, const 
 // i + 1 = N): the fitted row i+1 of the stratum itself (X_i lies in it),
 // truncated, whose product with dW_i / dt has conditional mean zero.
 // scf: the stratum's cell constants (sample_start_cached).
-template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel>
+template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel, bool PF = false>
 __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *scf,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
                                               uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
@@ -487,7 +529,7 @@ __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<
     }
     NormalStream<R, D> ns;
     ns.init(Key{a.key0, a.key1}, m, k, a.tag, a.sqrt_dt);
-    run_path<R, D, NB, LK, CV, EP, Model>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
+    run_path<R, D, NB, LK, CV, EP, Model, PF>(a, bsig, lk, ns, x, dWi_out, y1, Sp, cv, cvi);
 }
 
 // Near-face diagnostic of step i: the positions of a simulation do not depend
@@ -576,7 +618,8 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // a.grow_bytes per stratum).  The y pass draws X_i and phi(X_i) again from the
 // same counter and reads S', y_{i+1} back.  The launch covers strata
 // a.k0 .. a.k_end-1.
-template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false, class Model = BuiltinModel>
+template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false, class Model = BuiltinModel,
+          bool PF = false>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
                                             const R *__restrict__ bsig, R *__restrict__ lk,
@@ -773,7 +816,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             for (int m = t; m < mend; m += L) {
                 R *row = rows + (size_t)(CV ? (m < M ? m : M) : m) * SW;
                 R Sp, y1, cvi, centre;
-                simulate_path<R, D, NB, LK, CV, EP, Model>(a, scf, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp,
+                simulate_path<R, D, NB, LK, CV, EP, Model, PF>(a, scf, bsig, lk, ks, (uint32_t)m, row, row + NB, Sp,
                                                            y1, &cv, &cvi, &centre);
                 row[NB + D + 1] = y1;
                 if constexpr (CV) {
@@ -1040,7 +1083,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     }
 }
 
-template <typename R, int D, int NB, int LK, bool CV>
+template <typename R, int D, int NB, int LK, bool CV, bool PF = false>
 __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
                                                         const CellF<R> *__restrict__ cellF,
                                                         const R *__restrict__ bsig,
@@ -1048,7 +1091,8 @@ __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
                                                         unsigned long long *__restrict__ counters)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sweep_group<R, D, NB, LK, CV>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table,
+    sweep_group<R, D, NB, LK, CV, false, false, BuiltinModel, PF>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF,
+                                                              bsig, lk, table,
                                   counters, smem);
 }
 
