@@ -112,6 +112,21 @@ struct LaunchShape {
 };
 
 #if !defined(__HIPCC_RTC__)  // host launchers
+// Launches whose paths gather from at least this many bytes of look-up rows
+// (rows i+1..N-1) miss L2 on most gathers, and their time goes to gather
+// latency: binary32 sweeps then run the path loop that keeps one gather in
+// flight across a step (run_path, PF), at one wavefront per SIMD less; shorter
+// launches keep the plain loop.  Measured at d = 8, K = 4^8, M = 64 (5.2 MB
+// rows): 60.2 ms per sweep with the plain loop, 56.5 ms with the switch at 29
+// rows, 57.7 ms with the pipelined loop everywhere.
+constexpr size_t kPrefetchRowBytes = (size_t)144 << 20;
+
+template <typename R, int D, int NB, int LK>
+inline bool prefetch_launch(const StepArgs<R> &a)
+{
+    return (size_t)(a.N - a.i - 1) * a.K * LookupWidth<R, D, NB, LK>::value * sizeof(R) >= kPrefetchRowBytes;
+}
+
 template <typename R>
 hipError_t launch_setup(const SetupArgs &s, const double *sigma, void *cellF, void *bsig, hipStream_t st);
 template <typename R>

@@ -49,23 +49,13 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st)
 
 // --------------------------------------------------------- instantiation
 
-// Launches whose paths gather from more than this many bytes of look-up rows
-// (rows i+1..N-1) miss L2 on most gathers, and their time goes to gather
-// latency: they run the path loop that keeps one gather in flight across a
-// step (run_path, PF), at one wavefront per SIMD less.  Shorter launches keep
-// the plain loop.  Measured at d = 8, K = 4^8, M = 64 (5.2 MB rows): 60.2 ms
-// per sweep with the plain loop, 56.5 ms with this switch at 29 rows, 57.7 ms
-// with the pipelined loop everywhere.
-constexpr size_t kPrefetchRowBytes = (size_t)144 << 20;
-
 template <typename R, int D, int NB, int LK>
 static hipError_t launch_step_impl(const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                                    const void *bsig, void *lk, void *table, void *counters,
                                    hipStream_t st)
 {
     if constexpr (sizeof(R) == 4) {
-        const size_t rows = (size_t)(a.N - a.i - 1) * a.K * LookupWidth<R, D, NB, LK>::value * sizeof(R);
-        if (rows >= kPrefetchRowBytes) {
+        if (prefetch_launch<R, D, NB, LK>(a)) {
             hipLaunchKernelGGL((sweep_step_kernel<R, D, NB, LK, false, true>), dim3(s.blocks), dim3(s.threads),
                                s.lds_bytes, st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk,
                                (R *)table, (unsigned long long *)counters);

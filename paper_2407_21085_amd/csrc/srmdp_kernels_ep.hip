@@ -8,7 +8,7 @@
 
 namespace srmdp {
 
-template <typename R, int D, int NB, int LK>
+template <typename R, int D, int NB, int LK, bool PF = false>
 __global__ void __launch_bounds__(256) sweep_step_ep_kernel(const StepArgs<R> a,
                                                            const CellF<R> *__restrict__ cellF,
                                                            const R *__restrict__ bsig, R *__restrict__ lk,
@@ -16,14 +16,22 @@ __global__ void __launch_bounds__(256) sweep_step_ep_kernel(const StepArgs<R> a,
                                                            unsigned long long *__restrict__ counters)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sweep_group<R, D, NB, LK, false, false, true>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk,
-                                                  table, counters, smem);
+    sweep_group<R, D, NB, LK, false, false, true, BuiltinModel, PF>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF,
+                                                                    bsig, lk, table, counters, smem);
 }
 
 template <typename R, int D, int NB, int LK>
 static hipError_t launch_ep_lds_impl(const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                                      const void *bsig, void *lk, void *table, void *counters, hipStream_t st)
 {
+    if constexpr (sizeof(R) == 4) {
+        if (prefetch_launch<R, D, NB, LK>(a)) {
+            hipLaunchKernelGGL((sweep_step_ep_kernel<R, D, NB, LK, true>), dim3(s.blocks), dim3(s.threads),
+                               s.lds_bytes, st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
+                               (unsigned long long *)counters);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((sweep_step_ep_kernel<R, D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st, a,
                        (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
                        (unsigned long long *)counters);
