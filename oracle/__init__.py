@@ -30,11 +30,12 @@ G_COS_SUM, G_LOGISTIC = 0, 1
 GRID_EQUAL_SIZE, GRID_EQUAL_PROB = 0, 1
 
 
-def compile_source(src: str, out: str) -> str:
-    """gcc -O2, no fast-math, no contraction, OpenMP over strata."""
+def compile_source(src: str, out: str, extra_flags=()) -> str:
+    """gcc -O2, no fast-math, no contraction, OpenMP over strata (extra_flags:
+    an instrumented build, for instance)."""
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-           "-fPIC", "-shared", "-I", _HERE, src, "-o", tmp, "-lm"]
+    cmd = (["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared"] +
+           list(extra_flags) + ["-I", _HERE, src, "-o", tmp, "-lm"])
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -100,9 +101,13 @@ _lib = None
 
 def lib():
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=True)
-        _bind(ctypes.CDLL(_LIB_PATH))
+        # SRMDP_ORACLE_LIBRARY names another build of the oracle (an instrumented one)
+        path = os.environ.get("SRMDP_ORACLE_LIBRARY")
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(path):
+                build(force=True)
+        _bind(ctypes.CDLL(path))
     return _lib
 
 

@@ -3,6 +3,7 @@
 // from a cached hipGraph) and the read-outs.  Implements include/srmdp.h.
 #include "../../include/srmdp.h"
 
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +27,53 @@ using namespace srmdp;
 static thread_local std::string g_error;
 
 namespace {
+
+// Annotation ranges for profilers (roctx of rocprofiler-sdk, shown by
+// `rocprofv3 --marker-trace`): one per backward step, per training update and
+// per batched global step, pushed on the host when the work is enqueued.  The
+// roctx library is opened on first use; without it a range costs a null check.
+struct RoctxApi {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+};
+
+const RoctxApi &roctx_api()
+{
+    static const RoctxApi api = [] {
+        RoctxApi r;
+        for (const char *name : {"librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"}) {
+            void *h = dlopen(name, RTLD_NOW | RTLD_LOCAL);
+            if (!h) continue;
+            r.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+            r.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+            if (!r.push || !r.pop) r.push = nullptr, r.pop = nullptr;
+            break;
+        }
+        return r;
+    }();
+    return api;
+}
+
+class TraceRange {
+  public:
+    TraceRange(const char *what, int index)
+    {
+        const RoctxApi &api = roctx_api();
+        if (!api.push) return;
+        char name[64];
+        std::snprintf(name, sizeof name, "%s %d", what, index);
+        active_ = api.push(name) >= 0;
+    }
+    ~TraceRange()
+    {
+        if (active_) roctx_api().pop();
+    }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+
+  private:
+    bool active_ = false;
+};
 
 srmdp_status fail(srmdp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 srmdp_status fail(srmdp_status s, const char *fmt, ...)
@@ -596,6 +644,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
     if (steps0) HIP_TRY(hipEventRecord(steps0, st), "hipEventRecord");
     a.cell_table = ws + lay.cellF;
     for (int i = hi; i >= lo; --i) {
+        TraceRange range("srmdp backward step", i);
         a.i = i;
         a.tag = ((uint32_t)i & 0xFFFFu) | (o->instance << 16);
         a.debug_singular =
@@ -629,6 +678,7 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
                     t.eps = o->cv_train.eps;
                     t.packed_out = ws + lay.cv_packed;
                     t.loss = (float *)(ws + lay.cv_loss) + (size_t)(hi - i) * U;
+                    TraceRange train_range("srmdp network training after step", i);
                     HIP_TRY(launch_mlp_train(t, (float *)(ws + lay.cv_part), st), "network training");
                 }
                 launched = true;
@@ -1065,6 +1115,7 @@ srmdp_status enqueue_batch(int n, const srmdp_problem *P, const srmdp_grid *G, c
     HIP_TRY(launch_upload(ws, inst.data(), sizeof(BatchInstance<R>) * n, st), "instance upload");
     int active = n;
     for (int g = 0; g < bp.gmax; ++g) {
+        TraceRange range("srmdp batched global step", g);
         while (active > 0 && P[bp.order[active - 1]].N <= g) --active;
         HIP_TRY(launch_batch_step<R>(P[0].d, O[0].basis, bp.lk, bp.shapes[0].equal_prob, ws, active, prefix[active], g,
                                      threads, lds, st),

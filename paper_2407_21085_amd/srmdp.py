@@ -102,14 +102,16 @@ EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_e
 
 
 def _load():
-    if not os.path.exists(LIB_PATH):
+    # SRMDP_LIBRARY names another build of this library (an instrumented one)
+    path = os.environ.get("SRMDP_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_2407_21085_amd.build`")
+            f"{path} is missing: build it with `python -m paper_2407_21085_amd.build`")
     # PyTorch ships its own HIP runtime.  Loading torch first makes the library
     # bind to that same runtime (same soname), so one process holds one HIP
     # runtime and the library can work on torch's tensors and streams.
     import torch  # noqa: F401
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     P, G, O, S = (ctypes.POINTER(_Problem), ctypes.POINTER(_Grid), ctypes.POINTER(_Options),
                   ctypes.POINTER(_Stats))
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
