@@ -132,12 +132,19 @@ void orc_path_uniforms(uint64_t seed, uint32_t inst, int32_t i, uint32_t k, uint
 /* Number of Philox blocks used by the start point: ceil(d/4). */
 static int start_blocks(int d) { return (d + 3) / 4; }
 
-/* Standard normal number n of the path: Box-Muller on the uniform pair
- * p = n/2 that follows the start blocks; even n takes the cosine branch, odd n
- * the sine branch. */
-static double stream_normal(path_stream *s, int d, int64_t n)
+/* Standard normal l (0 <= l < q) of path step `step` (step j - i of a
+ * simulation started at step i).  The q normals of a step are the numbers
+ * n = step * Q + l of the path's normal sequence, with Q = q when q divides 4
+ * (4/q consecutive steps share a Philox block) and Q = 4 ceil(q/4) otherwise
+ * (each step starts on a block of its own, and the last block's unused
+ * numbers are skipped).  Number n is Box-Muller on the uniform pair p = n/2
+ * that follows the start blocks; even n takes the cosine branch, odd n the
+ * sine branch. */
+static double stream_normal(path_stream *s, int d, int q, int64_t step, int l)
 {
     const double pi = 3.14159265358979323846;
+    const int64_t Q = (4 % q == 0) ? q : 4 * ((q + 3) / 4);
+    const int64_t n = step * Q + l;
     int64_t p = n / 2;
     int64_t base = 4 * (int64_t)start_blocks(d) + 2 * p;
     double u1 = stream_uniform(s, base);
@@ -605,7 +612,7 @@ int orc_path_normals(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, in
     if (!P || P->d < 1) return -1;
     path_stream s;
     stream_init(&s, P->seed, P->inst, i, k, m);
-    for (int32_t a = 0; a < n; ++a) out[a] = stream_normal(&s, P->d, a);
+    for (int32_t a = 0; a < n; ++a) out[a] = stream_normal(&s, P->d, P->q, a / P->q, a % P->q);
     return 0;
 }
 
@@ -702,7 +709,7 @@ static void simulate(const orc_problem *P, const grid_t *G, const double *table,
     *cvi = 0.0;
     for (int32_t j = i; j < P->N; ++j) {
         for (int l = 0; l < q; ++l)
-            dW[l] = sdt * stream_normal(s, d, (int64_t)(j - i) * q + l);
+            dW[l] = sdt * stream_normal(s, d, q, j - i, l);
         if (P->model) {
             /* Algorithm "Euler dynamics" at (t_j, X_j) */
             double bj[64], sj[64];

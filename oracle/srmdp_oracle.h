@@ -123,7 +123,8 @@ void orc_path_uniforms(uint64_t seed, uint32_t inst, int32_t i, uint32_t k, uint
 /* Starting point X_i of simulation (i, k, m), drawn from nu_k. */
 int orc_start_point(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, double *x);
 
-/* First n standard normals of simulation (i, k, m) (before the sqrt(dt) scale). */
+/* First n standard normals of simulation (i, k, m) (before the sqrt(dt) scale),
+ * step by step: out[s q + l] is normal l of path step s. */
 int orc_path_normals(const orc_problem *P, int32_t i, uint32_t k, uint32_t m, int32_t n,
                      double *out);
 

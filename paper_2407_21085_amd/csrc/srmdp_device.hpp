@@ -87,8 +87,12 @@ __device__ __forceinline__ float box_muller_constant(float scale)
 }
 __device__ __forceinline__ double box_muller_constant(double scale) { return scale; }
 
-// The Gaussian increments of one simulation.  Normal n of the simulation
-// (n = step_offset * D + l) is the cosine (n even) or sine (n odd) branch of the
+// The Gaussian increments of one simulation.  The D normals of step offset
+// s = j - i are the numbers n = s Q + l of the simulation's normal sequence,
+// Q = D when D divides 4 (4/D consecutive steps share a Philox block) and
+// Q = 4 ceil(D/4) otherwise (each step starts on a block of its own and skips
+// the last block's unused numbers), so a step needs no branch on where its
+// numbers begin.  Number n is the cosine (n even) or sine (n odd) branch of the
 // Box-Muller pair n/2, which takes uniforms 2*(n/2) and 2*(n/2)+1 of the blocks
 // that follow the ceil(D/4) start blocks.  One Philox block feeds four normals.
 template <typename R, int D>
@@ -97,7 +101,6 @@ struct NormalStream {
     Key key;
     R bm;       // box_muller_constant(scale)
     R buf[4];
-    uint32_t buf_block;  // block held in buf (0 = none: block 0 is a start block)
 
     // Normals of standard deviation `scale` (sqrt(dt) gives the increments dW).
     __device__ __forceinline__ void init(Key k, uint32_t m, uint32_t cube, uint32_t tag, R scale)
@@ -105,7 +108,6 @@ struct NormalStream {
         key = k;
         ctr = make_uint4(0u, m, cube, tag);
         bm = box_muller_constant(scale);
-        buf_block = 0u;
     }
 
     __device__ __forceinline__ void fill(uint32_t blk)
@@ -114,21 +116,13 @@ struct NormalStream {
         const uint4 w = philox4x32_10(ctr, key);
         box_muller(open_uniform<R>(w.x), open_uniform<R>(w.y), bm, buf[0], buf[1]);
         box_muller(open_uniform<R>(w.z), open_uniform<R>(w.w), bm, buf[2], buf[3]);
-        buf_block = blk;
     }
 
     // D normals of step offset s = j - i (s is uniform over the wave).
     __device__ __forceinline__ void step(uint32_t s, R *out)
     {
         constexpr uint32_t B0 = (D + 3) / 4;
-        if constexpr (D % 4 == 0) {
-#pragma unroll
-            for (int b = 0; b < D / 4; ++b) {
-                fill(B0 + s * (D / 4) + b);
-#pragma unroll
-                for (int w = 0; w < 4; ++w) out[4 * b + w] = buf[w];
-            }
-        } else if constexpr (4 % D == 0) {
+        if constexpr (4 % D == 0) {
             constexpr uint32_t per = 4 / D;  // steps served by one block
             const uint32_t off = (s % per) * D;
             if (off == 0) fill(B0 + s / per);
@@ -138,13 +132,13 @@ struct NormalStream {
                 out[l] = w == 0 ? buf[0] : w == 1 ? buf[1] : w == 2 ? buf[2] : buf[3];
             }
         } else {
+            constexpr uint32_t NBK = (D + 3) / 4;  // blocks per step
 #pragma unroll
-            for (int l = 0; l < D; ++l) {
-                const uint32_t n = s * D + l;
-                const uint32_t blk = B0 + n / 4;
-                if (blk != buf_block) fill(blk);
-                const uint32_t w = n % 4;
-                out[l] = w == 0 ? buf[0] : w == 1 ? buf[1] : w == 2 ? buf[2] : buf[3];
+            for (int b = 0; b < (int)NBK; ++b) {
+                fill(B0 + s * NBK + b);
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    if (4 * b + w < D) out[4 * b + w] = buf[w];
             }
         }
     }

@@ -88,18 +88,25 @@ def test_normals_moments_and_ks():
 
 
 def test_normals_are_box_muller_of_the_stream():
-    # the pair p uses uniforms 4*ceil(d/4) + 2p and +1 of the same stream
-    for d in (1, 4, 5):
+    """Normal l of path step s is number n = s Q + l of the path's normal
+    sequence, Q = q when q divides 4 and 4 ceil(q/4) otherwise (a step starts
+    on a Philox block of its own); number n is the cosine (even n) or sine (odd
+    n) branch of Box-Muller on the uniforms 4 ceil(d/4) + 2 (n // 2) and + 1 of
+    the same stream."""
+    for d in (1, 2, 3, 4, 5, 8):
         P = _prob(d=d)
-        n = O.path_normals(P, 3, 5, 7, 8)
-        u = O.path_uniforms(P.seed, P.inst, 3, 5, 7, 4 * ((d + 3) // 4) + 8)
+        steps = 3
+        n = O.path_normals(P, 3, 5, 7, steps * d)
+        Q = d if 4 % d == 0 else 4 * ((d + 3) // 4)
         b = 4 * ((d + 3) // 4)
-        for p in range(4):
-            u1, u2 = u[b + 2 * p], u[b + 2 * p + 1]
-            rho = math.sqrt(-2.0 * math.log(u1))
-            assert n[2 * p] == pytest.approx(rho * math.cos(2 * math.pi * u2), rel=1e-14, abs=1e-15)
-            assert n[2 * p + 1] == pytest.approx(rho * math.sin(2 * math.pi * u2), rel=1e-14,
-                                                 abs=1e-15)
+        u = O.path_uniforms(P.seed, P.inst, 3, 5, 7, b + steps * Q + 2)
+        for s in range(steps):
+            for l in range(d):
+                num = s * Q + l
+                u1, u2 = u[b + 2 * (num // 2)], u[b + 2 * (num // 2) + 1]
+                rho = math.sqrt(-2.0 * math.log(u1))
+                ref = rho * (math.cos if num % 2 == 0 else math.sin)(2 * math.pi * u2)
+                assert n[s * d + l] == pytest.approx(ref, rel=1e-14, abs=1e-15), (d, s, l)
 
 
 def test_normals_uncorrelated_across_lags():
