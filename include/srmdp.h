@@ -230,10 +230,10 @@ typedef struct {
                              * read and overwritten by ONLINE; NULL when cv is NONE */
     srmdp_mlp_train_config cv_train;  /* ONLINE only */
     int32_t cv_stride;      /* network evaluated every cv_stride steps; <= 1 = every step */
-    int32_t global_rows_strata; /* clouds in global memory: strata per launch (rounded up to a
-                                 * multiple of 8); 0 = as many as 2 GiB of rows hold.  The
-                                 * workspace then holds that many clouds (M rows of
-                                 * nb + d + 2 values, plus binary64 chunk sums, each) */
+    int32_t global_rows_strata; /* streamed clouds: strata per launch (rounded up to a
+                                 * multiple of 8); 0 = as many as 2 GiB hold.  The workspace
+                                 * then holds, per stratum of a launch, S' and y_{i+1}(X_{i+1})
+                                 * of each of the M samples in the working precision */
     int32_t debug_step;     /* SRMDP_F_DEBUG_SINGULAR: step and stratum of the zeroed Gram */
     uint32_t debug_stratum;
 } srmdp_options;
