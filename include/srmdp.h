@@ -197,8 +197,9 @@ typedef struct {
 #define SRMDP_F_CV_CENTER_Z  0x4u  /* control variate: centre the z response (see srmdp_cv) */
 #define SRMDP_F_AUTOTUNE     0x8u  /* lanes_per_cube == 0: use the autotuned value (srmdp_tune_lanes;
                                     * tuned once per shape and cached; not during capture) */
-#define SRMDP_F_GLOBAL_ROWS  0x10u /* keep every stratum's cloud in global memory (see
-                                    * global_rows_strata); automatic, without the control
+#define SRMDP_F_GLOBAL_ROWS  0x10u /* stream every stratum's cloud through an LDS window in
+                                    * rounds, with S' and y_{i+1} per sample in global memory
+                                    * (see global_rows_strata); automatic, without the control
                                     * variate, when a cloud does not fit in 64 KB of LDS */
 #define SRMDP_F_DEBUG_SINGULAR 0x20u /* test aid: the Gram matrix of stratum debug_stratum at
                                       * step debug_step is replaced by zero, so that this

@@ -1,9 +1,8 @@
 // Backward-step kernels for clouds too large for LDS: the same body as
 // sweep_step_kernel (Algorithm SRMDP, eq. (PsiM)), with each stratum's cloud
-// rows and chunk sums in global memory and the launch covering a range of
-// strata (StepArgs::k0 .. k_end).  Per stratum the rows are written once and
-// read by the regression phases; against the path simulation that produced
-// them this traffic is small (a few per cent at M in the thousands).
+// streamed through an LDS window in rounds (sweep_group, GR), S' and y_{i+1}
+// of its samples in global memory, and the launch covering a range of strata
+// (StepArgs::k0 .. k_end).
 // Instantiated for equal-size cells in srmdp_kernels_gr.hip and for
 // equal-probability cells (EP) in srmdp_kernels_ep.hip.
 #pragma once

@@ -5,7 +5,7 @@
 //   HD_FN(name)   the names of its launchers,
 //   HD_NEXT(name) the launchers that take the other dimensions,
 //   HD_KERNEL, HD_IMPL  names of its kernel and launch helper.
-// Binary32 sweeps with the clouds in global memory and look-up modes Y and
+// Binary32 sweeps with streamed clouds and look-up modes Y and
 // YZ; every kernel around the sweep in both precisions.
 #include <type_traits>
 

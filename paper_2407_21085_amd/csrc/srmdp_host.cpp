@@ -476,8 +476,9 @@ uint32_t grows_strata(const Shape &s, size_t grow_bytes, const srmdp_options *o)
 // With the control variate a workgroup of up to four wavefronts shares one LDS
 // copy of the network's forward weights.
 // Without it, a stratum whose cloud does not fit in a workgroup's 64 KB of LDS
-// (or any stratum, with SRMDP_F_GLOBAL_ROWS) keeps its cloud rows and chunk
-// sums in global memory, and each step runs in launches of ls.kc strata.
+// (or any stratum, with SRMDP_F_GLOBAL_ROWS) streams its cloud through an LDS
+// window in rounds, keeping S' and y_{i+1} per sample in global memory, and
+// each step runs in launches of ls.kc strata.
 bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape &ls, size_t &per_cube, bool cv,
                 const srmdp_options *o)
 {
@@ -563,7 +564,7 @@ srmdp_status sweep_supported(const Shape &s, const srmdp_options *o, int lk)
 
 // What a problem with its own model runs: the LDS sweep on equal-size cells
 // for the dimensions compiled with it, without the control variate, the
-// autotuner or clouds in global memory.
+// autotuner or streamed clouds.
 srmdp_status model_supported(const Shape &s, int nb, const srmdp_options *o)
 {
     if (s.equal_prob) return fail(SRMDP_E_UNSUPPORTED, "a model runs on equal-size cells");

@@ -73,8 +73,8 @@ struct StepArgs {
     const unsigned char *cv_packed;  // control-variate network, packed (nullptr = none)
     int cv_stride;                   // network evaluated every cv_stride steps (>= 1)
     int z_center;                    // subtract y_{i+1}(X_i) from the z response's S'
-    // Global-rows launches (clouds too large for LDS): this launch runs strata
-    // k0 .. k_end-1, each keeping its regression inputs and chunk sums in
+    // Streamed-cloud launches (clouds too large for LDS): this launch runs
+    // strata k0 .. k_end-1, each keeping S' and y_{i+1} of its samples in
     // grow_bytes of global memory from grows (slot = stratum - k0).
     uint32_t k0, k_end;
     unsigned char *grows;
@@ -105,7 +105,7 @@ struct RootPoint {
 struct LaunchShape {
     unsigned blocks, threads;  // groups of strata, threads per workgroup
     size_t lds_bytes;
-    bool grows;                // clouds in global memory, launches of `kc` strata
+    bool grows;                // streamed clouds, launches of `kc` strata
     uint32_t kc;
     size_t grow_bytes;         // global bytes per stratum
     int stage_chunks;          // streamed clouds: chunks whose partial sums are formed together
@@ -152,8 +152,8 @@ hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &s, int kind
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st);
 
 // The dimensions of the high-dimension files (d = 7, 9, 10 and 11..19, the
-// paper's Tables LP0d11 .. LP1d15_19): binary32 sweeps with the cloud in global
-// memory and look-up modes Y and YZ, and every kernel around the sweep.
+// paper's Tables LP0d11 .. LP1d15_19): binary32 sweeps with streamed clouds
+// and look-up modes Y and YZ, and every kernel around the sweep.
 bool hd_dimension_compiled(int d);
 template <typename R>
 hipError_t launch_step_gr_hd(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
@@ -274,7 +274,7 @@ template <typename R>
 hipError_t launch_step_gr(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,
                           hipStream_t st);
-// Equal-probability cells (srmdp_kernels_ep.hip): clouds in global memory, and in LDS.
+// Equal-probability cells (srmdp_kernels_ep.hip): streamed clouds, and clouds in LDS.
 template <typename R>
 hipError_t launch_step_ep(int d, const StepArgs<R> &a, const LaunchShape &s, int basis, int lkmode,
                           const void *cellF, const void *bsig, void *lk, void *table, void *counters,

@@ -2,7 +2,7 @@
 // hypercubes under assumption (A_Strat): cells cut at the logistic quantiles,
 // every cube of nu-probability 1/K), for the dimensions of the LDS kernels, in
 // both precisions and every look-up mode: the clouds in LDS
-// (sweep_step_ep_kernel) or, when they do not fit, in global memory (the body
+// (sweep_step_ep_kernel) or, when they do not fit, streamed (the body
 // of srmdp_gr.hpp).  The equal-size kernels keep no code of this grid.
 #include "srmdp_gr.hpp"
 
