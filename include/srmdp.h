@@ -309,6 +309,20 @@ srmdp_status srmdp_eval(const srmdp_problem *problem, const srmdp_grid *grid, in
                         int32_t prec, const void *table, int32_t i, const double *x, int64_t n,
                         double *y, double *z, void *stream);
 
+/* The table in the paper's raw basis (1, x_1, .., x_d) of the local polynomials
+ * of degree 1 (Section 4.1), record by record.  A table record holds the
+ * coefficients beta on (1, xi_1, .., xi_d), xi_l = 2 s_l (x_l - m_l), with
+ * m_l the centre of the cell (equal-size cells, s_l = cells_l / (hi_l - lo_l))
+ * or its nu-median F^{-1}((c + 1/2) / cells_l) (equal-probability cells,
+ * s_l = mu / 2).  The raw coefficients are alpha_l = 2 s_l beta_l and
+ * alpha_0 = beta_0 - sum_l alpha_l m_l, so that alpha . (1, x) = beta . (1, xi).
+ * LP0 records are copied.  table, raw: device, srmdp_table_elems values of
+ * precision prec in the table layout; raw may be table (in place).  Far from
+ * the origin the raw form loses digits to cancellation; the sweep and the
+ * read-outs keep the centred form. */
+srmdp_status srmdp_to_raw_basis(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis,
+                                int32_t prec, const void *table, void *raw, void *stream);
+
 /* ROOT read-out of y(0, x0), z(0, x0): the MDP identity with the initial law
  * delta_{x0} (the value functions do not depend on the initial law, Section 2),
  * i.e. an LP0 regression on the point x0 with M_root simulations (counter

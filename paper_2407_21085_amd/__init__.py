@@ -18,7 +18,7 @@ _BINDING_NAMES = frozenset((
     "CV_FROZEN", "CV_NONE", "CV_ONLINE", "DRV_LINEAR", "DRV_LOGISTIC",
     "F_AUTOTUNE", "F_CHECK_FINITE", "F_CV_CENTER_Z", "F_DEBUG_SINGULAR", "F_GLOBAL_ROWS", "F_GRAPH", "FP32", "FP64",
     "GRID_EQUAL_PROB", "GRID_EQUAL_SIZE", "G_COS_SUM", "G_LOGISTIC", "LP0", "LP1", "Grid", "Model",
-    "Options", "Problem", "SrmdpError", "TrainConfig", "cv_pairs", "draw", "evaluate",
+    "Options", "Problem", "SrmdpError", "TrainConfig", "cv_pairs", "draw", "evaluate", "to_raw_basis",
     "mlp_backward", "mlp_forward", "mlp_init", "mlp_pack", "mlp_param_count", "mlp_train",
     "release_graphs", "root", "solve", "solve_batch", "solve_noalloc", "table_elems", "tune_lanes",
     "workspace_bytes", "workspace_bytes_batch",

@@ -202,6 +202,33 @@ __global__ void draw_kernel(const StepArgs<R> a, const SetupArgs sa, int kind,
     }
 }
 
+// Table records in the raw basis (1, x_1..x_d) (srmdp_to_raw_basis): one
+// record (step, stratum, component) per thread, alpha_l = 2 s_l beta_l and
+// alpha_0 = beta_0 - sum_l alpha_l m_l in binary64, m_l the cell's centre or
+// nu-median and s_l = scale_l (the LP1 coordinate 2 s_l (x_l - m_l)).  Every
+// value of a record is read before it is written, so raw may alias table.
+template <typename R>
+__global__ void raw_basis_kernel(const StepArgs<R> a, int d, int q1, const R *table, R *raw, size_t records)
+{
+    const int nb = d + 1;
+    for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < records;
+         r += (size_t)gridDim.x * blockDim.x) {
+        const R *b = table + r * nb;
+        R *o = raw + r * nb;
+        const uint32_t k = (uint32_t)((r / (size_t)q1) % a.K);
+        double a0 = (double)b[0];
+        for (int l = 0; l < d; ++l) {
+            const double c = (double)((k / a.stride[l]) % a.cells[l]);
+            const double s = (double)a.scale[l];
+            const double m = a.equal_prob ? log((c + 0.5) / ((double)a.cells[l] - c - 0.5)) / (s + s)
+                                           : (double)a.lo[l] + (c + 0.5) / s;
+            a0 -= 2.0 * s * (double)b[1 + l] * m;
+        }
+        for (int l = 0; l < d; ++l) o[1 + l] = (R)(2.0 * (double)a.scale[l] * (double)b[1 + l]);
+        o[0] = (R)a0;
+    }
+}
+
 // ------------------------------------------------------------- launchers
 
 // Dimensions with the equal-probability grid (those of the binary64 and LDS

@@ -1213,7 +1213,7 @@ srmdp_status batch_impl(int n, const srmdp_problem *P, const srmdp_grid *G, cons
 
 extern "C" {
 
-int32_t srmdp_abi_version(void) { return 107; }
+int32_t srmdp_abi_version(void) { return 108; }
 
 const char *srmdp_last_error(void) { return g_error.c_str(); }
 
@@ -1355,6 +1355,36 @@ srmdp_status srmdp_eval(const srmdp_problem *problem, const srmdp_grid *grid, in
     return SRMDP_OK;
 }
 
+
+srmdp_status srmdp_to_raw_basis(const srmdp_problem *problem, const srmdp_grid *grid, int32_t basis,
+                                int32_t prec, const void *table, void *raw, void *stream)
+{
+    g_error.clear();
+    Shape s;
+    srmdp_status rc = check_problem(problem, grid, s);
+    if (rc != SRMDP_OK) return rc;
+    if (basis != SRMDP_LP0 && basis != SRMDP_LP1) return fail(SRMDP_E_INVALID, "unknown basis");
+    if (prec != SRMDP_FP64 && prec != SRMDP_FP32) return fail(SRMDP_E_INVALID, "unknown precision");
+    if (!table || !raw) return fail(SRMDP_E_INVALID, "table and raw are required");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t rsz = prec == SRMDP_FP32 ? 4 : 8;
+    if (basis == SRMDP_LP0) {  // (1) is its own raw basis
+        if (raw != table)
+            HIP_TRY(hipMemcpyAsync(raw, table, (size_t)s.N * s.K * (1 + s.q) * rsz, hipMemcpyDeviceToDevice, st),
+                    "hipMemcpyAsync");
+        return SRMDP_OK;
+    }
+    if (prec == SRMDP_FP32) {
+        StepArgs<float> a;
+        fill_step_args<float>(a, problem, grid, s, nullptr);
+        HIP_TRY(launch_raw_basis<float>(s.d, s.q, a, table, raw, st), "raw-basis kernel");
+    } else {
+        StepArgs<double> a;
+        fill_step_args<double>(a, problem, grid, s, nullptr);
+        HIP_TRY(launch_raw_basis<double>(s.d, s.q, a, table, raw, st), "raw-basis kernel");
+    }
+    return SRMDP_OK;
+}
 
 srmdp_status srmdp_root(const srmdp_problem *problem, const srmdp_grid *grid, const srmdp_options *opts,
                         const void *table, const double *x0, int32_t M_root, double *y0, double *z0,

@@ -144,6 +144,8 @@ hipError_t launch_root(int d, int basis, int lkmode, const StepArgs<R> &a, const
                        const void *lk, const RootPoint &x0, int M_root, int nblocks, double *partial,
                        double *out, hipStream_t st);
 template <typename R>
+hipError_t launch_raw_basis(int d, int q, const StepArgs<R> &a, const void *table, void *raw, hipStream_t st);
+template <typename R>
 hipError_t launch_eval(int d, int basis, const StepArgs<R> &a, const void *table, const double *x,
                        int64_t n, double *y, double *z, hipStream_t st);
 template <typename R>

@@ -13,6 +13,8 @@
 // inverse times the right-hand sides, and the stratum's record is written once
 // to the coefficient table and once, projected on what the driver needs, to a
 // compact look-up row that later steps gather from L2/MALL.
+#include <algorithm>
+
 #include "srmdp_aux.hpp"
 
 namespace srmdp {
@@ -189,6 +191,16 @@ hipError_t launch_eval(int d, int basis, const StepArgs<R> &a, const void *table
 }
 
 template <typename R>
+hipError_t launch_raw_basis(int d, int q, const StepArgs<R> &a, const void *table, void *raw, hipStream_t st)
+{
+    const size_t records = (size_t)a.N * a.K * (size_t)(1 + q);
+    const size_t blocks = std::min<size_t>((records + 255) / 256, 65536);
+    hipLaunchKernelGGL((raw_basis_kernel<R>), dim3((unsigned)blocks), dim3(256), 0, st, a, d, 1 + q,
+                       (const R *)table, (R *)raw, records);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_draw(int d, const StepArgs<R> &a, const SetupArgs &sa, int kind, uint32_t k0,
                        uint32_t nk, uint32_t m0, uint32_t nm, int count, double *out, hipStream_t st)
 {
@@ -284,6 +296,8 @@ size_t cube_global_bytes(int prec_is_float, int M)
                                        double *, hipStream_t);                                       \
     template hipError_t launch_eval<R>(int, int, const StepArgs<R> &, const void *, const double *, \
                                        int64_t, double *, double *, hipStream_t);                    \
+    template hipError_t launch_raw_basis<R>(int, int, const StepArgs<R> &, const void *, void *,    \
+                                            hipStream_t);                                            \
     template hipError_t launch_draw<R>(int, const StepArgs<R> &, const SetupArgs &, int, uint32_t,  \
                                        uint32_t, uint32_t, uint32_t, int, double *, hipStream_t);    \
     template hipError_t launch_setup<R>(const SetupArgs &, const double *, void *, void *, hipStream_t);

@@ -98,7 +98,8 @@ EXPORTS = ("srmdp_table_elems", "srmdp_workspace_bytes", "srmdp_solve", "srmdp_e
            "srmdp_mlp_packed_bytes", "srmdp_mlp_init", "srmdp_mlp_pack", "srmdp_mlp_forward",
            "srmdp_mlp_backward_workspace", "srmdp_mlp_backward", "srmdp_mlp_train_workspace_bytes",
            "srmdp_mlp_train",
-           "srmdp_solve_noalloc", "srmdp_release_graphs", "srmdp_last_error", "srmdp_abi_version")
+           "srmdp_solve_noalloc", "srmdp_to_raw_basis", "srmdp_release_graphs", "srmdp_last_error",
+           "srmdp_abi_version")
 
 
 def _load():
@@ -124,6 +125,8 @@ def _load():
     L.srmdp_eval.argtypes = [P, G, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp,
                              ctypes.c_int64, vp, vp, vp]
     L.srmdp_eval.restype = ctypes.c_int
+    L.srmdp_to_raw_basis.argtypes = [P, G, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.srmdp_to_raw_basis.restype = ctypes.c_int
     L.srmdp_root.argtypes = [P, G, O, vp, dp, ctypes.c_int32, dp, dp, vp, ctypes.c_size_t, vp]
     L.srmdp_root.restype = ctypes.c_int
     L.srmdp_draw.argtypes = [P, G, O, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
@@ -405,6 +408,16 @@ def evaluate(problem: Problem, grid: Grid, basis: int, prec: int, table, i: int,
     _check(lib.srmdp_eval(problem.c(), grid.c(), basis, prec, table.data_ptr(), i, x.data_ptr(),
                           n, y.data_ptr(), z.data_ptr(), _stream_ptr(stream)))
     return y, z
+
+
+def to_raw_basis(problem: Problem, grid: Grid, basis: int, prec: int, table, out=None, stream=None):
+    """The table's coefficients on the paper's raw basis (1, x_1..x_d) (srmdp_to_raw_basis);
+    out may be table itself."""
+    torch = _torch()
+    out = torch.empty_like(table) if out is None else out
+    _check(lib.srmdp_to_raw_basis(problem.c(), grid.c(), basis, prec, table.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(stream)))
+    return out
 
 
 def root(problem: Problem, grid: Grid, opts: Options, table, x0: Sequence[float], M_root: int,

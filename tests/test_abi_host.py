@@ -23,7 +23,7 @@ def test_every_declared_function_is_exported():
     assert declared == set(S.srmdp.EXPORTS)
     for name in declared:
         assert hasattr(S.srmdp.lib, name), name
-    assert S.srmdp.lib.srmdp_abi_version() == 107
+    assert S.srmdp.lib.srmdp_abi_version() == 108
     # the binding's largest dimension is the header's
     assert int(re.search(r"#define SRMDP_MAX_D (\d+)", header).group(1)) == S.srmdp.MAX_D
 
