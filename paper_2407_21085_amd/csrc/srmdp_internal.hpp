@@ -112,19 +112,26 @@ struct LaunchShape {
 };
 
 #if !defined(__HIPCC_RTC__)  // host launchers
-// Launches whose paths gather from at least this many bytes of look-up rows
-// (rows i+1..N-1) miss L2 on most gathers, and their time goes to gather
-// latency: binary32 sweeps then run the path loop that keeps one gather in
-// flight across a step (run_path, PF), at one wavefront per SIMD less; shorter
-// launches keep the plain loop.  Measured at d = 8, K = 4^8, M = 64 (5.2 MB
-// rows): 60.2 ms per sweep with the plain loop, 56.5 ms with the switch at 29
-// rows, 57.7 ms with the pipelined loop everywhere.
+// Depth of the path loop's gather pipeline (run_path, PF) for a launch whose
+// paths gather from the look-up rows i+1..N-1.  Past 144 MiB of rows most
+// gathers miss L2 and the launch time goes to gather latency: binary32 sweeps
+// then keep one gather in flight across a step (one wavefront per SIMD less
+// than the plain loop).  Past 176 MiB the rows no longer stay in the 256 MB
+// last-level cache either, and two gathers in flight (a further wavefront per
+// SIMD less) pay; whole records (look-up mode Full) keep one.  Measured at
+// d = 8, K = 4^8, M = 64 (5.2 MB rows), per sweep: 60.2 ms with the plain
+// loop everywhere, 56.3 ms with depth 1 from 29 rows on, 52.9 ms with depth 2
+// from 29 rows on, which loses to depth 1 below 36 rows and gains up to 19 %
+// per launch beyond.
 constexpr size_t kPrefetchRowBytes = (size_t)144 << 20;
+constexpr size_t kPrefetch2RowBytes = (size_t)176 << 20;
 
 template <typename R, int D, int NB, int LK>
-inline bool prefetch_launch(const StepArgs<R> &a)
+inline int prefetch_depth(const StepArgs<R> &a)
 {
-    return (size_t)(a.N - a.i - 1) * a.K * LookupWidth<R, D, NB, LK>::value * sizeof(R) >= kPrefetchRowBytes;
+    const size_t rows = (size_t)(a.N - a.i - 1) * a.K * LookupWidth<R, D, NB, LK>::value * sizeof(R);
+    if (sizeof(R) != 4 || rows < kPrefetchRowBytes) return 0;
+    return rows >= kPrefetch2RowBytes && LK != kLookupFull ? 2 : 1;
 }
 
 template <typename R>

@@ -51,23 +51,28 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t st)
 
 // --------------------------------------------------------- instantiation
 
+template <typename R, int D, int NB, int LK, int PF>
+static hipError_t launch_step_pf(const StepArgs<R> &a, const LaunchShape &s, const void *cellF, const void *bsig,
+                                 void *lk, void *table, void *counters, hipStream_t st)
+{
+    hipLaunchKernelGGL((sweep_step_kernel<R, D, NB, LK, false, PF>), dim3(s.blocks), dim3(s.threads), s.lds_bytes,
+                       st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
+                       (unsigned long long *)counters);
+    return hipGetLastError();
+}
+
 template <typename R, int D, int NB, int LK>
 static hipError_t launch_step_impl(const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                                    const void *bsig, void *lk, void *table, void *counters,
                                    hipStream_t st)
 {
     if constexpr (sizeof(R) == 4) {
-        if (prefetch_launch<R, D, NB, LK>(a)) {
-            hipLaunchKernelGGL((sweep_step_kernel<R, D, NB, LK, false, true>), dim3(s.blocks), dim3(s.threads),
-                               s.lds_bytes, st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk,
-                               (R *)table, (unsigned long long *)counters);
-            return hipGetLastError();
-        }
+        const int depth = prefetch_depth<R, D, NB, LK>(a);
+        if constexpr (LK != kLookupFull)
+            if (depth == 2) return launch_step_pf<R, D, NB, LK, 2>(a, s, cellF, bsig, lk, table, counters, st);
+        if (depth >= 1) return launch_step_pf<R, D, NB, LK, 1>(a, s, cellF, bsig, lk, table, counters, st);
     }
-    hipLaunchKernelGGL((sweep_step_kernel<R, D, NB, LK, false>), dim3(s.blocks), dim3(s.threads),
-                       s.lds_bytes, st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk,
-                       (R *)table, (unsigned long long *)counters);
-    return hipGetLastError();
+    return launch_step_pf<R, D, NB, LK, 0>(a, s, cellF, bsig, lk, table, counters, st);
 }
 
 template <typename R>

@@ -8,7 +8,7 @@
 
 namespace srmdp {
 
-template <typename R, int D, int NB, int LK, bool PF = false>
+template <typename R, int D, int NB, int LK, int PF = 0>
 __global__ void __launch_bounds__(256) sweep_step_ep_kernel(const StepArgs<R> a,
                                                            const CellF<R> *__restrict__ cellF,
                                                            const R *__restrict__ bsig, R *__restrict__ lk,
@@ -20,22 +20,27 @@ __global__ void __launch_bounds__(256) sweep_step_ep_kernel(const StepArgs<R> a,
                                                                     bsig, lk, table, counters, smem);
 }
 
+template <typename R, int D, int NB, int LK, int PF>
+static hipError_t launch_ep_lds_pf(const StepArgs<R> &a, const LaunchShape &s, const void *cellF, const void *bsig,
+                                   void *lk, void *table, void *counters, hipStream_t st)
+{
+    hipLaunchKernelGGL((sweep_step_ep_kernel<R, D, NB, LK, PF>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st,
+                       a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
+                       (unsigned long long *)counters);
+    return hipGetLastError();
+}
+
 template <typename R, int D, int NB, int LK>
 static hipError_t launch_ep_lds_impl(const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                                      const void *bsig, void *lk, void *table, void *counters, hipStream_t st)
 {
     if constexpr (sizeof(R) == 4) {
-        if (prefetch_launch<R, D, NB, LK>(a)) {
-            hipLaunchKernelGGL((sweep_step_ep_kernel<R, D, NB, LK, true>), dim3(s.blocks), dim3(s.threads),
-                               s.lds_bytes, st, a, (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
-                               (unsigned long long *)counters);
-            return hipGetLastError();
-        }
+        const int depth = prefetch_depth<R, D, NB, LK>(a);
+        if constexpr (LK != kLookupFull)
+            if (depth == 2) return launch_ep_lds_pf<R, D, NB, LK, 2>(a, s, cellF, bsig, lk, table, counters, st);
+        if (depth >= 1) return launch_ep_lds_pf<R, D, NB, LK, 1>(a, s, cellF, bsig, lk, table, counters, st);
     }
-    hipLaunchKernelGGL((sweep_step_ep_kernel<R, D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st, a,
-                       (const CellF<R> *)cellF, (const R *)bsig, (R *)lk, (R *)table,
-                       (unsigned long long *)counters);
-    return hipGetLastError();
+    return launch_ep_lds_pf<R, D, NB, LK, 0>(a, s, cellF, bsig, lk, table, counters, st);
 }
 
 template <typename R, int D>

@@ -320,13 +320,16 @@ struct CvWave {
 // response; every lane of the wavefront must then run the same steps.
 // The first and last steps are peeled off so that the steady loop has no
 // branch that depends on j.
-// PF (built-in problems without the control variate): the positions do not
-// depend on the fitted rows, so X_{j+2} is formed and its record requested
-// while the record of X_{j+1} is evaluated: one gather in flight across a
-// step's arithmetic.  The same operations in the same order: results are
-// bit-identical.
+// PF, the depth of the gather pipeline (built-in problems without the control
+// variate): the positions do not depend on the fitted rows, so with PF = 1
+// X_{j+2} is formed and its record requested while the record of X_{j+1} is
+// evaluated (one gather in flight across a step's arithmetic), and with PF = 2
+// X_{j+3} while the records of X_{j+1} and X_{j+2} are held (two in flight).
+// The same operations in the same order as the plain loop: PF = 1 compiles
+// to the same bits, PF = 2 (whose loop the compiler unrolls) agrees with them
+// to rounding.
 template <typename R, int D, int NB, int LK, bool CV = false, bool EP = false, class Model = BuiltinModel,
-          bool PF = false>
+          int PF = 0>
 __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restrict__ bsig,
                                          const R *__restrict__ lk, NormalStream<R, D> &ns, R *x,
                                          R *dWi_out, R &y1, R &Sp, const CvWave *cv = nullptr,
@@ -369,7 +372,60 @@ __device__ __forceinline__ void run_path(const StepArgs<R> &a, const R *__restri
         x[l] = xn[l];
     }
     R S = (R)0;
-    if constexpr (PF && !CV && !Model::kUser) {
+    if constexpr (PF == 2 && !CV && !Model::kUser) {
+        constexpr int V = LookupWidth<R, D, NB, LK>::value;
+        // Records of X_{j+1} (A) and X_{j+2} (B) in flight while X_{j+3} is formed
+        // and its record (C) requested: two gathers stay in flight across a step.
+        const int nf = N - i - 2;  // driver terms f_j, j = i+1..N-2, from rows i+2..N-1
+        if (nf >= 1) {
+            R xiA[D], recA[V], xiB[D], recB[V];
+            ns.step(1u, dW);
+            model_step<R, D, Model>(a, bsig, i + 1, x, dW, xn);
+            load_record<R, V>(lk + (size_t)(i + 2) * row_elems + locate<R, D, NB, LK, EP>(a, xn, xiA), recA);
+#pragma unroll
+            for (int l = 0; l < D; ++l) x[l] = xn[l];
+            if (nf >= 2) {
+                ns.step(2u, dW);
+                model_step<R, D, Model>(a, bsig, i + 2, x, dW, xn);
+                load_record<R, V>(lk + (size_t)(i + 3) * row_elems + locate<R, D, NB, LK, EP>(a, xn, xiB), recB);
+#pragma unroll
+                for (int l = 0; l < D; ++l) x[l] = xn[l];
+            }
+            for (int j = i + 1; j < N - 3; ++j) {
+                // X_{j+3} from X_{j+2}, and its record requested
+                ns.step((uint32_t)(j + 2 - i), dW);
+                model_step<R, D, Model>(a, bsig, j + 2, x, dW, xn);
+                R xiC[D], recC[V];
+                load_record<R, V>(lk + (size_t)(j + 3) * row_elems + locate<R, D, NB, LK, EP>(a, xn, xiC), recC);
+                // f_j from the record of X_{j+1}
+                R yn, zn;
+                eval_record<R, D, NB, LK>(a, recA, xiA, yn, zn);
+                S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+                zsum_cur = zn;
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    x[l] = xn[l];
+                    xiA[l] = xiB[l];
+                    xiB[l] = xiC[l];
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    recA[v] = recB[v];
+                    recB[v] = recC[v];
+                }
+            }
+            // the last one or two terms, f_{N-3} and f_{N-2}, from the records in flight
+            R yn, zn;
+            eval_record<R, D, NB, LK>(a, recA, xiA, yn, zn);
+            S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+            zsum_cur = zn;
+            if (nf >= 2) {
+                eval_record<R, D, NB, LK>(a, recB, xiB, yn, zn);
+                S += driver_f<R>(a.driver, a.r, a.kappa, a.c_logistic, yn, zsum_cur) * dt;
+                zsum_cur = zn;
+            }
+        }
+    } else if constexpr (PF == 1 && !CV && !Model::kUser) {
         constexpr int V = LookupWidth<R, D, NB, LK>::value;
         if (i + 1 < N - 1) {
             // X_{i+2} and the request of its record (row i+2)
@@ -504,7 +560,7 @@ __device__ __forceinline__ void sample_start_cached(const StepArgs<R> &a, const 
 // i + 1 = N): the fitted row i+1 of the stratum itself (X_i lies in it),
 // truncated, whose product with dW_i / dt has conditional mean zero.
 // scf: the stratum's cell constants (sample_start_cached).
-template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel, bool PF = false>
+template <typename R, int D, int NB, int LK, bool CV, bool EP, class Model = BuiltinModel, int PF = 0>
 __device__ __forceinline__ void simulate_path(const StepArgs<R> &a, const CellF<R> *scf,
                                               const R *__restrict__ bsig, const R *__restrict__ lk,
                                               uint32_t k, uint32_t m, R *phi_out, R *dWi_out,
@@ -619,7 +675,7 @@ __device__ __forceinline__ uint32_t xcd_block_order(uint32_t b, uint32_t n)
 // same counter and reads S', y_{i+1} back.  The launch covers strata
 // a.k0 .. a.k_end-1.
 template <typename R, int D, int NB, int LK, bool CV, bool GR = false, bool EP = false, class Model = BuiltinModel,
-          bool PF = false>
+          int PF = 0>
 __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group,
                                             const CellF<R> *__restrict__ cellF,
                                             const R *__restrict__ bsig, R *__restrict__ lk,
@@ -1083,7 +1139,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     }
 }
 
-template <typename R, int D, int NB, int LK, bool CV, bool PF = false>
+template <typename R, int D, int NB, int LK, bool CV, int PF = 0>
 __global__ void __launch_bounds__(256) sweep_step_kernel(const StepArgs<R> a,
                                                         const CellF<R> *__restrict__ cellF,
                                                         const R *__restrict__ bsig,

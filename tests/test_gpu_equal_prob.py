@@ -9,7 +9,8 @@ library through its C ABI):
   with z truncation, Full), both bases, drift, Ornstein-Uhlenbeck and diffusion
   variants, and d = 8;
 * binary32 steps against the oracle's step from the same rows at the 2e-4
-  bound (strata with a near-face look-up compared separately);
+  bound (strata with a near-face look-up compared separately), small and at
+  the headline size with paths of up to 50 steps;
 * the TABLE and ROOT read-outs of the oracle's own table, at points far out in
   the unbounded cells too.
 """
@@ -100,6 +101,22 @@ def test_equal_probability_fp32_per_step_parity(d, cells, M, basis):
     assert err <= TP.TOL["fp32"]
     assert share < 0.1
     assert excess <= 0.0
+
+
+def test_equal_probability_full_size_long_paths_parity():
+    """The headline workload (d = 8, K = 4^8, M = 64, N = 50, binary32) on
+    equal-probability cells, y truncated at 1 as the benchmark runs it: steps
+    49, 16 and 0 of the library's sweep (paths of 1, 34 and 50 steps, through
+    the plain path loop and the loops with one and two gathers in flight)
+    against the oracle's step run from the library's own rows above it."""
+    cfg = _ep("cfg5", "equal-probability headline size fp32", clamp_y=1.0)
+    err, excess, share = TP.fp32_own_rows_parity(cfg, [49, 16, 0], eps=2e-5)
+    assert err <= TP.TOL["fp32"]
+    assert excess <= 0.0
+    # a stratum is flagged when any of its 64 x 50 x 8 coordinate look-ups
+    # lies within 2e-5 cell widths of an interior face: about half of them at
+    # 50-step paths (each flagged stratum is still held to its flip bound)
+    assert share < 0.7
 
 
 @pytest.mark.parametrize("basis", ["LP0", "LP1"])

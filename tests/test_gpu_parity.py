@@ -483,11 +483,12 @@ def test_cfg5_full_size_last_steps_parity():
 
 def test_cfg5_full_size_long_paths_parity():
     """The headline size in the benchmark's launch configuration, on the long
-    paths: steps 49, 25 and 0 of the library's full binary32 sweep (paths of 1,
-    25 and 50 Euler steps) against the oracle's step run from the library's
-    own rows above it."""
+    paths: steps 49, 25, 16 and 0 of the library's full binary32 sweep (paths
+    of 1, 25, 34 and 50 Euler steps, which run the plain path loop, the plain
+    loop, the loop with one gather in flight and the loop with two) against
+    the oracle's step run from the library's own rows above it."""
     cfg = W.config("cfg5")
-    err, excess, share = fp32_own_rows_parity(cfg, [49, 25, 0])
+    err, excess, share = fp32_own_rows_parity(cfg, [49, 25, 16, 0])
     assert err <= TOL["fp32"]
     assert excess <= 0.0
     assert share < 0.2
