@@ -34,11 +34,14 @@ template <typename R, int D, int NB, int LK>
 static hipError_t launch_ep_lds_impl(const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                                      const void *bsig, void *lk, void *table, void *counters, hipStream_t st)
 {
+    // At most one gather in flight: the longer cell location of these cells
+    // (a logistic CDF and a table read per coordinate) keeps the SIMDs busier,
+    // and the third wavefront per SIMD is worth more than the second gather
+    // (67.4 against 67.7 ms per sweep of the d = 8, K = 4^8, M = 64, N = 50
+    // workload).
     if constexpr (sizeof(R) == 4) {
-        const int depth = prefetch_depth<R, D, NB, LK>(a);
-        if constexpr (LK != kLookupFull)
-            if (depth == 2) return launch_ep_lds_pf<R, D, NB, LK, 2>(a, s, cellF, bsig, lk, table, counters, st);
-        if (depth >= 1) return launch_ep_lds_pf<R, D, NB, LK, 1>(a, s, cellF, bsig, lk, table, counters, st);
+        if (prefetch_depth<R, D, NB, LK>(a) >= 1)
+            return launch_ep_lds_pf<R, D, NB, LK, 1>(a, s, cellF, bsig, lk, table, counters, st);
     }
     return launch_ep_lds_pf<R, D, NB, LK, 0>(a, s, cellF, bsig, lk, table, counters, st);
 }

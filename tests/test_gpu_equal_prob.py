@@ -107,8 +107,8 @@ def test_equal_probability_full_size_long_paths_parity():
     """The headline workload (d = 8, K = 4^8, M = 64, N = 50, binary32) on
     equal-probability cells, y truncated at 1 as the benchmark runs it: steps
     49, 16 and 0 of the library's sweep (paths of 1, 34 and 50 steps, through
-    the plain path loop and the loops with one and two gathers in flight)
-    against the oracle's step run from the library's own rows above it."""
+    the plain path loop and the loop with one gather in flight) against the
+    oracle's step run from the library's own rows above it."""
     cfg = _ep("cfg5", "equal-probability headline size fp32", clamp_y=1.0)
     err, excess, share = TP.fp32_own_rows_parity(cfg, [49, 16, 0], eps=2e-5)
     assert err <= TP.TOL["fp32"]
