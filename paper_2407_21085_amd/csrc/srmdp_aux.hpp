@@ -231,22 +231,14 @@ __global__ void raw_basis_kernel(const StepArgs<R> a, int d, int q1, const R *ta
 
 // ------------------------------------------------------------- launchers
 
-// Dimensions with the equal-probability grid (those of the binary64 and LDS
-// sweep kernels); the kernels of the other dimensions take equal-size cells only.
-template <int D>
-constexpr bool kEqualProbDim = D <= 6 || D == 8;
-
 template <typename R, int D, int NB>
 static hipError_t launch_face_flags_impl(const StepArgs<R> &a, const void *cellF, const void *bsig,
                                          void *counters, hipStream_t st)
 {
     if (a.equal_prob) {
-        if constexpr (kEqualProbDim<D>) {
-            hipLaunchKernelGGL((face_flags_kernel<R, D, NB, true>), dim3(a.K), dim3(64), 0, st, a,
-                               (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
-            return hipGetLastError();
-        }
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((face_flags_kernel<R, D, NB, true>), dim3(a.K), dim3(64), 0, st, a,
+                           (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((face_flags_kernel<R, D, NB, false>), dim3(a.K), dim3(64), 0, st, a,
                        (const CellF<R> *)cellF, (const R *)bsig, (unsigned long long *)counters);
@@ -270,12 +262,8 @@ static hipError_t launch_root_impl(const StepArgs<R> &a, const void *bsig, const
                                    double *out, hipStream_t st)
 {
     if (a.equal_prob) {
-        if constexpr (kEqualProbDim<D>) {
-            hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK, true>), dim3(nblocks), dim3(256), 0, st, a,
-                               (const R *)bsig, (const R *)lk, x0, M_root, partial);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK, true>), dim3(nblocks), dim3(256), 0, st, a,
+                           (const R *)bsig, (const R *)lk, x0, M_root, partial);
     } else {
         hipLaunchKernelGGL((root_paths_kernel<R, D, NB, LK, false>), dim3(nblocks), dim3(256), 0, st, a,
                            (const R *)bsig, (const R *)lk, x0, M_root, partial);
@@ -294,12 +282,9 @@ static hipError_t launch_eval_impl(const StepArgs<R> &a, const void *table, cons
     const int64_t blocks64 = (n + 255) / 256;
     const int blocks = (int)(blocks64 < 16384 ? (blocks64 > 0 ? blocks64 : 1) : 16384);
     if (a.equal_prob) {
-        if constexpr (kEqualProbDim<D>) {
-            hipLaunchKernelGGL((eval_kernel<R, D, NB, true>), dim3(blocks), dim3(256), 0, st, a,
-                               (const R *)table, x, n, y, z);
-            return hipGetLastError();
-        }
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((eval_kernel<R, D, NB, true>), dim3(blocks), dim3(256), 0, st, a, (const R *)table, x,
+                           n, y, z);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((eval_kernel<R, D, NB, false>), dim3(blocks), dim3(256), 0, st, a, (const R *)table,
                        x, n, y, z);

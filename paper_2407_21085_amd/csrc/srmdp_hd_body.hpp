@@ -5,15 +5,16 @@
 //   HD_FN(name)   the names of its launchers,
 //   HD_NEXT(name) the launchers that take the other dimensions,
 //   HD_KERNEL, HD_IMPL  names of its kernel and launch helper.
-// Binary32 sweeps with streamed clouds and look-up modes Y and
-// YZ; every kernel around the sweep in both precisions.
+// Binary32 sweeps with streamed clouds, look-up modes Y and YZ, on equal-size
+// or equal-probability cells; every kernel around the sweep in both
+// precisions.
 #include <type_traits>
 
 #include "srmdp_aux.hpp"
 
 namespace srmdp {
 
-template <typename R, int D, int NB, int LK>
+template <typename R, int D, int NB, int LK, bool EP>
 __global__ void __launch_bounds__(256) HD_KERNEL(const StepArgs<R> a,
                                                            const CellF<R> *__restrict__ cellF,
                                                            const R *__restrict__ bsig, R *__restrict__ lk,
@@ -21,17 +22,23 @@ __global__ void __launch_bounds__(256) HD_KERNEL(const StepArgs<R> a,
                                                            unsigned long long *__restrict__ counters)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sweep_group<R, D, NB, LK, false, true>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table,
-                                           counters, smem);
+    sweep_group<R, D, NB, LK, false, true, EP>(a, xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table,
+                                               counters, smem);
 }
 
+// Equal-size or equal-probability cells (StepArgs::equal_prob).
 template <int D, int NB, int LK>
 static hipError_t HD_IMPL(const StepArgs<float> &a, const LaunchShape &s, const void *cellF, const void *bsig,
                                  void *lk, void *table, void *counters, hipStream_t st)
 {
-    hipLaunchKernelGGL((HD_KERNEL<float, D, NB, LK>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st,
-                       a, (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
-                       (unsigned long long *)counters);
+    if (a.equal_prob)
+        hipLaunchKernelGGL((HD_KERNEL<float, D, NB, LK, true>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st,
+                           a, (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
+                           (unsigned long long *)counters);
+    else
+        hipLaunchKernelGGL((HD_KERNEL<float, D, NB, LK, false>), dim3(s.blocks), dim3(s.threads), s.lds_bytes, st,
+                           a, (const CellF<float> *)cellF, (const float *)bsig, (float *)lk, (float *)table,
+                           (unsigned long long *)counters);
     return hipGetLastError();
 }
 

@@ -238,8 +238,6 @@ srmdp_status check_options(const srmdp_options *o, const Shape &s, int &nb)
     if ((o->flags & SRMDP_F_GLOBAL_ROWS) && o->cv != SRMDP_CV_NONE)
         return fail(SRMDP_E_UNSUPPORTED, "global cloud rows run without the control variate");
 
-    if (s.equal_prob && !lds_dimension_compiled(s.d))
-        return fail(SRMDP_E_UNSUPPORTED, "equal-probability cells are compiled for d = 1..6 and 8, not %d", s.d);
     if ((o->flags & SRMDP_F_CV_CENTER_Z) && o->cv == SRMDP_CV_NONE)
         return fail(SRMDP_E_INVALID, "SRMDP_F_CV_CENTER_Z needs a control variate");
     if (o->cv_stride > 65535) return fail(SRMDP_E_INVALID, "cv_stride above 65535");

@@ -3,7 +3,8 @@
 // every cube of nu-probability 1/K), for the dimensions of the LDS kernels, in
 // both precisions and every look-up mode: the clouds in LDS
 // (sweep_step_ep_kernel) or, when they do not fit, streamed (the body
-// of srmdp_gr.hpp).  The equal-size kernels keep no code of this grid.
+// of srmdp_gr.hpp).  The other dimensions run the high-dimension kernels'
+// equal-probability form.  The equal-size kernels keep no code of this grid.
 #include "srmdp_gr.hpp"
 
 namespace srmdp {
@@ -88,7 +89,7 @@ hipError_t launch_step_ep(int d, const StepArgs<R> &a, const LaunchShape &s, int
     case DD: return dispatch_gr_d<R, DD, true>(a, s, basis, lkmode, cellF, bsig, lk, table, counters, st);
         SRMDP_GR_FOR_EACH_D(X)
 #undef X
-    default: return hipErrorInvalidValue;
+    default: return launch_step_gr_hd<R>(d, a, s, basis, lkmode, cellF, bsig, lk, table, counters, st);
     }
 }
 

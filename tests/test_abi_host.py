@@ -283,10 +283,9 @@ def test_batch_workspace_and_rejections():
 def test_equal_probability_grid_host_checks():
     """Equal-probability cells: lo and hi may be NULL; the workspace is that of
     an equal-size grid of the same shape (clouds in LDS, or in global memory
-    with SRMDP_F_GLOBAL_ROWS); the control variate with z truncation, the
-    dimensions without the LDS kernel and an unknown grid kind are refused
-    before anything is
-    enqueued; a batch may hold equal-probability instances when all of them
+    with SRMDP_F_GLOBAL_ROWS); the control variate with z truncation, binary64
+    sweeps and z truncation at the dimensions without the LDS kernel, and an
+    unknown grid kind are refused before anything is enqueued; a batch may hold equal-probability instances when all of them
     do."""
     import ctypes
     S = _S()
@@ -301,10 +300,13 @@ def test_equal_probability_grid_host_checks():
     cv = S.Options(M=40, prec=S.FP32, cv=1, cv_params=_FakeTensor())
     Pz = S.Problem(d=2, N=4, clamp_z=0.3)   # z truncation: look-up mode Full
     assert lib.srmdp_solve(Pz.c(), Gp.c(), cv.c(), 16, 16, 1 << 40, None, None) == -2
+    # the dimensions without the LDS kernel take equal-probability cells as they
+    # take equal-size ones: binary32 sweeps without z truncation
     G7 = S.Grid(None, None, [2] * 7, kind=S.GRID_EQUAL_PROB)
-    rc = lib.srmdp_solve(S.Problem(d=7, N=3).c(), G7.c(), S.Options(M=40, prec=S.FP32).c(), 16, 16, 1 << 40,
-                         None, None)
-    assert rc == -2, lib.srmdp_last_error().decode()
+    for prob, opts in ((S.Problem(d=7, N=3), S.Options(M=40, prec=S.FP64)),
+                       (S.Problem(d=7, N=3, clamp_z=0.3), S.Options(M=40, prec=S.FP32))):
+        rc = lib.srmdp_solve(prob.c(), G7.c(), opts.c(), 16, 16, 1 << 40, None, None)
+        assert rc == -2, lib.srmdp_last_error().decode()
     Gbad = S.Grid([-2.0] * 2, [2.0] * 2, [5, 4], 1.3, kind=7)
     assert lib.srmdp_solve(P.c(), Gbad.c(), S.Options(M=40).c(), 16, 16, 1 << 40, None, None) == -1
     Gnull = S.Grid(None, None, [5, 4], 1.3)   # equal size without lo/hi

@@ -9,10 +9,11 @@ library through its C ABI):
   with z truncation, Full), both bases, drift, Ornstein-Uhlenbeck and diffusion
   variants, and d = 8;
 * binary32 steps against the oracle's step from the same rows at the 2e-4
-  bound (strata with a near-face look-up compared separately), small and at
-  the headline size with paths of up to 50 steps;
+  bound (strata with a near-face look-up compared separately), small, at the
+  high dimensions (d = 7, 11, 12, 17, 19) and at the headline size with paths
+  of up to 50 steps;
 * the TABLE and ROOT read-outs of the oracle's own table, at points far out in
-  the unbounded cells too.
+  the unbounded cells too, also at d = 13.
 """
 import sys
 
@@ -101,6 +102,47 @@ def test_equal_probability_fp32_per_step_parity(d, cells, M, basis):
     assert err <= TP.TOL["fp32"]
     assert share < 0.1
     assert excess <= 0.0
+
+
+@pytest.mark.parametrize("d,cells,M,basis", [(7, [2] * 7, 40, "LP1"), (11, [3] * 3 + [2] * 4 + [1] * 4, 32, "LP0"),
+                                             (12, [2] * 6 + [1] * 6, 48, "LP1"),
+                                             (17, [2] * 6 + [1] * 11, 40, "LP1"),
+                                             (19, [2] * 7 + [1] * 12, 48, "LP1")])
+def test_equal_probability_high_dimension_per_step_parity(d, cells, M, basis):
+    """The dimensions of the high-dimension kernels (clouds streamed through
+    LDS, binary32): each step against the oracle's step from the same rows."""
+    cfg = _ep("cfg2", f"equal-probability logistic d={d} {basis} fp32", d=d, N=3, cells=cells, M=M,
+              basis=basis, mu=1.0)
+    err, excess, share = TP.fp32_step_parity(cfg, [2, 1, 0], eps=2e-5)
+    assert err <= TP.TOL["fp32"]
+    assert share < 0.1
+    assert excess <= 0.0
+
+
+def test_equal_probability_high_dimension_readouts_of_oracle_table():
+    """d = 13, LP1: the TABLE read-out at points far out in the unbounded cells
+    and the ROOT read-out of the oracle's own binary64 table, against the
+    oracle's."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    d = 13
+    cfg = _ep("cfg1", "equal-probability cos d=13 LP1 fp64", prec="fp64", d=d, N=3, cells=[2] * 5 + [1] * 8,
+              M=40, r=0.1, mu=1.2)
+    Po = oracle_problem(cfg)
+    orc, _ = O.solve(Po)
+    P, G, Opt = product_args(cfg)
+    table = torch.from_numpy(orc).cuda()
+    _say("[gpu] d = 13 equal-probability read-outs of the oracle's table")
+    x0 = [0.2] * d
+    y0, z0 = S.root(P, G, Opt, table, x0, 20000)
+    yo, zo = O.root(Po, orc, x0, 20000)
+    assert y0 == pytest.approx(yo, rel=1e-9)
+    np.testing.assert_allclose(z0, zo, rtol=1e-8, atol=1e-10)
+    pts = np.random.default_rng(4).uniform(-9.0, 9.0, (257, d))
+    y, z = S.evaluate(P, G, Opt.basis, Opt.prec, table, 1, torch.from_numpy(pts).cuda())
+    ye, ze = O.evaluate(Po, orc, 1, pts)
+    np.testing.assert_allclose(y.cpu().numpy(), ye, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(z.cpu().numpy(), ze, rtol=1e-12, atol=1e-14)
 
 
 def test_equal_probability_full_size_long_paths_parity():
