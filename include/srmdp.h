@@ -49,7 +49,7 @@ extern "C" {
 #define SRMDP_MAX_D 19          /* largest d = q compiled.  d = 1..6 and 8 run every
                                  * option; d = 7 and 9..19 run binary32 sweeps with
                                  * look-up modes Y and YZ (no z truncation), without
-                                 * the control variate, on equal-size cells; other
+                                 * the control variate, on either grid kind; other
                                  * requests return SRMDP_E_UNSUPPORTED */
 #define SRMDP_ROOT_STRATUM 0xFFFFFFFFu  /* counter stratum tag of ROOT paths */
 
@@ -100,11 +100,13 @@ typedef enum { SRMDP_G_COS_SUM = 0, SRMDP_G_LOGISTIC = 1 } srmdp_terminal;
  *  params   host [n_params] or NULL: p[0..n_params-1] of the functions above,
  *           converted to srmdp_real (a new value needs no new compilation).
  *  n_params 0..64.
- * Kernels are compiled once per (device, source, d, basis, precision) and
- * kept for the process.  A compilation error returns SRMDP_E_INVALID with the
- * compiler's log in srmdp_last_error().  Covered: srmdp_solve (equal-size
- * cells, clouds in LDS, d <= 8, no control variate), srmdp_eval; other
- * entry points return SRMDP_E_UNSUPPORTED for a problem with a model. */
+ * Kernels are compiled once per (device, source, d, basis, precision, grid
+ * kind, cloud storage) and kept for the process.  A compilation error returns
+ * SRMDP_E_INVALID with the compiler's log in srmdp_last_error().  Covered:
+ * srmdp_solve (d <= 8, either grid kind, clouds in LDS or, for large M or with
+ * SRMDP_F_GLOBAL_ROWS, streamed through it; no control variate or
+ * autotuner), srmdp_eval; other entry points return SRMDP_E_UNSUPPORTED for a
+ * problem with a model. */
 typedef struct {
     const char *source;
     const double *params;

@@ -517,12 +517,18 @@ bool make_shape(const Shape &s, int nb, int is_float, int M, int L, LaunchShape 
 
 // One backward step without the control variate: one launch, or with global
 // rows one launch per ls.kc strata.
+// mk: the problem's own model kernels (compiled for this shape's grid kind and
+// cloud storage), or nullptr for the built-in problems.
 template <typename R>
 hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &ls, int basis, int lk,
                              unsigned char *ws, size_t off_cellF, size_t off_bsig, size_t off_lookup,
-                             size_t off_counters, size_t off_grows, void *table, hipStream_t st)
+                             size_t off_counters, size_t off_grows, void *table, hipStream_t st,
+                             const ModelKernels *mk = nullptr)
 {
     a.cell_table = ws + off_cellF;
+    if (!ls.grows && mk)
+        return launch_model_step<R>(*mk, a, ls, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
+                                    ws + off_counters, st);
     if (!ls.grows && a.equal_prob)
         return launch_step_ep_lds<R>(s.d, a, ls, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
                                      ws + off_counters, st);
@@ -538,8 +544,11 @@ hipError_t launch_plain_step(const Shape &s, StepArgs<R> &a, const LaunchShape &
         a.stage_chunks = ls.stage_chunks;
         LaunchShape sub = ls;
         sub.blocks = (a.k_end - k0 + cpw - 1) / cpw;
-        const hipError_t e = launch_step_gr<R>(s.d, a, sub, basis, lk, ws + off_cellF, ws + off_bsig,
-                                               ws + off_lookup, table, ws + off_counters, st);
+        const hipError_t e =
+            mk ? launch_model_step<R>(*mk, a, sub, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
+                                      ws + off_counters, st)
+               : launch_step_gr<R>(s.d, a, sub, basis, lk, ws + off_cellF, ws + off_bsig, ws + off_lookup, table,
+                                   ws + off_counters, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -560,20 +569,21 @@ srmdp_status sweep_supported(const Shape &s, const srmdp_options *o, int lk)
     return SRMDP_OK;
 }
 
-// What a problem with its own model runs: the LDS sweep on equal-size cells
-// for the dimensions compiled with it, without the control variate, the
-// autotuner or streamed clouds.
-srmdp_status model_supported(const Shape &s, int nb, const srmdp_options *o)
+// What a problem with its own model runs: d = 1..8 (its look-ups read whole
+// records, (d + 1)^2 coefficients for LP1), either grid kind, clouds in LDS or
+// streamed through it (large M, or SRMDP_F_GLOBAL_ROWS), without the control
+// variate or the autotuner.  *streamed tells which cloud storage the shape
+// takes, for which the model's kernel is compiled.
+srmdp_status model_supported(const Shape &s, int nb, const srmdp_options *o, bool *streamed)
 {
-    if (s.equal_prob) return fail(SRMDP_E_UNSUPPORTED, "a model runs on equal-size cells");
-    if (!lds_dimension_compiled(s.d)) return fail(SRMDP_E_UNSUPPORTED, "a model runs for d = 1..6 and 8");
+    if (s.d > 8) return fail(SRMDP_E_UNSUPPORTED, "a model runs for d = 1..8");
     if (o->cv != SRMDP_CV_NONE) return fail(SRMDP_E_UNSUPPORTED, "a model runs without the control variate");
-    if (o->flags & (SRMDP_F_AUTOTUNE | SRMDP_F_GLOBAL_ROWS))
-        return fail(SRMDP_E_UNSUPPORTED, "a model runs without the autotuner and global cloud rows");
+    if (o->flags & SRMDP_F_AUTOTUNE) return fail(SRMDP_E_UNSUPPORTED, "a model runs without the autotuner");
     LaunchShape ls;
     size_t per_cube;
-    if (!make_shape(s, nb, o->prec == SRMDP_FP32, o->M, lanes_for(o), ls, per_cube, false, o) || ls.grows)
-        return fail(SRMDP_E_UNSUPPORTED, "a model runs with clouds in LDS (M = %d is too large)", o->M);
+    if (!make_shape(s, nb, o->prec == SRMDP_FP32, o->M, lanes_for(o), ls, per_cube, false, o))
+        return fail(SRMDP_E_UNSUPPORTED, "no launch shape fits M = %d", o->M);
+    *streamed = ls.grows;
     return SRMDP_OK;
 }
 
@@ -684,8 +694,8 @@ srmdp_status enqueue_sweep(const srmdp_problem *p, const srmdp_grid *g, const sr
             }
         }
         if (mk) {
-            HIP_TRY(launch_model_step<R>(*mk, a, ls, ws + lay.cellF, ws + lay.bsig, ws + lay.lookup, table,
-                                         ws + lay.counters, st),
+            HIP_TRY(launch_plain_step<R>(s, a, ls, o->basis, lk, ws, lay.cellF, lay.bsig, lay.lookup, lay.counters,
+                                         lay.grows, table, st, mk),
                     "sweep step (model)");
             launched = true;
         }
@@ -1249,16 +1259,19 @@ srmdp_status srmdp_solve(const srmdp_problem *problem, const srmdp_grid *grid,
     const size_t need = layout(s, nb, opts->prec == SRMDP_FP32, lookup_mode(problem), opts).total;
     if (ws_bytes < need)
         return fail(SRMDP_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-    rc = sweep_supported(s, opts, lookup_mode(problem));
-    if (rc != SRMDP_OK) return rc;
+    if (!problem->model) {  // a model's kernels are compiled for it (model_supported below)
+        rc = sweep_supported(s, opts, lookup_mode(problem));
+        if (rc != SRMDP_OK) return rc;
+    }
     hipStream_t st = (hipStream_t)stream;
     srmdp_options o = *opts;
     ModelKernels mk;
     const ModelKernels *mkp = nullptr;
     if (problem->model) {
-        rc = model_supported(s, nb, opts);
+        bool streamed = false;
+        rc = model_supported(s, nb, opts, &streamed);
         if (rc != SRMDP_OK) return rc;
-        rc = model_kernels(problem->model, s.d, nb, opts->prec == SRMDP_FP32, mk);
+        rc = model_kernels(problem->model, s.d, nb, opts->prec == SRMDP_FP32, s.equal_prob, streamed, mk);
         if (rc != SRMDP_OK) return rc;
         mkp = &mk;
     }

@@ -256,11 +256,13 @@ hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s
 
 // Kernels of a problem's own model (srmdp_model), compiled at run time for the
 // current device (srmdp_rtc.cpp): hipFunction_t of the step kernel and of the
-// near-face diagnostic.
+// near-face diagnostic, for the grid kind (equal_prob) and the cloud storage
+// (streamed: clouds streamed through LDS, LaunchShape::grows) of the shape.
 struct ModelKernels {
     void *step = nullptr, *face_flags = nullptr;
 };
-srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, ModelKernels &out);
+srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, bool equal_prob, bool streamed,
+                           ModelKernels &out);
 template <typename R>
 hipError_t launch_model_step(const ModelKernels &k, const StepArgs<R> &a, const LaunchShape &s, const void *cellF,
                              const void *bsig, void *lk, void *table, void *counters, hipStream_t st);

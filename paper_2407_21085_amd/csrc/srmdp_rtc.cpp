@@ -5,7 +5,9 @@
 //
 // The device code is the library's own (srmdp_sweep.hpp and the headers it
 // includes, embedded at build time); the model enters as the policy `Model`
-// of sweep_group / face_flags_kernel, whose look-ups read whole records.
+// of sweep_group / face_flags_kernel, whose look-ups read whole records.  One
+// program per model, dimension, basis, precision, grid kind and cloud storage
+// (in LDS, or streamed through it for large M).
 // hipRTC is opened with dlopen on the first model, so problems without one
 // never load it.
 #include "../../include/srmdp.h"
@@ -77,7 +79,7 @@ const RtcApi &rtc_api()
 // The run-time translation unit: the integer types (hipRTC keeps them in a
 // namespace of its own), the sweep device code, the caller's source, the
 // policy that calls it, and the step kernel.
-std::string kernel_source(const srmdp_model *m, int d, int nb, bool is_float)
+std::string kernel_source(const srmdp_model *m, int d, int nb, bool is_float, bool ep, bool gr)
 {
     std::string s;
     s += "using __hip_internal::uint8_t; using __hip_internal::uint16_t; using __hip_internal::uint32_t;\n"
@@ -122,17 +124,17 @@ std::string kernel_source(const srmdp_model *m, int d, int nb, bool is_float)
          "                 srmdp_real *__restrict__ table, unsigned long long *__restrict__ counters)\n"
          "{\n"
          "    extern __shared__ __align__(16) unsigned char smem[];\n"
-         "    srmdp::sweep_group<srmdp_real, " + D + ", " + NB +
-         ", srmdp::kLookupFull, false, false, false, srmdp_model_glue::Model>(\n"
+         "    srmdp::sweep_group<srmdp_real, " + D + ", " + NB + ", srmdp::kLookupFull, false, " +
+         (gr ? "true" : "false") + ", " + (ep ? "true" : "false") + ", srmdp_model_glue::Model>(\n"
          "        a, srmdp::xcd_block_order(blockIdx.x, gridDim.x), cellF, bsig, lk, table, counters, smem);\n"
          "}\n";
     return s;
 }
 
-std::string face_flags_name(int d, int nb, bool is_float)
+std::string face_flags_name(int d, int nb, bool is_float, bool ep)
 {
     return std::string("srmdp::face_flags_kernel<") + (is_float ? "float" : "double") + ", " + std::to_string(d) +
-           ", " + std::to_string(nb) + ", false, srmdp_model_glue::Model>";
+           ", " + std::to_string(nb) + (ep ? ", true" : ", false") + ", srmdp_model_glue::Model>";
 }
 
 struct Entry {
@@ -144,13 +146,15 @@ std::unordered_map<std::string, Entry> g_rtc;
 
 }  // namespace
 
-srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, ModelKernels &out)
+srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, bool equal_prob, bool streamed,
+                           ModelKernels &out)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return set_error(SRMDP_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
     std::string key = std::to_string(dev) + "|" + std::to_string(d) + "|" + std::to_string(nb) + "|" +
-                      std::to_string(is_float) + "|" + m->source;
+                      std::to_string(is_float) + "|" + (equal_prob ? "ep|" : "es|") + (streamed ? "gr|" : "lds|") +
+                      m->source;
     std::lock_guard<std::mutex> lock(g_rtc_mu);
     auto it = g_rtc.find(key);
     if (it == g_rtc.end()) {
@@ -161,12 +165,12 @@ srmdp_status model_kernels(const srmdp_model *m, int d, int nb, int is_float, Mo
         if (e != hipSuccess) return set_error(SRMDP_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
         std::string arch = prop.gcnArchName;
         arch = "--offload-arch=" + arch.substr(0, arch.find(':'));
-        const std::string src = kernel_source(m, d, nb, is_float != 0);
+        const std::string src = kernel_source(m, d, nb, is_float != 0, equal_prob, streamed);
         hiprtcProgram prog;
         if (api.create(&prog, src.c_str(), "srmdp_model.hip", kRtcHeaderCount, kRtcHeaderBodies,
                        kRtcHeaderNames) != HIPRTC_SUCCESS)
             return set_error(SRMDP_E_HIP, "hiprtcCreateProgram failed");
-        const std::string ff = face_flags_name(d, nb, is_float != 0);
+        const std::string ff = face_flags_name(d, nb, is_float != 0, equal_prob);
         api.add_name(prog, ff.c_str());
         // packed binary32 instructions are kept out, as in the compiled kernels
         const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",

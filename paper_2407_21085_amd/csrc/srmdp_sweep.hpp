@@ -683,7 +683,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                                             unsigned long long *__restrict__ counters,
                                             unsigned char *smem)
 {
-    static_assert(!(GR && (CV || Model::kUser)), "streamed clouds run without the control variate or a model");
+    static_assert(!(GR && CV), "streamed clouds run without the control variate");
     using Lay = CubeLds<R, D, NB, CV>;
     constexpr int SW = Lay::SW;
     constexpr int REC = (1 + D) * NB;
@@ -827,8 +827,8 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                     const int m = r0 + u;
                     R *row = rows + (size_t)u * SW;
                     R Sp, y1, cvi, centre;
-                    simulate_path<R, D, NB, LK, false, EP>(a, scf, bsig, lk, k, (uint32_t)m, row, row + NB, Sp,
-                                                           y1, &cv, &cvi, &centre);
+                    simulate_path<R, D, NB, LK, false, EP, Model>(a, scf, bsig, lk, k, (uint32_t)m, row, row + NB,
+                                                                  Sp, y1, &cv, &cvi, &centre);
                     row[NB + D] = Sp;
                     row[NB + D + 1] = y1;
                     sy[2 * (size_t)m] = Sp;
@@ -1008,7 +1008,24 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
                     R *row = rows + (size_t)u * YW;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) row[b] = phi[b];
-                    row[NB] = y_response(phi, sy[2 * (size_t)m], sy[2 * (size_t)m + 1]);
+                    if constexpr (Model::kUser) {
+                        // the model's driver at X_i with every z_{i,c}(X_i), as in
+                        // the clouds held in LDS
+                        R z[D];
+#pragma unroll 1
+                        for (int c = 0; c < D; ++c) {
+                            R v = (R)0;
+#pragma unroll
+                            for (int b = 0; b < NB; ++b) v += (R)beta[(1 + c) * NB + b] * phi[b];
+                            z[c] = clamp_level<R>(v, a.clamp_z);
+                        }
+                        R Sy = sy[2 * (size_t)m];
+                        Sy += Model::template driver<R, D>(a, bsig, (R)a.i * a.dt, x, sy[2 * (size_t)m + 1], z) *
+                              a.dt;
+                        row[NB] = Sy;
+                    } else {
+                        row[NB] = y_response(phi, sy[2 * (size_t)m], sy[2 * (size_t)m + 1]);
+                    }
                 }
             }
             __syncthreads();

@@ -381,11 +381,24 @@ def test_model_arguments_rejected_before_compiling(name, mkw, pkw):
 
 def test_model_refused_where_not_supported():
     """Batches and the no-allocation entry point refuse a model before any
-    HIP call (compiling one allocates)."""
+    HIP call (compiling one allocates); srmdp_solve refuses a model above
+    d = 8 (whole records of (d + 1)^2 coefficients per look-up), with the
+    control variate or with the autotuner before compiling it."""
     S = _S()
-    P = S.Problem(d=2, N=4, model=S.Model("__device__ void srmdp_b() {}"))
+    src = "__device__ void srmdp_b() {}"
+    P = S.Problem(d=2, N=4, model=S.Model(src))
     G = S.Grid([-1.0] * 2, [1.0] * 2, [2, 2])
     O = S.Options(M=16)
     rc = S.srmdp.lib.srmdp_solve_noalloc(P.c(), G.c(), O.c(), 16, None)
     assert rc == S.srmdp.E_INVALID
     assert "model" in S.srmdp.lib.srmdp_last_error().decode()
+    lib = S.srmdp.lib
+    P9 = S.Problem(d=9, N=3, model=S.Model(src))
+    G9 = S.Grid([-1.0] * 9, [1.0] * 9, [2] + [1] * 8)
+    assert lib.srmdp_solve(P9.c(), G9.c(), S.Options(M=16, prec=S.FP32).c(), 16, 16, 1 << 40, None,
+                           None) == S.srmdp.E_UNSUPPORTED
+    assert "d = 1..8" in lib.srmdp_last_error().decode()
+    cv = S.Options(M=16, prec=S.FP32, cv=1, cv_params=_FakeTensor())
+    assert lib.srmdp_solve(P.c(), G.c(), cv.c(), 16, 16, 1 << 40, None, None) == S.srmdp.E_UNSUPPORTED
+    tuned = S.Options(M=16, flags=S.F_AUTOTUNE)
+    assert lib.srmdp_solve(P.c(), G.c(), tuned.c(), 16, 16, 1 << 40, None, None) == S.srmdp.E_UNSUPPORTED

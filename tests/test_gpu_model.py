@@ -11,6 +11,8 @@ separately in C (tests/test_oracle_model.py pins that path of the oracle).
 
 Binary64 sweeps at 1e-9 over every step; binary32 steps at 2e-4 plus the
 oracle's face-flip bound (it takes the model's Lipschitz constants in y and z).
+Also: clouds streamed through LDS (large M, and SRMDP_F_GLOBAL_ROWS bit-identical
+to the clouds in LDS), equal-probability cells, and d = 7.
 """
 import sys
 
@@ -270,6 +272,66 @@ def test_model_fp32_steps_match_oracle(case):
     _say(f"[gpu] model {name}: binary32 per-step parity {err:.3e}, worst excess {excess:.3e}")
     assert err <= TP.TOL["fp32"]
     assert excess <= 0.0
+
+
+def test_model_streamed_clouds_match_oracle():
+    """A cloud too large for LDS (M = 3000 at d = 4, LP1: 264 KB of binary64
+    rows per stratum, streamed through LDS in rounds) with the general model:
+    the binary64 sweep against the oracle at 1e-9 over every step."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = CASES[3]
+    cfg = _cfg("general d=4 M=3000 streamed", d, [2, 2, 1, 1], 3, 3000, basis, "fp64", clamp_z)
+    orc, sing = O.solve(_oracle_problem(cfg, csrc, params, lip))
+    P, G, Opt = _product(cfg, hip, params)
+    _say("[gpu] model general d=4, M = 3000: binary64 sweep, streamed clouds")
+    table, stats = S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    assert stats["singular_cubes"] == sing
+    err = TP.parity(table.cpu().numpy(), orc, range(3))
+    _say(f"[gpu] model streamed clouds: parity {err:.3e}")
+    assert err <= TP.TOL["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_model_global_rows_bit_identical_to_lds(prec):
+    """SRMDP_F_GLOBAL_ROWS (the clouds streamed through LDS, S' and y_{i+1} per
+    sample in global memory) gives the table of the clouds held in LDS, bit for
+    bit, for the general model."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    name, d, cells, N, M, basis, hip, csrc, params, lip, clamp_z = CASES[3]
+    cfg = _cfg(name, d, cells, N, M, basis, prec, clamp_z)
+    P, G, Opt = _product(cfg, hip, params)
+    _say(f"[gpu] model {name} {prec}: clouds in LDS and streamed")
+    t_lds, _ = S.solve(P, G, Opt)
+    P, G, Opt = _product(cfg, hip, params, flags=S.F_GLOBAL_ROWS)
+    t_gr, _ = S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    assert torch.equal(t_lds, t_gr)
+
+
+@pytest.mark.parametrize("d,cells,grid_kind", [(3, [3, 2, 3], 1), (7, [2] * 3 + [1] * 4, 0),
+                                               (7, [2] * 3 + [1] * 4, 1)],
+                         ids=["d=3 equal probability", "d=7 equal size", "d=7 equal probability"])
+def test_model_grids_and_d7_match_oracle(d, cells, grid_kind):
+    """The general model on equal-probability cells (the outer ones unbounded)
+    and at d = 7, which has no LDS kernel in the library and runs the model's
+    streamed-cloud kernel: binary64 sweeps against the oracle at 1e-9."""
+    import paper_2407_21085_amd as S
+    torch = TP._torch()
+    cfg = _cfg(f"general d={d} grid {grid_kind}", d, cells, 3, 40, "LP1", "fp64", None)
+    if grid_kind == 1:
+        cfg.update(lo=None, hi=None, grid_kind=O.GRID_EQUAL_PROB, mu=1.0)
+    orc, sing = O.solve(_oracle_problem(cfg, GENERAL_C, GENERAL_PARAMS, GENERAL_LIP))
+    P, G, Opt = _product(cfg, GENERAL_HIP, GENERAL_PARAMS)
+    _say(f"[gpu] model general d={d} grid {grid_kind}: binary64 sweep")
+    table, stats = S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    assert stats["singular_cubes"] == sing
+    err = TP.parity(table.cpu().numpy(), orc, range(3))
+    _say(f"[gpu] model general d={d} grid {grid_kind}: parity {err:.3e}")
+    assert err <= TP.TOL["fp64"]
 
 
 def test_model_parameters_change_without_recompiling_and_graphs_replay():
