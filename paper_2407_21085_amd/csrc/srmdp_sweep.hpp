@@ -780,6 +780,75 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
         }
         return acc;
     };
+    // Work items of the Gram and z right-hand-side sums: up to three entries
+    // that share a column value v_m = row[x] row[y] and take their other
+    // factor from row[a_k]; each entry sums row[a_k] v_m in binary64 over the
+    // samples, in sample order.
+    //   Gram entry (r, c), r <= c: v = row[c] row[0], which is row[c] exactly
+    //   (phi_0 = 1), a = r; items run down a column c, rows 3j..3j+2 <= c.
+    //   z right-hand side (l, b): v = S' dW_l, a = b; items take b = 3j..3j+2.
+    // One item per lane (entry triples share the loads and the product of v);
+    // the sums are those of one entry per lane, operation for operation, so
+    // both forms give the same bits.  The items take more registers: the
+    // streamed-cloud kernels of LP1 at d >= 12 (whole wavefronts per SIMD
+    // unchanged, two to seven rounds of entries per chunk set before, one to
+    // three after) use them, the others sum one entry per lane.
+    constexpr bool kItems = GR && NB >= 13;
+    constexpr int NTR3 = (NB + 2) / 3;  // right-hand-side items per component
+    constexpr int NTG = [] {
+        int n = 0;
+        for (int c = 0; c < NB; ++c) n += (c + 3) / 3;
+        return n;
+    }();
+    constexpr int NT = NTG + D * NTR3;
+    struct SumItem {
+        int x, y, a[3], e[3], n;
+    };
+    auto sum_item = [&](int w) {
+        SumItem it;
+        if (w < NTG) {
+            int c = 0, j = w;
+            while (j >= (c + 3) / 3) {
+                j -= (c + 3) / 3;
+                ++c;
+            }
+            it.x = c;
+            it.y = 0;
+            it.n = min(3, c + 1 - 3 * j);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int r = 3 * j + (k < it.n ? k : 0);
+                it.a[k] = r;
+                it.e[k] = r * NB - r * (r - 1) / 2 + (c - r);  // packed upper triangle
+            }
+        } else {
+            const int l = (w - NTG) / NTR3, j = (w - NTG) % NTR3;
+            it.x = NB + D;
+            it.y = NB + l;
+            it.n = min(3, NB - 3 * j);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int b = 3 * j + (k < it.n ? k : 0);
+                it.a[k] = b;
+                it.e[k] = NG + l * NB + b;
+            }
+        }
+        return it;
+    };
+    auto item_sums = [&](const R *rb, const SumItem &it, int m0, int m1, double *acc) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll kSumUnroll
+        for (int m = m0; m < m1; ++m) {
+            const R *row = rb + (size_t)m * SW;
+            const double v = (double)row[it.x] * (double)row[it.y];
+            s0 += (double)row[it.a[0]] * v;
+            s1 += (double)row[it.a[1]] * v;
+            s2 += (double)row[it.a[2]] * v;
+        }
+        acc[0] = s0;
+        acc[1] = s1;
+        acc[2] = s2;
+    };
     // Where entry e is kept: the upper triangle of G, or the z right-hand side.
     auto entry_slot = [&](int e) -> double * {
         if (e < NG) {
@@ -839,13 +908,27 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
             const int rc = (rn + kChunk - 1) / kChunk;
             for (int c0 = 0; c0 < rc; c0 += pb) {
                 const int nbc = min(pb, rc - c0);
-                // consecutive lanes take different entries of one chunk: rows
-                // kChunk apart would fall in the same LDS bank
-                if (live)
-                    for (int w = t; w < NE * nbc; w += L) {
-                        const int e = w % NE, c = w / NE;
-                        part[e * nbc + c] = gram_sum(rows, e, (c0 + c) * kChunk, min(rn, (c0 + c + 1) * kChunk));
+                // consecutive lanes take different entries (items) of one
+                // chunk: rows kChunk apart would fall in the same LDS bank
+                if (live) {
+                    if constexpr (kItems) {
+                        for (int w = t; w < NT * nbc; w += L) {
+                            const int c = w / NT;
+                            const SumItem it = sum_item(w % NT);
+                            double acc[3];
+                            item_sums(rows, it, (c0 + c) * kChunk, min(rn, (c0 + c + 1) * kChunk), acc);
+#pragma unroll
+                            for (int k = 0; k < 3; ++k)
+                                if (k < it.n) part[it.e[k] * nbc + c] = acc[k];
+                        }
+                    } else {
+                        for (int w = t; w < NE * nbc; w += L) {
+                            const int e = w % NE, c = w / NE;
+                            part[e * nbc + c] =
+                                gram_sum(rows, e, (c0 + c) * kChunk, min(rn, (c0 + c + 1) * kChunk));
+                        }
                     }
+                }
                 __syncthreads();
                 if (live)
                     for (int e = t; e < NE; e += L) {
