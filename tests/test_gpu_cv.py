@@ -395,6 +395,29 @@ def test_frozen_network_with_zero_output_equals_plain_sweep():
     assert torch.equal(plain, with_net)
 
 
+def test_frozen_zero_network_at_headline_size_matches_plain_sweep():
+    """At the headline size (K = 4^8, M = 64, N = 50, binary32) the sweep with a
+    zero-output network subtracts nothing and gives the plain sweep's rows bit
+    for bit where the plain sweep runs the plain path loop or the loop with one
+    gather in flight (steps 49..14, paths of up to 36 steps; the control-variate
+    kernel keeps the plain loop).  From 176 MiB of look-up rows (steps 13..0)
+    the plain sweep keeps two gathers in flight, the same arithmetic compiled
+    otherwise: there every record agrees to 1e-4 of its largest coefficient."""
+    import paper_2407_21085_amd as S
+    torch = _torch()
+    cfg = W.config("cfg5")
+    P, G, Opt = product_args(cfg)
+    _say("[gpu] headline size: plain sweep and the sweep with a zero-output network")
+    plain, _ = S.solve(P, G, Opt)
+    Opt.cv, Opt.cv_params = S.CV_FROZEN, S.mlp_init(cfg["d"] + 1, cfg["d"], 5, zero_output_layer=True)
+    with_net, _ = S.solve(P, G, Opt)
+    torch.cuda.synchronize()
+    assert torch.equal(plain[14:], with_net[14:])
+    a, b = plain[:14].double(), with_net[:14].double()
+    scale = a.abs().amax(dim=(2, 3), keepdim=True)
+    assert float(((a - b).abs() / scale).max()) <= 1e-4
+
+
 def _logistic_exact(t, x):
     s = np.sum(x, axis=-1) + t
     u = 1.0 / (1.0 + np.exp(-s))
