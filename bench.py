@@ -48,7 +48,10 @@ import workloads as W  # noqa: E402
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 FP32_PEAK_FLOPS = 157.3e12
 
-PHILOX_OPS = 10 * 8 + 9 * 2      # per block: 2 mul-hi, 2 mul-lo, 4 xor per round; key bumps
+# per block and lane: 10 rounds of 2 widening 32 x 32 -> 64-bit products and 2
+# three-input XORs (4 two-input XOR operations); the key schedule is the same for
+# every lane (scalar work) and is not counted
+PHILOX_OPS = 10 * (2 + 4)
 UNIFORM_OPS = 4                  # shift, or, convert, scale
 BOX_MULLER_OPS = 8               # log, sqrt, sincos (2), 4 multiplies per pair
 LOCATE_OPS = 8                   # sub, mul, floor, max, min, convert, index fma, xi fma
