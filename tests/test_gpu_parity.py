@@ -494,6 +494,21 @@ def test_cfg5_full_size_long_paths_parity():
     assert share < 0.2
 
 
+def test_look_up_mode_y_long_paths_parity():
+    """The headline grid (d = 8, K = 4^8, M = 64) with the linear driver and
+    the cos terminal (look-up mode Y: 48-byte records, 3 MiB rows) and N = 64:
+    steps 63, 10 and 0 of the library's binary32 sweep (paths of 1, 53 and 64
+    steps, gathering from 0, 159 and 189 MiB of rows: the plain path loop and
+    the loops with one and two gathers in flight) against the oracle's step
+    run from the library's own rows above it."""
+    cfg = dict(W.config("cfg5"), name="cos linear d=8 K=4^8 M=64 N=64 LP1 fp32", driver="linear", r=0.1,
+               kappa=0.0, terminal="cos", N=64)
+    err, excess, share = fp32_own_rows_parity(cfg, [63, 10, 0])
+    assert err <= TOL["fp32"]
+    assert excess <= 0.0
+    assert share < 0.2
+
+
 def test_cfg5_full_sweep_properties():
     """Whole sweep at the headline size: finite coefficients, no singular
     strata, and the ROOT read-out within the scheme's error of the continuous
