@@ -509,13 +509,17 @@ def test_look_up_mode_y_long_paths_parity():
     assert share < 0.2
 
 
-def test_two_gathers_in_flight_on_the_shortest_paths():
-    """The loop with two gathers in flight where the paths are shortest: d = 8,
-    6^8 = 1679616 strata (128 MiB look-up rows), M = 16, N = 4.  Step 1 gathers
-    from two rows and step 0 from three, so both take that loop with one and
-    two driver terms; step 2 (one row) takes the plain loop.  Each step against
-    the oracle's step from the oracle's rows above it."""
-    cfg = dict(W.config("cfg5"), name="logistic d=8 K=6^8 M=16 N=4 LP1 fp32", cells=[6] * 8, M=16, N=4)
+@pytest.mark.parametrize("cells", [[6] * 8, [6] * 7 + [4]], ids=["K=6^8", "K=6^7*4"])
+def test_gather_pipelines_on_the_shortest_paths(cells):
+    """The loops with gathers in flight where the paths are shortest: d = 8,
+    M = 16, N = 4.  With 6^8 strata (128 MiB look-up rows) step 1 gathers from
+    two rows and step 0 from three, so both take the loop with two gathers in
+    flight, with one and two driver terms; with 6^7 * 4 strata (85 MiB rows)
+    step 1 takes the loop with one gather in flight with one driver term and
+    step 0 the two-gather loop.  Step 2 takes the plain loop.  Each step
+    against the oracle's step from the oracle's rows above it."""
+    K = int(np.prod(cells))
+    cfg = dict(W.config("cfg5"), name=f"logistic d=8 K={K} M=16 N=4 LP1 fp32", cells=cells, M=16, N=4)
     err, excess, share = fp32_step_parity(cfg, [2, 1, 0])
     assert err <= TOL["fp32"]
     assert excess <= 0.0
