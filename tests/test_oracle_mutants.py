@@ -135,7 +135,8 @@ MUTANTS = [
 
 @pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pin_catches_planted_mistake(name, old, new, pin):
-    src = open(O._SRC).read()
+    with open(O._SRC) as f:
+        src = f.read()
     assert src.count(old) == 1, f"mutation site not unique: {name}"
     with tempfile.TemporaryDirectory() as tmp:
         path = os.path.join(tmp, "mutant.c")
