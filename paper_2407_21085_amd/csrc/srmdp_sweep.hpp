@@ -789,11 +789,19 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     //   z right-hand side (l, b): v = S' dW_l, a = b; items take b = 3j..3j+2.
     // One item per lane (entry triples share the loads and the product of v);
     // the sums are those of one entry per lane, operation for operation, so
-    // both forms give the same bits.  The items take more registers: the
-    // streamed-cloud kernels of LP1 at d >= 12 (whole wavefronts per SIMD
-    // unchanged, two to seven rounds of entries per chunk set before, one to
-    // three after) use them, the others sum one entry per lane.
+    // both forms give the same bits.  The items take more registers, so they
+    // run only where they save rounds of the lanes: the streamed-cloud kernels
+    // of LP1 at d >= 12 (two to seven rounds of entries per chunk set before,
+    // one to three after), and the binary32 kernels with clouds in LDS when
+    // there are more entries than 64 (LP1 at d >= 6: at d = 8, 117 entries in
+    // two divergent rounds against 42 items in one) and the lanes of the launch
+    // take fewer rounds of items than of entries.  There the samples of an
+    // item unroll by four: by eight the headline kernel's plain path loop went
+    // from 94 to 111 VGPRs, one wavefront per SIMD fewer.  The others, and the
+    // control variate, sum one entry per lane.
     constexpr bool kItems = GR && NB >= 13;
+    constexpr bool kItemsLds = !GR && !CV && NE > 64 && sizeof(R) == 4;
+    constexpr int kItemUnroll = GR ? kSumUnroll : 4;
     constexpr int NTR3 = (NB + 2) / 3;  // right-hand-side items per component
     constexpr int NTG = [] {
         int n = 0;
@@ -837,7 +845,7 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
     };
     auto item_sums = [&](const R *rb, const SumItem &it, int m0, int m1, double *acc) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll kSumUnroll
+#pragma unroll kItemUnroll
         for (int m = m0; m < m1; ++m) {
             const R *row = rb + (size_t)m * SW;
             const double v = (double)row[it.x] * (double)row[it.y];
@@ -971,15 +979,42 @@ __device__ __forceinline__ void sweep_group(const StepArgs<R> &a, uint32_t group
 
         // 2. Gram entries and z right-hand sides over the M samples, one
         //    (entry, chunk) pair per lane, then the chunks in order.
+        // work items where they take fewer rounds of the lanes than single entries
+        const bool items = kItemsLds && (NT * nch + L - 1) / L < (NE * nch + L - 1) / L;
         if (nch == 1) {
-            if (live)
-                for (int e = t; e < NE; e += L) gram_store(e, gram_sum(rows, e, 0, M));
-        } else {
-            if (live)
-                for (int w = t; w < NE * nch; w += L) {
-                    const int e = w % NE, c = w / NE;
-                    part[e * nch + c] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
+            if (live) {
+                if (items) {
+                    for (int w = t; w < NT; w += L) {
+                        const SumItem it = sum_item(w);
+                        double acc[3];
+                        item_sums(rows, it, 0, M, acc);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            if (k < it.n) gram_store(it.e[k], acc[k]);
+                    }
+                } else {
+                    for (int e = t; e < NE; e += L) gram_store(e, gram_sum(rows, e, 0, M));
                 }
+            }
+        } else {
+            if (live) {
+                if (items) {
+                    for (int w = t; w < NT * nch; w += L) {
+                        const int c = w / NT;
+                        const SumItem it = sum_item(w % NT);
+                        double acc[3];
+                        item_sums(rows, it, c * kChunk, min(M, (c + 1) * kChunk), acc);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            if (k < it.n) part[it.e[k] * nch + c] = acc[k];
+                    }
+                } else {
+                    for (int w = t; w < NE * nch; w += L) {
+                        const int e = w % NE, c = w / NE;
+                        part[e * nch + c] = gram_sum(rows, e, c * kChunk, min(M, (c + 1) * kChunk));
+                    }
+                }
+            }
             __syncthreads();
             if (live)
                 for (int e = t; e < NE; e += L) {
