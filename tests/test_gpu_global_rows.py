@@ -39,6 +39,23 @@ def test_global_rows_bit_identical_to_lds(prec, lanes):
         np.testing.assert_array_equal(got, ref)
 
 
+@pytest.mark.parametrize("d, cells, M, N, lanes", [(6, 3, 200, 3, 0), (6, 3, 200, 3, 64), (8, 2, 64, 4, 0)])
+def test_global_rows_bit_identical_to_lds_work_items(d, cells, M, N, lanes):
+    """binary32 with more than 64 Gram and z right-hand-side entries (LP1 at
+    d = 6: 70, d = 8: 117): the LDS path sums them in work items of three
+    entries, the global-memory path one entry per lane; each entry's sum takes
+    the same operations in the same order, so the tables are bit-identical
+    (d = 6: four chunks of sums at 256 and 64 lanes; d = 8: one chunk)."""
+    import paper_2407_21085_amd as S
+    cfg = dict(W.config("cfg2", d=d, N=N, lo=[-3.0] * d, hi=[3.0] * d, cells=[cells] * d, M=M),
+               prec="fp32", lanes=lanes)
+    _say(f"[gpu] global rows against LDS work items: d={d} M={M} lanes={lanes}")
+    ref, _ = TP.gpu_table(cfg)
+    got, _ = TP.gpu_table(cfg, flags=S.F_GLOBAL_ROWS)
+    assert np.isfinite(ref).all()
+    np.testing.assert_array_equal(got, ref)
+
+
 def test_large_cloud_fp64_full_sweep_parity():
     """cfg1 (d = 1, LP1, binary64, K = 32, N = 10) at M = 12000: 480 KB of rows
     per stratum, so the clouds go to global memory by themselves; the whole
